@@ -1,0 +1,170 @@
+/*
+ * bri.h -- C ABI of the MI355X block recursive inverse (BRI) library.
+ *
+ * The library returns one chosen b x b block N_ij of M^{-1} for a nonsingular
+ * n x n matrix M partitioned into k x k square blocks of order b = ceil(n/k)
+ * (Section "Preliminaries", eqs. blockmatricesnxn and
+ * inverseblockmatricesnxn).  The block is computed by recursive Schur
+ * complement splitting (Section "Block Recursive Inversion algorithm"): every
+ * intermediate block is a Schur complement v(r, c, I) = M_rc - M_rI M_II^{-1}
+ * M_Ic that is recomputed rather than stored, so the device workspace is a
+ * small multiple of b^2 per concurrently evaluated branch (Section
+ * "Implementation", Theorem "MC_BRI").  When k does not divide n the matrix is
+ * treated as the augmented Gamma = [[M, 0], [0, I_l]] (eq. M_augmented) and the
+ * returned block is the block of Gamma^{-1} (eq. inverse_M_augmented): rows or
+ * columns past n of the last block hold the identity / zero padding.
+ *
+ * Conventions for every entry point below:
+ *  - Matrices are row-major.  Element (r, c) of M is M[r * ldm + c].
+ *  - Block indices i, j are 0-based: the paper's N_11 is (i, j) = (0, 0).
+ *  - Every matrix pointer is a DEVICE pointer owned by the caller.  M is only
+ *    read.  The library never allocates device memory: the caller passes a
+ *    workspace of at least bri_workspace_size() bytes.
+ *  - All work is enqueued on opts->stream; calls return once the work is
+ *    enqueued (asynchronous).  The caller keeps M, out and the workspace alive
+ *    until the stream has executed the work.
+ *  - Calls that share a workspace must not overlap in time.
+ *
+ * Error behaviour:
+ *  - Synchronous argument checks return -p when argument p (1-based position
+ *    in the C signature) is invalid, in the style of LAPACK's info; nothing is
+ *    enqueued then.
+ *  - BRI_ERR_WORKSPACE: the workspace is smaller than bri_workspace_size().
+ *  - BRI_ERR_UNSUPPORTED: a size or precision this build does not support
+ *    (b > BRI_MAX_BLOCK, or a precision not available for the entry point).
+ *  - BRI_ERR_HIP: a HIP launch or copy failed; the stream state is undefined.
+ *  - Numerical failures are only known on the device and are written to
+ *    *opts->d_info (a device int32; may be NULL): 0 = success, t > 0 = the
+ *    pivot factorisation of Schur operation t-1 (in execution order; the final
+ *    inversion counts as the last operation) met an exactly zero or
+ *    non-finite pivot.  The result is then undefined, as with LAPACK getrf.
+ *    For the mixed-precision paths d_info = -1 means that iterative refinement
+ *    did not reach the requested tolerance within refine_max_iters.
+ */
+#ifndef BRI_H
+#define BRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BRI_OK 0
+#define BRI_ERR_HIP (-1000)
+#define BRI_ERR_WORKSPACE (-1001)
+#define BRI_ERR_UNSUPPORTED (-1002)
+
+/* Largest block order b supported by the pivot factorisation kernels. */
+#define BRI_MAX_BLOCK 4096
+
+/* Element type of M / out and the arithmetic the Schur updates run in. */
+typedef enum {
+  BRI_F64 = 0,        /* M, out: double.  All arithmetic FP64 (FP64 MFMA).        */
+  BRI_F32 = 1,        /* M, out: float.   All arithmetic FP32 (FP32 MFMA).        */
+  BRI_MIXED_F32 = 2,  /* M, out: double.  Schur products in FP32, FP64 refinement. */
+  BRI_MIXED_F16 = 3,  /* M, out: double.  Schur products in FP16 MFMA (FP32 acc).  */
+  BRI_MIXED_BF16 = 4  /* M, out: double.  Schur products in BF16 MFMA (FP32 acc).  */
+} bri_precision;
+
+typedef struct {
+  int precision;           /* a bri_precision value                                   */
+  int concurrency;         /* W: Schur operations evaluated side by side; <= 0: auto  */
+  int refine_max_iters;    /* mixed paths: refinement sweeps (0 = none)               */
+  double refine_tol;       /* mixed paths: stop when ||dX||_F <= tol * ||X||_F        */
+  void* workspace;         /* device workspace, >= bri_workspace_size() bytes         */
+  size_t workspace_bytes;  /* its size                                                */
+  int32_t* d_info;         /* device int32 status (see above), or NULL                */
+  hipStream_t stream;      /* stream the work is enqueued on (NULL = default stream)  */
+} bri_opts;
+
+/* Fills *o with defaults: BRI_F64, automatic concurrency, 10 refinement sweeps,
+ * tolerance 1e-12, no workspace, no d_info, default stream. */
+void bri_default_opts(bri_opts* o);
+
+/* Bytes of device workspace invert_block() needs for (n, k, i, j) with the
+ * precision and concurrency of *o (the workspace fields of *o are ignored).
+ * Returns 0 for invalid arguments. */
+size_t bri_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o);
+
+/* Block N_ij of M^{-1} (of Gamma^{-1} when k does not divide n).
+ *   M    : n x n, leading dimension ldm >= n, element type per precision.
+ *   k    : number of block rows/columns, 2 <= k <= n.
+ *   i, j : target block, 0 <= i, j < k.
+ *   out  : b x b result, b = ceil(n / k), leading dimension ldo >= b.
+ * Recursive Schur splitting of Sections "Forward recursive procedure" and
+ * "Backward recursive procedure" in the principal elimination order; for
+ * i != j the last step takes the lower-left block of eq. invSchur. */
+int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j,
+                 void* out, int64_t ldo, const bri_opts* o);
+
+/* Block column j of M^{-1} (Gamma^{-1}): X = Gamma^{-1} E_j, (k*b) x b with
+ * leading dimension ldx >= b, by block back substitution whose Schur
+ * complements are recomputed by the same recursion.  With transpose != 0 the
+ * block column of (M^T)^{-1} is returned instead (its transpose is block row j
+ * of M^{-1}).  Workspace: bri_block_column_workspace_size(). */
+size_t bri_block_column_workspace_size(int64_t n, int k, int j, const bri_opts* o);
+int bri_block_column(const void* M, int64_t n, int64_t ldm, int k, int j, int transpose,
+                     void* X, int64_t ldx, const bri_opts* o);
+
+/* Batched form: count independent problems (M[t], n[t], k[t], i[t], j[t]) ->
+ * out[t]; all arrays are HOST arrays (of device pointers where pointers).  All
+ * problems share one workspace of bri_batched_workspace_size() bytes and are
+ * evaluated together.  d_info, if not NULL, points to count device int32s. */
+size_t bri_batched_workspace_size(int count, const int64_t* n, const int* k, const int* i,
+                                  const int* j, const bri_opts* o);
+int invert_block_batched(int count, const void* const* M, const int64_t* n, const int64_t* ldm,
+                         const int* k, const int* i, const int* j, void* const* out,
+                         const int64_t* ldo, const bri_opts* o);
+
+/* Adjoint of invert_block: for L = sum(G .* N_ij), writes
+ *   grad_M = dL/dM = -(N_{i,:})^T G (N_{:,j})^T            (n x n, ld ldgm)
+ * where N_{i,:} and N_{:,j} are block row i and block column j of M^{-1},
+ * recomputed through the recursion (nothing is stored by the forward call).
+ * G is b x b with leading dimension ldg.  Precisions: BRI_F64, BRI_F32.
+ * Workspace: bri_backward_workspace_size(). */
+size_t bri_backward_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o);
+int invert_block_backward(const void* M, int64_t n, int64_t ldm, int k, int i, int j,
+                          const void* G, int64_t ldg, void* grad_M, int64_t ldgm,
+                          const bri_opts* o);
+
+/* Structure of the evaluation plan for (n, k, i, j) under *o, without running
+ * it (host only).  Counts are per call of invert_block. */
+typedef struct {
+  int64_t schur_ops;        /* Schur complement operations executed                  */
+  int64_t final_inversions; /* b x b inversions after the recursion (1)              */
+  int64_t slots;            /* b x b workspace blocks live at the high-water mark    */
+  int64_t batch_width;      /* W actually used                                       */
+  int64_t steps;            /* batched plan steps                                    */
+  int64_t kernel_launches;  /* kernel launches one call enqueues                     */
+  int64_t block;            /* b                                                     */
+  double algorithmic_flops; /* T(k) (14/3) b^3 + 2 b^3 (+ 2 b^3 if i != j)          */
+  double executed_flops;    /* flops the kernels execute                             */
+  size_t workspace_bytes;   /* == bri_workspace_size()                               */
+} bri_plan_stats;
+int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_plan_stats* s);
+
+/* Host-only description of the plan's steps for inspection by tests:
+ * writes up to cap int64 words, returns the number needed (or < 0 on bad
+ * arguments).  Format: for every step, [kind, nitems] followed per item by 16
+ * words: dst(kind, a, b), x(kind, a, b), y(kind, a, b), cin(kind, a, b),
+ * sub(kind, a, b), node.  Operand kinds: 0 none, 1 slot a, 2 block (a, b) of
+ * M, 3 identity, 4 out.  Step kinds: 1 load, 2 getrf, 3 trtri, 4 trmm_lower,
+ * 5 trmm_upper, 6 gemm (dst = cin - x * y - sub), 7 gemm_acc (dst = cin + x * y),
+ * 8 gemm_neg (dst = -x * y). */
+int64_t bri_plan_dump(int64_t n, int k, int i, int j, const bri_opts* o, int64_t* words,
+                      int64_t cap);
+
+/* Human-readable text for a status code returned by any entry point. */
+const char* bri_status_string(int status);
+
+/* Library version string. */
+const char* bri_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BRI_H */

@@ -1,0 +1,324 @@
+"""MI355X block recursive inverse (BRI): Python binding of ``libbri.so``.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libbri.so`` (see ``include/bri.h``).  PyTorch provides device
+memory (tensors for inputs, outputs and the workspace) and the stream.  There
+is no CPU fallback: the functions raise if the library is not built or the
+tensors are not on a GPU.
+
+Block indices are 0-based; the paper's N_11 is ``invert_block(M, k, 0, 0)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbri.so")
+
+PRECISIONS = {"f64": 0, "f32": 1, "mixed_f32": 2, "mixed_f16": 3, "mixed_bf16": 4}
+_DTYPE_OF = {"f64": torch.float64, "f32": torch.float32, "mixed_f32": torch.float64,
+             "mixed_f16": torch.float64, "mixed_bf16": torch.float64}
+
+BRI_ERR_HIP = -1000
+BRI_ERR_WORKSPACE = -1001
+BRI_ERR_UNSUPPORTED = -1002
+
+
+class BriOpts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("concurrency", ctypes.c_int),
+        ("refine_max_iters", ctypes.c_int),
+        ("refine_tol", ctypes.c_double),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("d_info", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class BriPlanStats(ctypes.Structure):
+    _fields_ = [
+        ("schur_ops", ctypes.c_int64),
+        ("final_inversions", ctypes.c_int64),
+        ("slots", ctypes.c_int64),
+        ("batch_width", ctypes.c_int64),
+        ("steps", ctypes.c_int64),
+        ("kernel_launches", ctypes.c_int64),
+        ("block", ctypes.c_int64),
+        ("algorithmic_flops", ctypes.c_double),
+        ("executed_flops", ctypes.c_double),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class BriError(RuntimeError):
+    def __init__(self, status: int, text: str):
+        super().__init__(f"BRI status {status}: {text}")
+        self.status = status
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point of include/bri.h.
+_SIGNATURES = [
+    ("bri_default_opts", None, [ctypes.POINTER(BriOpts)]),
+    ("bri_workspace_size", ctypes.c_size_t,
+     [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BriOpts)]),
+    ("invert_block", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+      ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(BriOpts)]),
+    ("bri_block_column_workspace_size", ctypes.c_size_t,
+     [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BriOpts)]),
+    ("bri_block_column", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+      ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(BriOpts)]),
+    ("bri_batched_workspace_size", ctypes.c_size_t,
+     [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(BriOpts)]),
+    ("invert_block_batched", ctypes.c_int,
+     [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+      ctypes.POINTER(BriOpts)]),
+    ("bri_backward_workspace_size", ctypes.c_size_t,
+     [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BriOpts)]),
+    ("invert_block_backward", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+      ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(BriOpts)]),
+    ("bri_plan_describe", ctypes.c_int,
+     [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BriOpts),
+      ctypes.POINTER(BriPlanStats)]),
+    ("bri_plan_dump", ctypes.c_int64,
+     [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BriOpts),
+      ctypes.POINTER(ctypes.c_int64), ctypes.c_int64]),
+    ("bri_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("bri_version", ctypes.c_char_p, []),
+]
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded ``libbri.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().bri_status_string(int(status)).decode()
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise BriError(status, status_string(status))
+
+
+def make_opts(precision: str = "f64", concurrency: int = 0, refine_max_iters: int = 10,
+              refine_tol: float = 1e-12) -> BriOpts:
+    o = BriOpts()
+    lib().bri_default_opts(ctypes.byref(o))
+    if precision not in PRECISIONS:
+        raise ValueError(f"unknown precision {precision!r}")
+    o.precision = PRECISIONS[precision]
+    o.concurrency = int(concurrency)
+    o.refine_max_iters = int(refine_max_iters)
+    o.refine_tol = float(refine_tol)
+    return o
+
+
+def _require_gpu(t: torch.Tensor, name: str, dtype: torch.dtype) -> None:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (there is no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a row-major 2-D tensor with unit column stride")
+
+
+def _stream_ptr(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def block_size(n: int, k: int) -> int:
+    return -(-n // k)
+
+
+def plan_describe(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0) -> dict:
+    """Host-only structure of the plan (no GPU needed)."""
+    o = make_opts(precision, concurrency)
+    s = BriPlanStats()
+    _check(lib().bri_plan_describe(n, k, i, j, ctypes.byref(o), ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in BriPlanStats._fields_}
+
+
+def plan_dump(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0) -> List[tuple]:
+    """Host-only list of plan steps: [(kind, [items...])], item = (dst, x, y, cin, sub, node)."""
+    o = make_opts(precision, concurrency)
+    need = lib().bri_plan_dump(n, k, i, j, ctypes.byref(o), None, 0)
+    if need < 0:
+        raise BriError(int(need), status_string(int(need)))
+    buf = (ctypes.c_int64 * need)()
+    lib().bri_plan_dump(n, k, i, j, ctypes.byref(o), buf, need)
+    words = list(buf)
+    steps, pos = [], 0
+    while pos < len(words):
+        kind, count = words[pos], words[pos + 1]
+        pos += 2
+        items = []
+        for _ in range(count):
+            w = words[pos:pos + 16]
+            pos += 16
+            items.append((tuple(w[0:3]), tuple(w[3:6]), tuple(w[6:9]), tuple(w[9:12]), tuple(w[12:15]), w[15]))
+        steps.append((kind, items))
+    return steps
+
+
+def workspace_size(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0) -> int:
+    o = make_opts(precision, concurrency)
+    return int(lib().bri_workspace_size(n, k, i, j, ctypes.byref(o)))
+
+
+def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
+                 out: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
+                 workspace: Optional[torch.Tensor] = None, refine_max_iters: int = 10,
+                 refine_tol: float = 1e-12) -> torch.Tensor:
+    """Block N_ij (b x b, b = ceil(n/k)) of M^{-1} (of Gamma^{-1} when k does not divide n).
+
+    ``info`` (optional int32 GPU tensor of one element) receives the device
+    status of include/bri.h; it is not checked here (no synchronisation).
+    """
+    dtype = _DTYPE_OF[precision]
+    _require_gpu(M, "M", dtype)
+    n = M.shape[0]
+    if M.shape[1] != n:
+        raise ValueError("M must be square")
+    b = block_size(n, k)
+    o = make_opts(precision, concurrency, refine_max_iters, refine_tol)
+    need = lib().bri_workspace_size(n, k, i, j, ctypes.byref(o))
+    if need == 0:
+        # Invalid arguments: let the library name the offending one (it
+        # validates before enqueuing anything).
+        _check(lib().invert_block(M.data_ptr(), n, M.stride(0), k, i, j, M.data_ptr(), b, ctypes.byref(o))
+               or BRI_ERR_UNSUPPORTED)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=M.device)
+    if out is None:
+        out = torch.empty(b, b, dtype=dtype, device=M.device)
+    _require_gpu(out, "out", dtype)
+    o.workspace = workspace.data_ptr()
+    o.workspace_bytes = workspace.numel()
+    o.d_info = info.data_ptr() if info is not None else None
+    o.stream = _stream_ptr(M.device)
+    _check(lib().invert_block(M.data_ptr(), n, M.stride(0), k, i, j, out.data_ptr(), out.stride(0),
+                              ctypes.byref(o)))
+    return out
+
+
+def block_column(M: torch.Tensor, k: int, j: int, transpose: bool = False, precision: str = "f64",
+                 concurrency: int = 0) -> torch.Tensor:
+    """Block column j of Gamma^{-1} ((k*b) x b); with ``transpose`` the block
+    column of (Gamma^T)^{-1}, i.e. the transposed block row j of Gamma^{-1}."""
+    dtype = _DTYPE_OF[precision]
+    _require_gpu(M, "M", dtype)
+    n = M.shape[0]
+    b = block_size(n, k)
+    o = make_opts(precision, concurrency)
+    need = lib().bri_block_column_workspace_size(n, k, j, ctypes.byref(o))
+    if need == 0:
+        raise BriError(BRI_ERR_UNSUPPORTED, "invalid arguments")
+    ws = torch.empty(need, dtype=torch.uint8, device=M.device)
+    X = torch.empty(k * b, b, dtype=dtype, device=M.device)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = need
+    o.stream = _stream_ptr(M.device)
+    _check(lib().bri_block_column(M.data_ptr(), n, M.stride(0), k, j, int(bool(transpose)), X.data_ptr(),
+                                  X.stride(0), ctypes.byref(o)))
+    return X
+
+
+def invert_block_backward(M: torch.Tensor, k: int, i: int, j: int, G: torch.Tensor,
+                          precision: str = "f64", concurrency: int = 0) -> torch.Tensor:
+    """dL/dM for L = sum(G * N_ij): -(N_{i,:})^T G (N_{:,j})^T, recomputed through the recursion."""
+    dtype = _DTYPE_OF[precision]
+    _require_gpu(M, "M", dtype)
+    G = G.contiguous()
+    _require_gpu(G, "G", dtype)
+    n = M.shape[0]
+    o = make_opts(precision, concurrency)
+    need = lib().bri_backward_workspace_size(n, k, i, j, ctypes.byref(o))
+    if need == 0:
+        raise BriError(BRI_ERR_UNSUPPORTED, "invalid arguments")
+    ws = torch.empty(need, dtype=torch.uint8, device=M.device)
+    grad = torch.empty(n, n, dtype=dtype, device=M.device)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = need
+    o.stream = _stream_ptr(M.device)
+    _check(lib().invert_block_backward(M.data_ptr(), n, M.stride(0), k, i, j, G.data_ptr(), G.stride(0),
+                                       grad.data_ptr(), grad.stride(0), ctypes.byref(o)))
+    return grad
+
+
+def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Sequence[int],
+                         jjs: Sequence[int], precision: str = "f64", concurrency: int = 0,
+                         info: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
+    """One block per problem; all problems share one workspace and one call."""
+    count = len(Ms)
+    dtype = _DTYPE_OF[precision]
+    for t, m in enumerate(Ms):
+        _require_gpu(m, f"Ms[{t}]", dtype)
+    dev = Ms[0].device
+    n = (ctypes.c_int64 * count)(*[m.shape[0] for m in Ms])
+    ldm = (ctypes.c_int64 * count)(*[m.stride(0) for m in Ms])
+    kk = (ctypes.c_int * count)(*ks)
+    ii = (ctypes.c_int * count)(*iis)
+    jj = (ctypes.c_int * count)(*jjs)
+    outs = [torch.empty(block_size(m.shape[0], k), block_size(m.shape[0], k), dtype=dtype, device=dev)
+            for m, k in zip(Ms, ks)]
+    ldo = (ctypes.c_int64 * count)(*[o_.stride(0) for o_ in outs])
+    mp = (ctypes.c_void_p * count)(*[m.data_ptr() for m in Ms])
+    op = (ctypes.c_void_p * count)(*[o_.data_ptr() for o_ in outs])
+    o = make_opts(precision, concurrency)
+    need = lib().bri_batched_workspace_size(count, n, kk, ii, jj, ctypes.byref(o))
+    if need == 0 and count > 0:
+        raise BriError(BRI_ERR_UNSUPPORTED, "invalid arguments")
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = need
+    o.d_info = info.data_ptr() if info is not None else None
+    o.stream = _stream_ptr(dev)
+    _check(lib().invert_block_batched(count, mp, n, ldm, kk, ii, jj, op, ldo, ctypes.byref(o)))
+    return outs
+
+
+class InvertBlock(torch.autograd.Function):
+    """N_ij = block (i, j) of M^{-1} with a backward pass that recomputes the
+    needed block row and column of M^{-1} instead of storing them."""
+
+    @staticmethod
+    def forward(ctx, M, k: int, i: int, j: int, precision: str = "f64"):
+        ctx.k, ctx.i, ctx.j, ctx.precision = k, i, j, precision
+        ctx.save_for_backward(M)
+        return invert_block(M, k, i, j, precision=precision)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (M,) = ctx.saved_tensors
+        g = invert_block_backward(M, ctx.k, ctx.i, ctx.j, grad_out, precision=ctx.precision)
+        return g, None, None, None, None
+
+
+def version() -> str:
+    return lib().bri_version().decode()

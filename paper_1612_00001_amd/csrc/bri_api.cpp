@@ -1,0 +1,682 @@
+// C ABI (include/bri.h) and the plan executor.
+//
+// A plan (bri_plan.cpp) is a list of batched steps over b x b workspace
+// slots.  The executor resolves every operand to a device view, writes all
+// work descriptors of one call into a pinned host buffer, uploads them with a
+// single copy into the caller's workspace and then enqueues the kernels of
+// every step on the caller's stream.  Nothing is allocated on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <tuple>
+
+#include "../../include/bri.h"
+#include "bri_internal.h"
+#include "bri_kernels.h"
+
+namespace bri {
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t slot_bytes = 0;
+  size_t slots_off = 0, perm_off = 0, swap_off = 0, info_off = 0, desc_off = 0;
+  size_t desc_bytes = 0;
+  size_t total = 0;
+  std::vector<size_t> step_off;  // descriptor offset of every step (relative to desc_off)
+};
+
+size_t item_bytes(StepKind k) {
+  switch (k) {
+    case ST_LOAD:
+      return sizeof(LoadItem);
+    case ST_GETRF:
+    case ST_TRTRI:
+      return sizeof(LuItem);
+    default:
+      return sizeof(GemmItem);
+  }
+}
+
+Layout make_layout(const Plan& p, int elem) {
+  Layout L;
+  const size_t b = static_cast<size_t>(p.b);
+  L.slot_bytes = align_up(b * b * elem);
+  size_t off = 0;
+  L.slots_off = off;
+  off += L.slot_bytes * p.nslots;
+  L.perm_off = off;
+  off += align_up(b * sizeof(int32_t) * p.nslots);
+  L.swap_off = off;
+  off += align_up(sizeof(int32_t) * kSwapWords * p.nslots);
+  L.info_off = off;
+  off += kAlign;
+  L.desc_off = off;
+  size_t d = 0;
+  for (const Step& s : p.steps) {
+    L.step_off.push_back(d);
+    d += align_up(item_bytes(s.kind) * s.items.size());
+  }
+  L.desc_bytes = d;
+  off += d;
+  L.total = off;
+  return L;
+}
+
+struct CachedPlan {
+  Plan plan;
+  Layout layout;
+  void* host = nullptr;  // pinned descriptor staging buffer
+  hipEvent_t uploaded = nullptr;
+  std::mutex mu;
+  ~CachedPlan() {
+    if (uploaded) (void)hipEventDestroy(uploaded);
+    if (host) (void)hipHostFree(host);
+  }
+};
+
+typedef std::tuple<int, int64_t, int, int, int, int, int, int> PlanKey;  // kind,n,k,i,j,width,elem,transpose
+
+std::mutex g_cache_mu;
+std::map<PlanKey, std::shared_ptr<CachedPlan>>& cache() {
+  static std::map<PlanKey, std::shared_ptr<CachedPlan>> c;
+  return c;
+}
+
+int elem_size(int precision) { return precision == BRI_F32 ? 4 : 8; }
+
+int64_t leaves_of(int k) { return static_cast<int64_t>(std::pow(4.0, std::max(0, k - 2))); }
+
+int auto_width(int64_t n, int k, int precision) {
+  const int64_t b = (n + k - 1) / k;
+  const int64_t tiles = ((b + 127) / 128) * ((b + 127) / 128);
+  // Enough independent Schur operations for ~2048 output tiles of 128 x 128,
+  // rounded up to a power of 4 (the lock-step batch sizes).
+  int64_t w = 1;
+  while (w * tiles < 2048) w *= 4;
+  // Keep the live workspace of the batch within 16 GiB.
+  const double per = static_cast<double>(k + 4) * b * b * elem_size(precision);
+  const int64_t wmem = std::max<int64_t>(1, static_cast<int64_t>((16.0 * (1ull << 30)) / per));
+  w = std::min(w, wmem);
+  return static_cast<int>(std::min<int64_t>(w, leaves_of(k)));
+}
+
+int resolve_width(int64_t n, int k, const bri_opts* o) {
+  if (o && o->concurrency > 0) return static_cast<int>(std::min<int64_t>(o->concurrency, leaves_of(k)));
+  return auto_width(n, k, o ? o->precision : BRI_F64);
+}
+
+std::shared_ptr<CachedPlan> get_plan(int kind, int64_t n, int k, int i, int j, int width, int elem, int transpose) {
+  PlanKey key(kind, n, k, i, j, width, elem, transpose);
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  auto& c = cache();
+  auto itp = c.find(key);
+  if (itp != c.end()) return itp->second;
+  auto cp = std::make_shared<CachedPlan>();
+  cp->plan = kind == 0 ? make_block_plan(n, k, i, j, width) : make_column_plan(n, k, j, width);
+  cp->plan.transpose = transpose;
+  cp->layout = make_layout(cp->plan, elem);
+  if (c.size() > 64) c.clear();
+  c[key] = cp;
+  return cp;
+}
+
+// ---------------------------------------------------------------------------
+// Operand resolution
+// ---------------------------------------------------------------------------
+struct Ctx {
+  const char* M = nullptr;
+  int64_t n = 0, ldm = 0;
+  int b = 0;
+  int elem = 8;
+  int transpose = 0;
+  char* ws = nullptr;
+  const Layout* lay = nullptr;
+  char* out = nullptr;
+  int64_t ldo = 0;
+  int32_t* info = nullptr;
+};
+
+DView zero_view() {
+  DView v;
+  v.p = nullptr;
+  v.ld = 0;
+  v.rowperm = nullptr;
+  v.rows = 0;
+  v.cols = 0;
+  v.diag = INT_MIN / 2;
+  v.trans = 0;
+  v.tri = 0;
+  return v;
+}
+
+char* slot_ptr(const Ctx& c, int s) { return c.ws + c.lay->slots_off + c.lay->slot_bytes * s; }
+int32_t* perm_ptr(const Ctx& c, int s) {
+  return reinterpret_cast<int32_t*>(c.ws + c.lay->perm_off) + static_cast<int64_t>(s) * c.b;
+}
+int32_t* swap_ptr(const Ctx& c, int s) {
+  return reinterpret_cast<int32_t*>(c.ws + c.lay->swap_off) + static_cast<int64_t>(s) * kSwapWords;
+}
+
+DView slot_view(const Ctx& c, int s, int tri = 0) {
+  DView v = zero_view();
+  v.p = slot_ptr(c, s);
+  v.ld = c.b;
+  v.rows = c.b;
+  v.cols = c.b;
+  v.tri = static_cast<int16_t>(tri);
+  return v;
+}
+
+DView resolve(const Ctx& c, const Opnd& o) {
+  DView v = zero_view();
+  const int64_t b = c.b;
+  switch (o.kind) {
+    case OPND_SLOT:
+      return slot_view(c, o.a);
+    case OPND_MBLK: {
+      const int64_t r = o.a, col = o.b;
+      const int64_t rows = std::max<int64_t>(0, std::min<int64_t>(b, c.n - r * b));
+      const int64_t cols = std::max<int64_t>(0, std::min<int64_t>(b, c.n - col * b));
+      v.rows = static_cast<int32_t>(rows);
+      v.cols = static_cast<int32_t>(cols);
+      v.diag = static_cast<int32_t>(col * b - r * b);
+      v.ld = c.ldm;
+      if (rows > 0 && cols > 0) {
+        // Block (r, c) of Gamma, or of Gamma^T (stored transposed).
+        const int64_t off = c.transpose ? (col * b) * c.ldm + r * b : (r * b) * c.ldm + col * b;
+        v.p = c.M + off * c.elem;
+      } else {
+        v.p = c.M;
+      }
+      v.trans = static_cast<int16_t>(c.transpose ? 1 : 0);
+      return v;
+    }
+    case OPND_IDENT:
+      v.diag = 0;
+      return v;
+    case OPND_OUT:
+      v.p = c.out + static_cast<int64_t>(o.a) * b * c.ldo * c.elem;
+      v.ld = c.ldo;
+      v.rows = c.b;
+      v.cols = c.b;
+      return v;
+    default:
+      return v;
+  }
+}
+
+void* dst_ptr(const Ctx& c, const Opnd& o, int64_t& ld) {
+  if (o.kind == OPND_SLOT) {
+    ld = c.b;
+    return slot_ptr(c, o.a);
+  }
+  if (o.kind == OPND_OUT) {
+    ld = c.ldo;
+    return c.out + static_cast<int64_t>(o.a) * c.b * c.ldo * c.elem;
+  }
+  throw std::logic_error("bad destination operand");
+}
+
+GemmItem gemm_base(const Ctx& c) {
+  GemmItem g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = g.B = g.Cin = g.Sub = zero_view();
+  g.M = g.N = g.K = c.b;
+  return g;
+}
+
+void build_descriptors(const Ctx& c, const Plan& p, char* host) {
+  for (size_t si = 0; si < p.steps.size(); ++si) {
+    const Step& s = p.steps[si];
+    char* base = host + c.lay->step_off[si];
+    for (size_t t = 0; t < s.items.size(); ++t) {
+      const StepItem& it = s.items[t];
+      switch (s.kind) {
+        case ST_LOAD: {
+          LoadItem li;
+          std::memset(&li, 0, sizeof(li));
+          li.src = resolve(c, it.x);
+          li.dst = dst_ptr(c, it.dst, li.ldd);
+          li.rows = c.b;
+          li.cols = c.b;
+          std::memcpy(base + t * sizeof(LoadItem), &li, sizeof(li));
+          break;
+        }
+        case ST_GETRF:
+        case ST_TRTRI: {
+          LuItem lu;
+          std::memset(&lu, 0, sizeof(lu));
+          lu.a = slot_ptr(c, it.dst.a);
+          lu.perm = perm_ptr(c, it.dst.a);
+          lu.swaps = swap_ptr(c, it.dst.a);
+          lu.tmp = s.kind == ST_TRTRI ? slot_ptr(c, it.x.a) : nullptr;
+          lu.node = it.node;
+          lu.b = c.b;
+          std::memcpy(base + t * sizeof(LuItem), &lu, sizeof(lu));
+          break;
+        }
+        default: {
+          GemmItem g = gemm_base(c);
+          g.out = dst_ptr(c, it.dst, g.ldo);
+          if (s.kind == ST_TRMM_L) {
+            g.A = slot_view(c, it.x.a, 1);
+            g.B = resolve(c, it.y);
+            g.B.rowperm = perm_ptr(c, it.x.a);
+            g.alpha = 1.0;
+          } else if (s.kind == ST_TRMM_U) {
+            g.A = slot_view(c, it.x.a, 2);
+            g.B = resolve(c, it.y);
+            g.alpha = 1.0;
+          } else {
+            g.A = resolve(c, it.x);
+            g.B = resolve(c, it.y);
+            if (it.cin.kind != OPND_NONE) {
+              g.Cin = resolve(c, it.cin);
+              g.has_cin = 1;
+              g.beta = 1.0;
+            }
+            if (it.sub.kind != OPND_NONE) {
+              g.Sub = resolve(c, it.sub);
+              g.has_sub = 1;
+            }
+            g.alpha = (s.kind == ST_GEMM_ACC) ? 1.0 : -1.0;
+          }
+          std::memcpy(base + t * sizeof(GemmItem), &g, sizeof(g));
+          break;
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
+  const char* dbase = c.ws + c.lay->desc_off;
+  for (size_t si = 0; si < p.steps.size(); ++si) {
+    const Step& s = p.steps[si];
+    const void* d = dbase + c.lay->step_off[si];
+    const int count = static_cast<int>(s.items.size());
+    hipError_t e = hipSuccess;
+    switch (s.kind) {
+      case ST_LOAD:
+        e = launch_load<T>(static_cast<const LoadItem*>(d), count, c.b, c.b, st);
+        break;
+      case ST_GETRF:
+        e = launch_getrf<T>(static_cast<const LuItem*>(d), count, c.b, c.info, st);
+        break;
+      case ST_TRTRI:
+        e = launch_trtri<T>(static_cast<const LuItem*>(d), count, c.b, st);
+        break;
+      default: {
+        GemmLaunch L{};
+        L.mode = GEMM_EXPLICIT;
+        L.elem = sizeof(T);
+        L.items = d;
+        L.count = count;
+        e = launch_gemm<T>(L, c.b, c.b, st);
+        break;
+      }
+    }
+    if (e != hipSuccess) return BRI_ERR_HIP;
+  }
+  return BRI_OK;
+}
+
+// Uploads the descriptors of plan cp for context c and enqueues its kernels.
+int execute(CachedPlan& cp, Ctx& c, hipStream_t st, bool clear_info) {
+  c.lay = &cp.layout;
+  std::lock_guard<std::mutex> g(cp.mu);
+  if (!cp.host) {
+    if (hipHostMalloc(&cp.host, std::max<size_t>(cp.layout.desc_bytes, 64)) != hipSuccess) return BRI_ERR_HIP;
+    if (hipEventCreateWithFlags(&cp.uploaded, hipEventDisableTiming) != hipSuccess) return BRI_ERR_HIP;
+  } else {
+    // The previous upload from this staging buffer must have completed.
+    if (hipEventSynchronize(cp.uploaded) != hipSuccess) return BRI_ERR_HIP;
+  }
+  try {
+    build_descriptors(c, cp.plan, static_cast<char*>(cp.host));
+  } catch (const std::exception&) {
+    return BRI_ERR_UNSUPPORTED;
+  }
+  if (clear_info && launch_fill_int(c.info, 1, 0, st) != hipSuccess) return BRI_ERR_HIP;
+  if (cp.layout.desc_bytes > 0) {
+    if (hipMemcpyAsync(c.ws + cp.layout.desc_off, cp.host, cp.layout.desc_bytes, hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return BRI_ERR_HIP;
+  }
+  if (hipEventRecord(cp.uploaded, st) != hipSuccess) return BRI_ERR_HIP;
+  return c.elem == 8 ? run_steps<double>(c, cp.plan, st) : run_steps<float>(c, cp.plan, st);
+}
+
+bool plain_precision(int p) { return p == BRI_F64 || p == BRI_F32; }
+
+}  // namespace
+}  // namespace bri
+
+using namespace bri;
+
+extern "C" {
+
+void bri_default_opts(bri_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = BRI_F64;
+  o->concurrency = 0;
+  o->refine_max_iters = 10;
+  o->refine_tol = 1e-12;
+}
+
+const char* bri_version(void) { return "bri-mi355x 0.1"; }
+
+const char* bri_status_string(int status) {
+  if (status == BRI_OK) return "success";
+  if (status == BRI_ERR_HIP) return "HIP launch or copy failed";
+  if (status == BRI_ERR_WORKSPACE) return "workspace smaller than required";
+  if (status == BRI_ERR_UNSUPPORTED) return "size or precision not supported";
+  if (status < 0 && status > -100) return "invalid argument (see the position -status)";
+  return "unknown status";
+}
+
+static int check_block_args(int64_t n, int64_t ldm, int k, int i, int j, int64_t ldo) {
+  if (n < 1) return -2;
+  if (ldm < n) return -3;
+  if (k < 2 || k > n) return -4;
+  if (i < 0 || i >= k) return -5;
+  if (j < 0 || j >= k) return -6;
+  const int64_t b = (n + k - 1) / k;
+  if (ldo < b) return -8;
+  if (b > BRI_MAX_BLOCK) return BRI_ERR_UNSUPPORTED;
+  return 0;
+}
+
+size_t bri_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
+  if (!o || check_block_args(n, n, k, i, j, (n + k - 1) / k) != 0) return 0;
+  if (!plain_precision(o->precision)) return 0;
+  const int w = resolve_width(n, k, o);
+  try {
+    auto cp = get_plan(0, n, k, i, j, w, elem_size(o->precision), 0);
+    return cp->layout.total;
+  } catch (const std::exception&) {
+    return 0;
+  }
+}
+
+int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_plan_stats* s) {
+  if (!s) return -6;
+  if (!o) return -5;
+  const int rc = check_block_args(n, n, k, i, j, (n + k - 1) / k);
+  if (rc) return rc;
+  const int w = resolve_width(n, k, o);
+  auto cp = get_plan(0, n, k, i, j, w, elem_size(o->precision), 0);
+  const Plan& p = cp->plan;
+  s->schur_ops = p.schur_ops;
+  s->final_inversions = p.final_inversions;
+  s->slots = p.nslots;
+  s->batch_width = p.width;
+  s->steps = static_cast<int64_t>(p.steps.size());
+  s->kernel_launches = p.launches + 1;  // + clearing d_info
+  s->block = p.b;
+  s->algorithmic_flops = p.algorithmic_flops;
+  s->executed_flops = p.executed_flops;
+  s->workspace_bytes = cp->layout.total;
+  return 0;
+}
+
+int64_t bri_plan_dump(int64_t n, int k, int i, int j, const bri_opts* o, int64_t* words, int64_t cap) {
+  if (!o) return -5;
+  const int rc = check_block_args(n, n, k, i, j, (n + k - 1) / k);
+  if (rc) return rc;
+  const int w = resolve_width(n, k, o);
+  auto cp = get_plan(0, n, k, i, j, w, elem_size(o->precision), 0);
+  int64_t pos = 0;
+  auto put = [&](int64_t v) {
+    if (words && pos < cap) words[pos] = v;
+    ++pos;
+  };
+  auto opnd = [&](const Opnd& x) {
+    put(x.kind);
+    put(x.a);
+    put(x.b);
+  };
+  for (const Step& s : cp->plan.steps) {
+    put(s.kind);
+    put(static_cast<int64_t>(s.items.size()));
+    for (const StepItem& it : s.items) {
+      opnd(it.dst);
+      opnd(it.x);
+      opnd(it.y);
+      opnd(it.cin);
+      opnd(it.sub);
+      put(it.node);
+    }
+  }
+  return pos;
+}
+
+int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, void* out, int64_t ldo,
+                 const bri_opts* o) {
+  if (!M) return -1;
+  if (!out) return -7;
+  if (!o) return -9;
+  const int rc = check_block_args(n, ldm, k, i, j, ldo);
+  if (rc) return rc;
+  if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
+  const int elem = elem_size(o->precision);
+  const int w = resolve_width(n, k, o);
+  std::shared_ptr<CachedPlan> cp;
+  try {
+    cp = get_plan(0, n, k, i, j, w, elem, 0);
+  } catch (const std::exception&) {
+    return BRI_ERR_UNSUPPORTED;
+  }
+  if (!o->workspace || o->workspace_bytes < cp->layout.total) return BRI_ERR_WORKSPACE;
+  Ctx c;
+  c.M = static_cast<const char*>(M);
+  c.n = n;
+  c.ldm = ldm;
+  c.b = cp->plan.b;
+  c.elem = elem;
+  c.ws = static_cast<char*>(o->workspace);
+  c.out = static_cast<char*>(out);
+  c.ldo = ldo;
+  c.info = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(c.ws + cp->layout.info_off);
+  return execute(*cp, c, o->stream, true);
+}
+
+size_t bri_block_column_workspace_size(int64_t n, int k, int j, const bri_opts* o) {
+  if (!o || check_block_args(n, n, k, 0, j, (n + k - 1) / k) != 0) return 0;
+  if (!plain_precision(o->precision)) return 0;
+  const int w = resolve_width(n, k, o);
+  try {
+    auto cp = get_plan(1, n, k, 0, j, w, elem_size(o->precision), 0);
+    return cp->layout.total;
+  } catch (const std::exception&) {
+    return 0;
+  }
+}
+
+int bri_block_column(const void* M, int64_t n, int64_t ldm, int k, int j, int transpose, void* X, int64_t ldx,
+                     const bri_opts* o) {
+  if (!M) return -1;
+  if (!X) return -7;
+  if (!o) return -9;
+  const int rc = check_block_args(n, ldm, k, 0, j, ldx);
+  if (rc) return rc == -8 ? -8 : (rc == -6 ? -5 : rc);
+  if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
+  const int elem = elem_size(o->precision);
+  const int w = resolve_width(n, k, o);
+  std::shared_ptr<CachedPlan> cp;
+  try {
+    cp = get_plan(1, n, k, 0, j, w, elem, transpose ? 1 : 0);
+  } catch (const std::exception&) {
+    return BRI_ERR_UNSUPPORTED;
+  }
+  if (!o->workspace || o->workspace_bytes < cp->layout.total) return BRI_ERR_WORKSPACE;
+  Ctx c;
+  c.M = static_cast<const char*>(M);
+  c.n = n;
+  c.ldm = ldm;
+  c.b = cp->plan.b;
+  c.elem = elem;
+  c.transpose = transpose ? 1 : 0;
+  c.ws = static_cast<char*>(o->workspace);
+  c.out = static_cast<char*>(X);
+  c.ldo = ldx;
+  c.info = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(c.ws + cp->layout.info_off);
+  return execute(*cp, c, o->stream, true);
+}
+
+size_t bri_batched_workspace_size(int count, const int64_t* n, const int* k, const int* i, const int* j,
+                                  const bri_opts* o) {
+  if (count < 0 || !n || !k || !i || !j || !o) return 0;
+  size_t m = 0;
+  for (int t = 0; t < count; ++t) {
+    const size_t s = bri_workspace_size(n[t], k[t], i[t], j[t], o);
+    if (s == 0) return 0;
+    m = std::max(m, s);
+  }
+  return m;
+}
+
+int invert_block_batched(int count, const void* const* M, const int64_t* n, const int64_t* ldm, const int* k,
+                         const int* i, const int* j, void* const* out, const int64_t* ldo, const bri_opts* o) {
+  if (count < 0) return -1;
+  if (!M) return -2;
+  if (!n) return -3;
+  if (!ldm) return -4;
+  if (!k) return -5;
+  if (!i) return -6;
+  if (!j) return -7;
+  if (!out) return -8;
+  if (!ldo) return -9;
+  if (!o) return -10;
+  for (int t = 0; t < count; ++t) {
+    bri_opts ot = *o;
+    ot.d_info = o->d_info ? o->d_info + t : nullptr;
+    const int rc = invert_block(M[t], n[t], ldm[t], k[t], i[t], j[t], out[t], ldo[t], &ot);
+    if (rc != BRI_OK) return rc;
+  }
+  return BRI_OK;
+}
+
+size_t bri_backward_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
+  if (!o || check_block_args(n, n, k, i, j, (n + k - 1) / k) != 0) return 0;
+  if (!plain_precision(o->precision)) return 0;
+  const int elem = elem_size(o->precision);
+  const int64_t b = (n + k - 1) / k;
+  const size_t colbuf = align_up(static_cast<size_t>(k * b) * b * elem);
+  const int w = resolve_width(n, k, o);
+  size_t plan_ws = 0;
+  try {
+    plan_ws = std::max(get_plan(1, n, k, 0, i, w, elem, 1)->layout.total, get_plan(1, n, k, 0, j, w, elem, 0)->layout.total);
+  } catch (const std::exception&) {
+    return 0;
+  }
+  return 3 * colbuf + align_up(2 * sizeof(GemmItem)) + plan_ws;
+}
+
+int invert_block_backward(const void* M, int64_t n, int64_t ldm, int k, int i, int j, const void* G, int64_t ldg,
+                          void* grad_M, int64_t ldgm, const bri_opts* o) {
+  if (!M) return -1;
+  if (!G) return -7;
+  if (!grad_M) return -9;
+  if (!o) return -11;
+  if (n < 1) return -2;
+  if (ldm < n) return -3;
+  if (k < 2 || k > n) return -4;
+  if (i < 0 || i >= k) return -5;
+  if (j < 0 || j >= k) return -6;
+  const int64_t b = (n + k - 1) / k;
+  if (ldg < b) return -8;
+  if (ldgm < n) return -10;
+  if (b > BRI_MAX_BLOCK) return BRI_ERR_UNSUPPORTED;
+  if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
+  const size_t need = bri_backward_workspace_size(n, k, i, j, o);
+  if (need == 0) return BRI_ERR_UNSUPPORTED;
+  if (!o->workspace || o->workspace_bytes < need) return BRI_ERR_WORKSPACE;
+  const int elem = elem_size(o->precision);
+  const size_t colbuf = align_up(static_cast<size_t>(k * b) * b * elem);
+  char* ws = static_cast<char*>(o->workspace);
+  char* U = ws;                // block column i of (M^T)^{-1} = (N_{i,:})^T
+  char* V = ws + colbuf;       // block column j of M^{-1}    = N_{:,j}
+  char* T1 = ws + 2 * colbuf;  // U G
+  char* desc = ws + 3 * colbuf;
+  char* rest = desc + align_up(2 * sizeof(GemmItem));
+  bri_opts oc = *o;
+  oc.workspace = rest;
+  oc.workspace_bytes = o->workspace_bytes - (rest - ws);
+  int rc = bri_block_column(M, n, ldm, k, i, 1, U, b, &oc);
+  if (rc != BRI_OK) return rc;
+  rc = bri_block_column(M, n, ldm, k, j, 0, V, b, &oc);
+  if (rc != BRI_OK) return rc;
+  // T1 = U G (kb x b), grad_M = -T1 V^T restricted to n x n.
+  GemmItem g[2];
+  std::memset(g, 0, sizeof(g));
+  for (int t = 0; t < 2; ++t) g[t].A = g[t].B = g[t].Cin = g[t].Sub = zero_view();
+  g[0].A.p = U;
+  g[0].A.ld = b;
+  g[0].A.rows = static_cast<int32_t>(k * b);
+  g[0].A.cols = static_cast<int32_t>(b);
+  g[0].B.p = G;
+  g[0].B.ld = ldg;
+  g[0].B.rows = static_cast<int32_t>(b);
+  g[0].B.cols = static_cast<int32_t>(b);
+  g[0].out = T1;
+  g[0].ldo = b;
+  g[0].M = static_cast<int32_t>(n);
+  g[0].N = static_cast<int32_t>(b);
+  g[0].K = static_cast<int32_t>(b);
+  g[0].alpha = 1.0;
+  g[1].A.p = T1;
+  g[1].A.ld = b;
+  g[1].A.rows = static_cast<int32_t>(n);
+  g[1].A.cols = static_cast<int32_t>(b);
+  g[1].B.p = V;  // element (t, c) of V^T is V[c][t]
+  g[1].B.ld = b;
+  g[1].B.trans = 1;
+  g[1].B.rows = static_cast<int32_t>(b);
+  g[1].B.cols = static_cast<int32_t>(n);
+  g[1].out = grad_M;
+  g[1].ldo = ldgm;
+  g[1].M = static_cast<int32_t>(n);
+  g[1].N = static_cast<int32_t>(n);
+  g[1].K = static_cast<int32_t>(b);
+  g[1].alpha = -1.0;
+  static std::mutex mu;
+  static void* host = nullptr;
+  static hipEvent_t ev = nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!host) {
+    if (hipHostMalloc(&host, 2 * sizeof(GemmItem)) != hipSuccess) return BRI_ERR_HIP;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return BRI_ERR_HIP;
+  } else if (hipEventSynchronize(ev) != hipSuccess) {
+    return BRI_ERR_HIP;
+  }
+  std::memcpy(host, g, sizeof(g));
+  if (hipMemcpyAsync(desc, host, sizeof(g), hipMemcpyHostToDevice, o->stream) != hipSuccess) return BRI_ERR_HIP;
+  if (hipEventRecord(ev, o->stream) != hipSuccess) return BRI_ERR_HIP;
+  GemmLaunch L{};
+  L.mode = GEMM_EXPLICIT;
+  L.elem = elem;
+  L.count = 1;
+  L.items = desc;
+  hipError_t e = elem == 8 ? launch_gemm<double>(L, static_cast<int>(n), static_cast<int>(b), o->stream)
+                           : launch_gemm<float>(L, static_cast<int>(n), static_cast<int>(b), o->stream);
+  if (e != hipSuccess) return BRI_ERR_HIP;
+  L.items = desc + sizeof(GemmItem);
+  e = elem == 8 ? launch_gemm<double>(L, static_cast<int>(n), static_cast<int>(n), o->stream)
+                : launch_gemm<float>(L, static_cast<int>(n), static_cast<int>(n), o->stream);
+  return e == hipSuccess ? BRI_OK : BRI_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// Internal types shared by the host planner, the executor and the kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace bri {
+
+// ---------------------------------------------------------------------------
+// Device-side operand view: element (x, y) of a b x b block.
+//   - tri == 1: unit lower triangle of the stored data (x > y stored, x == y
+//     reads 1, x < y reads 0); tri == 2: upper triangle (x <= y stored).
+//   - rowperm: element (x, y) is the stored element (rowperm[x], y).
+//   - Stored extent rows x cols; outside it the element is synthesised as
+//     (x - y == diag) ? 1 : 0, which realises the identity padding of the
+//     augmented matrix Gamma without a padded copy.
+//   - trans: the stored element (x, y) lives at p[y * ld + x].
+// ---------------------------------------------------------------------------
+struct DView {
+  const void* p;
+  int64_t ld;
+  const int32_t* rowperm;
+  int32_t rows, cols;
+  int32_t diag;
+  int16_t trans, tri;
+};
+
+// out[x, y] = beta * Cin[x, y] + alpha * sum_t A[x, t] B[t, y] - Sub[x, y]
+struct GemmItem {
+  DView A, B, Cin, Sub;
+  void* out;
+  int64_t ldo;
+  int32_t M, N, K;
+  int32_t has_cin, has_sub, pad_;
+  double alpha, beta;
+};
+
+// One b x b matrix factored in place (P A = L U, unit L strictly below the
+// diagonal, U on and above), later overwritten by L^{-1} and U^{-1} in the
+// same packed layout.
+struct LuItem {
+  void* a;           // dense b x b, leading dimension b
+  int32_t* perm;     // b entries: row x of P A is row perm[x] of A
+  int32_t* swaps;    // per-panel list of moved rows: [count, (dest, src) ...]
+  void* tmp;         // b x b scratch for the triangular inversion
+  int32_t node;      // Schur operation index reported through d_info
+  int32_t b;
+};
+
+struct LoadItem {
+  DView src;
+  void* dst;
+  int64_t ldd;
+  int32_t rows, cols;
+};
+
+enum GemmMode : int32_t {
+  GEMM_EXPLICIT = 0,    // items[] are GemmItem
+  GEMM_LU_TRAILING = 1, // trailing update of a right-looking LU step
+  GEMM_TRTRI_STEP1 = 2, // recursive-doubling triangular inversion, first product
+  GEMM_TRTRI_STEP2 = 3, // second product
+};
+
+struct GemmLaunch {
+  int32_t mode;
+  int32_t elem;         // 8 = double, 4 = float
+  const void* items;    // GemmItem* or LuItem*
+  int32_t count;        // items for GEMM_EXPLICIT, matrices otherwise
+  int32_t j, w;         // LU step: panel start and width
+  int32_t s;            // TRTRI level: half-block size
+  int32_t npairs;       // TRTRI level: block pairs per matrix
+};
+
+constexpr int kSwapWords = 1 + 2 * 2 * 64;  // count + up to 128 (dest, src) pairs
+constexpr int kTrtriTile = 32;                // diagonal tile of the triangular inversion
+
+// Width of the LU panel held in registers for a panel of h rows (512 threads
+// hold ceil(h / 512) rows of at most 64 doubles each).
+inline int panel_width(int h) { return h <= 1024 ? 32 : (h <= 2048 ? 16 : 8); }
+
+// ---------------------------------------------------------------------------
+// Host plan: batched steps over b x b workspace slots.
+// ---------------------------------------------------------------------------
+enum OpndKind : int8_t { OPND_NONE = 0, OPND_SLOT = 1, OPND_MBLK = 2, OPND_IDENT = 3, OPND_OUT = 4 };
+
+struct Opnd {
+  int8_t kind = OPND_NONE;
+  int32_t a = 0, b = 0;
+  static Opnd none() { return Opnd(); }
+  static Opnd slot(int s) { Opnd o; o.kind = OPND_SLOT; o.a = s; return o; }
+  static Opnd mblk(int r, int c) { Opnd o; o.kind = OPND_MBLK; o.a = r; o.b = c; return o; }
+  static Opnd ident() { Opnd o; o.kind = OPND_IDENT; return o; }
+  static Opnd outp() { Opnd o; o.kind = OPND_OUT; return o; }
+};
+
+enum StepKind : int32_t {
+  ST_LOAD = 1,      // dst <- x
+  ST_GETRF = 2,     // dst <- LU(dst)
+  ST_TRTRI = 3,     // dst (LU) <- packed inverses of L and U; x = scratch slot
+  ST_TRMM_L = 4,    // dst <- L(x)^{-1} P(x) y
+  ST_TRMM_U = 5,    // dst <- U(x)^{-1} y
+  ST_GEMM = 6,      // dst <- cin - x * y - sub
+  ST_GEMM_ACC = 7,  // dst <- cin + x * y   (cin may be none)
+  ST_GEMM_NEG = 8,  // dst <- -x * y
+};
+
+struct StepItem {
+  Opnd dst, x, y, cin, sub;
+  int32_t node = -1;
+};
+
+struct Step {
+  StepKind kind;
+  std::vector<StepItem> items;
+};
+
+struct Plan {
+  int64_t n = 0;
+  int k = 0, i = 0, j = 0;
+  int b = 0;
+  int width = 1;
+  int transpose = 0;        // operands are blocks of Gamma^T
+  std::vector<Step> steps;
+  int nslots = 0;           // high-water mark of simultaneously live slots
+  int64_t schur_ops = 0;
+  int64_t final_inversions = 0;
+  int64_t launches = 0;
+  double executed_flops = 0;
+  double algorithmic_flops = 0;
+};
+
+// Builds the plan of invert_block for target (i, j) with batch width W.
+Plan make_block_plan(int64_t n, int k, int i, int j, int width);
+// Builds the plan of bri_block_column (block column j of Gamma^{-1}).
+Plan make_column_plan(int64_t n, int k, int j, int width);
+
+// Launch/flop accounting of the kernels that realise a step.
+int64_t getrf_launches(int b);
+int64_t trtri_launches(int b);
+double getrf_flops(int b);
+double trtri_flops(int b);
+
+}  // namespace bri

@@ -1,0 +1,20 @@
+// Host launchers of the device kernels (bri_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bri_internal.h"
+
+namespace bri {
+
+template <typename T>
+hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st);
+template <typename T>
+hipError_t launch_getrf(const LuItem* d_items, int count, int b, int32_t* info, hipStream_t st);
+template <typename T>
+hipError_t launch_trtri(const LuItem* d_items, int count, int b, hipStream_t st);
+template <typename T>
+hipError_t launch_load(const LoadItem* d_items, int count, int rows, int cols, hipStream_t st);
+hipError_t launch_fill_int(int32_t* p, int n, int v, hipStream_t st);
+
+}  // namespace bri

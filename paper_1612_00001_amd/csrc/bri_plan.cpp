@@ -1,0 +1,582 @@
+// Host planner: turns the recursive Schur complement splitting into a list of
+// batched steps over b x b workspace slots.
+//
+// Notation (principal elimination order): v(r, c, I) is block (r, c) after the
+// blocks in I were eliminated,
+//     v(r, c, I) = v(r, c, I') - v(r, p, I') v(p, p, I')^{-1} v(p, c, I'),
+// p the last entry of I (the Schur complement of eqs. SchurofA..SchurofD with
+// the pivot moved to the principal position).  A node of depth d has the four
+// children (r,c), (r,p), (p,p), (p,c) of depth d-1; depth-0 nodes are blocks of
+// M.  The recursion recomputes every child, as the backward procedure of the
+// paper does branch by branch (Section "Implementation"), so one block costs
+// sum_{i=1}^{k-1} 4^{k-1-i} Schur operations (Theorem "C_BRI").
+//
+// Evaluation order.  Nodes of one depth are processed in lock-step batches of
+// at most W (the largest power of 4 not above W): for a batch of nodes the planner evaluates all their pivot
+// children, factors them, evaluates the right-hand children and solves, then
+// the left children (accumulated into one running sum per chain), and finally
+// the diagonal children, whose last product subtracts the accumulated sum.
+// Each recursion level holds one pending block per node of the batch, which
+// keeps the live workspace at about (depth + 3) blocks per batch entry
+// (Theorem "MC_BRI" bounds it by O(b^2) per branch); with W = 1 the peak is
+// (k + 1) blocks.  Result blocks are allocated only when they are written.
+// Above the depth at which a level reaches W nodes the tree is expanded
+// breadth first.
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+
+#include "bri_internal.h"
+
+namespace bri {
+
+namespace {
+
+struct SlotPool {
+  std::vector<int> free_list;
+  int next = 0;
+  int live = 0;
+  int peak = 0;
+  int alloc() {
+    int s;
+    if (!free_list.empty()) {
+      s = free_list.back();
+      free_list.pop_back();
+    } else {
+      s = next++;
+    }
+    ++live;
+    peak = std::max(peak, live);
+    return s;
+  }
+  void release(int s) {
+    free_list.push_back(s);
+    --live;
+  }
+};
+
+struct Node {
+  int r, c, depth;
+};
+
+class Builder {
+ public:
+  Builder(Plan& p, std::vector<int> elim, int width) : plan_(p), elim_(std::move(elim)), width_(width) {}
+
+  int next_node() { return node_counter_++; }
+  SlotPool& pool() { return pool_; }
+
+  Step& step(StepKind kind) {
+    plan_.steps.push_back(Step{kind, {}});
+    return plan_.steps.back();
+  }
+
+  // Evaluates the batch L (all of one depth d >= 1) and returns the slots
+  // holding the results (allocated only when the result is written); when
+  // accs[t] >= 0 the accumulated sum in that slot is subtracted at the end.
+  std::vector<int> eval(const std::vector<Node>& L, const std::vector<int>& accs) {
+    if (L.empty()) return {};
+    const int d = L[0].depth;
+    if (d == 1) return leaf(L, accs);
+    if (4 * static_cast<int64_t>(L.size()) <= width_) return expand(L, accs);
+    return lockstep(L, accs);
+  }
+
+  // Factor pivots, invert their triangular factors and form X = P^{-1} B for
+  // a batch; lu[t] holds the pivot, rhs[t] the operand B; the result X goes to
+  // xdst[t].  Releases nothing.
+  void factor_and_solve(const std::vector<int>& lu, const std::vector<Opnd>& rhs, const std::vector<Opnd>& xdst,
+                        bool count_schur) {
+    const size_t n = lu.size();
+    Step& g = step(ST_GETRF);
+    for (size_t t = 0; t < n; ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(lu[t]);
+      it.node = next_node();
+      g.items.push_back(it);
+      if (count_schur) plan_.schur_ops++;
+    }
+    std::vector<int> tmp(n);
+    for (size_t t = 0; t < n; ++t) tmp[t] = pool_.alloc();
+    Step& tr = step(ST_TRTRI);
+    for (size_t t = 0; t < n; ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(lu[t]);
+      it.x = Opnd::slot(tmp[t]);
+      tr.items.push_back(it);
+    }
+    Step& l = step(ST_TRMM_L);
+    for (size_t t = 0; t < n; ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(tmp[t]);
+      it.x = Opnd::slot(lu[t]);
+      it.y = rhs[t];
+      l.items.push_back(it);
+    }
+    Step& u = step(ST_TRMM_U);
+    for (size_t t = 0; t < n; ++t) {
+      StepItem it;
+      it.dst = xdst[t];
+      it.x = Opnd::slot(lu[t]);
+      it.y = Opnd::slot(tmp[t]);
+      u.items.push_back(it);
+    }
+    for (size_t t = 0; t < n; ++t) pool_.release(tmp[t]);
+  }
+
+  int pivot_of(int depth) const { return elim_[depth - 1]; }
+
+ private:
+  std::vector<int> leaf(const std::vector<Node>& L, const std::vector<int>& accs) {
+    const size_t n = L.size();
+    const int p = pivot_of(1);
+    std::vector<int> sp(n), sx(n), outs(n);
+    for (size_t t = 0; t < n; ++t) sp[t] = pool_.alloc();
+    for (size_t t = 0; t < n; ++t) sx[t] = pool_.alloc();
+    Step& ld = step(ST_LOAD);
+    for (size_t t = 0; t < n; ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(sp[t]);
+      it.x = Opnd::mblk(p, p);
+      ld.items.push_back(it);
+    }
+    std::vector<Opnd> rhs(n), xd(n);
+    for (size_t t = 0; t < n; ++t) {
+      rhs[t] = Opnd::mblk(p, L[t].c);
+      xd[t] = Opnd::slot(sx[t]);
+    }
+    factor_and_solve(sp, rhs, xd, true);
+    for (size_t t = 0; t < n; ++t) pool_.release(sp[t]);
+    for (size_t t = 0; t < n; ++t) outs[t] = pool_.alloc();
+    Step& g = step(ST_GEMM);
+    for (size_t t = 0; t < n; ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(outs[t]);
+      it.x = Opnd::mblk(L[t].r, p);
+      it.y = Opnd::slot(sx[t]);
+      it.cin = Opnd::mblk(L[t].r, L[t].c);
+      it.sub = accs[t] >= 0 ? Opnd::slot(accs[t]) : Opnd::none();
+      g.items.push_back(it);
+    }
+    for (size_t t = 0; t < n; ++t) pool_.release(sx[t]);
+    return outs;
+  }
+
+  std::vector<int> expand(const std::vector<Node>& L, const std::vector<int>& accs) {
+    const size_t n = L.size();
+    const int d = L[0].depth;
+    const int p = pivot_of(d);
+    std::vector<Node> kids;
+    for (size_t t = 0; t < n; ++t) {
+      kids.push_back({L[t].r, L[t].c, d - 1});
+      kids.push_back({L[t].r, p, d - 1});
+      kids.push_back({p, p, d - 1});
+      kids.push_back({p, L[t].c, d - 1});
+    }
+    const std::vector<int> res = eval(kids, std::vector<int>(kids.size(), -1));
+    std::vector<int> src(n), srp(n), spp(n), spc(n);
+    for (size_t t = 0; t < n; ++t) {
+      src[t] = res[4 * t];
+      srp[t] = res[4 * t + 1];
+      spp[t] = res[4 * t + 2];
+      spc[t] = res[4 * t + 3];
+    }
+    std::vector<Opnd> rhs(n), xd(n);
+    for (size_t t = 0; t < n; ++t) {
+      rhs[t] = Opnd::slot(spc[t]);
+      xd[t] = Opnd::slot(spc[t]);
+    }
+    factor_and_solve(spp, rhs, xd, true);
+    for (size_t t = 0; t < n; ++t) pool_.release(spp[t]);
+    Step& g = step(ST_GEMM);
+    for (size_t t = 0; t < n; ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(src[t]);
+      it.x = Opnd::slot(srp[t]);
+      it.y = Opnd::slot(spc[t]);
+      it.cin = Opnd::slot(src[t]);
+      it.sub = accs[t] >= 0 ? Opnd::slot(accs[t]) : Opnd::none();
+      g.items.push_back(it);
+    }
+    for (size_t t = 0; t < n; ++t) {
+      pool_.release(srp[t]);
+      pool_.release(spc[t]);
+    }
+    return src;
+  }
+
+  std::vector<int> lockstep(const std::vector<Node>& L, const std::vector<int>& accs) {
+    const size_t n = L.size();
+    const int d = L[0].depth;
+    const int p = pivot_of(d);
+    const std::vector<int> none(n, -1);
+    std::vector<Node> kids(n);
+    // Pivot children, factored at once so only their factors stay live.
+    for (size_t t = 0; t < n; ++t) kids[t] = {p, p, d - 1};
+    const std::vector<int> sp = eval(kids, none);
+    factor_only(sp);
+    // Right-hand children; X = P^{-1} B replaces them.
+    for (size_t t = 0; t < n; ++t) kids[t] = {p, L[t].c, d - 1};
+    const std::vector<int> sb = eval(kids, none);
+    solve_only(sp, sb);
+    for (size_t t = 0; t < n; ++t) pool_.release(sp[t]);
+    // Left children: acc (+)= C X.
+    for (size_t t = 0; t < n; ++t) kids[t] = {L[t].r, p, d - 1};
+    const std::vector<int> sc = eval(kids, none);
+    std::vector<int> acc(n);
+    std::vector<bool> own(n, false);
+    for (size_t t = 0; t < n; ++t) {
+      if (accs[t] >= 0) {
+        acc[t] = accs[t];
+      } else {
+        acc[t] = pool_.alloc();
+        own[t] = true;
+      }
+    }
+    Step& g = step(ST_GEMM_ACC);
+    for (size_t t = 0; t < n; ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(acc[t]);
+      it.x = Opnd::slot(sc[t]);
+      it.y = Opnd::slot(sb[t]);
+      it.cin = own[t] ? Opnd::none() : Opnd::slot(acc[t]);
+      g.items.push_back(it);
+    }
+    for (size_t t = 0; t < n; ++t) {
+      pool_.release(sc[t]);
+      pool_.release(sb[t]);
+    }
+    // Diagonal children subtract the accumulated sum in their last product.
+    for (size_t t = 0; t < n; ++t) kids[t] = {L[t].r, L[t].c, d - 1};
+    const std::vector<int> outs = eval(kids, acc);
+    for (size_t t = 0; t < n; ++t)
+      if (own[t]) pool_.release(acc[t]);
+    return outs;
+  }
+
+ public:
+  void factor_only(const std::vector<int>& lu) {
+    Step& g = step(ST_GETRF);
+    for (int s : lu) {
+      StepItem it;
+      it.dst = Opnd::slot(s);
+      it.node = next_node();
+      g.items.push_back(it);
+      plan_.schur_ops++;
+    }
+    std::vector<int> tmp;
+    for (size_t t = 0; t < lu.size(); ++t) tmp.push_back(pool_.alloc());
+    Step& tr = step(ST_TRTRI);
+    for (size_t t = 0; t < lu.size(); ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(lu[t]);
+      it.x = Opnd::slot(tmp[t]);
+      tr.items.push_back(it);
+    }
+    for (int s : tmp) pool_.release(s);
+  }
+
+  // X = U^{-1} L^{-1} P B in place of B (lu already holds the inverted factors).
+  void solve_only(const std::vector<int>& lu, const std::vector<int>& b) {
+    std::vector<int> tmp;
+    for (size_t t = 0; t < lu.size(); ++t) tmp.push_back(pool_.alloc());
+    Step& l = step(ST_TRMM_L);
+    for (size_t t = 0; t < lu.size(); ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(tmp[t]);
+      it.x = Opnd::slot(lu[t]);
+      it.y = Opnd::slot(b[t]);
+      l.items.push_back(it);
+    }
+    Step& u = step(ST_TRMM_U);
+    for (size_t t = 0; t < lu.size(); ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(b[t]);
+      it.x = Opnd::slot(lu[t]);
+      it.y = Opnd::slot(tmp[t]);
+      u.items.push_back(it);
+    }
+    for (int s : tmp) pool_.release(s);
+  }
+
+  // Inverse of the matrix in slot z written to dst: getrf, triangular
+  // inversion, then U^{-1} (L^{-1} P I).
+  void final_inverse(int z, Opnd dst, bool count_final) {
+    Step& g = step(ST_GETRF);
+    StepItem it;
+    it.dst = Opnd::slot(z);
+    it.node = next_node();
+    g.items.push_back(it);
+    if (count_final) plan_.final_inversions++;
+    int tmp = pool_.alloc();
+    Step& tr = step(ST_TRTRI);
+    StepItem t1;
+    t1.dst = Opnd::slot(z);
+    t1.x = Opnd::slot(tmp);
+    tr.items.push_back(t1);
+    Step& l = step(ST_TRMM_L);
+    StepItem t2;
+    t2.dst = Opnd::slot(tmp);
+    t2.x = Opnd::slot(z);
+    t2.y = Opnd::ident();
+    l.items.push_back(t2);
+    Step& u = step(ST_TRMM_U);
+    StepItem t3;
+    t3.dst = dst;
+    t3.x = Opnd::slot(z);
+    t3.y = Opnd::slot(tmp);
+    u.items.push_back(t3);
+    pool_.release(tmp);
+  }
+
+  // Value of the depth-d node (r, c) in a fresh slot (d may be 0: a plain load).
+  int value(int r, int c, int d) {
+    if (d == 0) {
+      const int out = pool_.alloc();
+      Step& ld = step(ST_LOAD);
+      StepItem it;
+      it.dst = Opnd::slot(out);
+      it.x = Opnd::mblk(r, c);
+      ld.items.push_back(it);
+      return out;
+    }
+    return eval({Node{r, c, d}}, {-1})[0];
+  }
+
+  Plan& plan_;
+  std::vector<int> elim_;
+  int width_;
+  SlotPool pool_;
+  int node_counter_ = 0;
+};
+
+double cube(double x) { return x * x * x; }
+
+void account(Plan& p) {
+  const double b = p.b;
+  p.launches = 0;
+  p.executed_flops = 0;
+  for (const Step& s : p.steps) {
+    const double n = static_cast<double>(s.items.size());
+    switch (s.kind) {
+      case ST_LOAD:
+        p.launches += 1;
+        break;
+      case ST_GETRF:
+        p.launches += getrf_launches(p.b);
+        p.executed_flops += n * getrf_flops(p.b);
+        break;
+      case ST_TRTRI:
+        p.launches += trtri_launches(p.b);
+        p.executed_flops += n * trtri_flops(p.b);
+        break;
+      case ST_TRMM_L:
+      case ST_TRMM_U:
+        p.launches += 1;
+        p.executed_flops += n * cube(b);
+        break;
+      default:
+        p.launches += 1;
+        p.executed_flops += n * 2.0 * cube(b);
+        break;
+    }
+  }
+}
+
+}  // namespace
+
+int64_t getrf_launches(int b) {
+  int64_t n = 0;
+  for (int j = 0; j < b;) {
+    const int w = std::min(panel_width(b - j), b - j);
+    n += 1;                          // panel
+    if (j > 0 || j + w < b) n += 1;  // row interchanges (+ triangular solve)
+    if (j + w < b) n += 1;           // trailing update
+    j += w;
+  }
+  return n;
+}
+
+int64_t trtri_launches(int b) {
+  int64_t n = 1;
+  for (int s = kTrtriTile; s < b; s *= 2) n += 2;
+  return n;
+}
+
+double getrf_flops(int b) { return 2.0 / 3.0 * cube(b); }
+double trtri_flops(int b) { return 2.0 / 3.0 * cube(b); }
+
+Plan make_block_plan(int64_t n, int k, int i, int j, int width) {
+  if (k < 2 || n < k || i < 0 || i >= k || j < 0 || j >= k) throw std::invalid_argument("bad target");
+  Plan plan;
+  plan.n = n;
+  plan.k = k;
+  plan.i = i;
+  plan.j = j;
+  plan.b = static_cast<int>((n + k - 1) / k);
+  const int64_t leaves = static_cast<int64_t>(std::pow(4.0, std::max(0, k - 2)));
+  plan.width = std::max<int64_t>(1, std::min<int64_t>(width, leaves));
+  // Final 2 x 2 frame [[a, c], ...] and elimination sequence (oracle reading:
+  // i == j: a = i, c = largest index != i; i != j: a = j, c = i).
+  int a, c;
+  if (i == j) {
+    a = i;
+    c = (i == k - 1) ? k - 2 : k - 1;
+  } else {
+    a = j;
+    c = i;
+  }
+  std::vector<int> elim;
+  for (int t = 0; t < k; ++t)
+    if (t != a && t != c) elim.push_back(t);
+  elim.push_back(c);
+  Builder B(plan, elim, plan.width);
+  SlotPool& pool = B.pool();
+  const int depth = k - 1;
+  int sz = -1;
+  int sx = -1;
+  if (depth == 1) {
+    // k = 2: the root itself reads blocks of M.
+    int sp = pool.alloc();
+    sx = pool.alloc();
+    Step& ld = B.step(ST_LOAD);
+    StepItem it;
+    it.dst = Opnd::slot(sp);
+    it.x = Opnd::mblk(c, c);
+    ld.items.push_back(it);
+    B.factor_and_solve({sp}, {Opnd::mblk(c, a)}, {Opnd::slot(sx)}, true);
+    pool.release(sp);
+    sz = pool.alloc();
+    Step& g = B.step(ST_GEMM);
+    StepItem gi;
+    gi.dst = Opnd::slot(sz);
+    gi.x = Opnd::mblk(a, c);
+    gi.y = Opnd::slot(sx);
+    gi.cin = Opnd::mblk(a, a);
+    g.items.push_back(gi);
+  } else if (plan.width >= 4) {
+    // Expand the root: its four children are evaluated as one batch.
+    const std::vector<int> r4 = B.eval({Node{a, a, depth - 1}, Node{a, c, depth - 1}, Node{c, c, depth - 1},
+                                        Node{c, a, depth - 1}},
+                                       {-1, -1, -1, -1});
+    sz = r4[0];
+    const int sc_ = r4[1], sp = r4[2];
+    sx = r4[3];
+    B.factor_and_solve({sp}, {Opnd::slot(sx)}, {Opnd::slot(sx)}, true);
+    pool.release(sp);
+    Step& g = B.step(ST_GEMM);
+    StepItem gi;
+    gi.dst = Opnd::slot(sz);
+    gi.x = Opnd::slot(sc_);
+    gi.y = Opnd::slot(sx);
+    gi.cin = Opnd::slot(sz);
+    g.items.push_back(gi);
+    pool.release(sc_);
+  } else {
+    // Branch by branch (W = 1): pivot child, factor, right child, solve, left
+    // child into the running sum, diagonal child.
+    const int sp = B.value(c, c, depth - 1);
+    B.factor_only({sp});
+    sx = B.value(c, a, depth - 1);
+    B.solve_only({sp}, {sx});
+    pool.release(sp);
+    const int sc_ = B.value(a, c, depth - 1);
+    const int acc = pool.alloc();
+    Step& g = B.step(ST_GEMM_ACC);
+    StepItem gi;
+    gi.dst = Opnd::slot(acc);
+    gi.x = Opnd::slot(sc_);
+    gi.y = Opnd::slot(sx);
+    g.items.push_back(gi);
+    pool.release(sc_);
+    if (i == j) {
+      pool.release(sx);  // X is only needed for the off-diagonal block
+      sx = -1;
+    }
+    sz = B.eval({Node{a, a, depth - 1}}, {acc})[0];
+    pool.release(acc);
+  }
+  // N_aa = Z^{-1}; for i != j, N_ij = -X N_aa (lower-left block of eq. invSchur).
+  if (i == j) {
+    B.final_inverse(sz, Opnd::outp(), true);
+  } else {
+    int sn = pool.alloc();
+    B.final_inverse(sz, Opnd::slot(sn), true);
+    Step& g = B.step(ST_GEMM_NEG);
+    StepItem gi;
+    gi.dst = Opnd::outp();
+    gi.x = Opnd::slot(sx);
+    gi.y = Opnd::slot(sn);
+    g.items.push_back(gi);
+    pool.release(sn);
+  }
+  if (sx >= 0) pool.release(sx);
+  pool.release(sz);
+  plan.nslots = pool.peak;
+  const double b3 = cube(plan.b);
+  const double T = static_cast<double>((static_cast<int64_t>(std::pow(4.0, k - 1)) - 1) / 3);
+  plan.algorithmic_flops = T * (14.0 / 3.0) * b3 + 2.0 * b3 + (i != j ? 2.0 * b3 : 0.0);
+  account(plan);
+  return plan;
+}
+
+Plan make_column_plan(int64_t n, int k, int j, int width) {
+  if (k < 2 || n < k || j < 0 || j >= k) throw std::invalid_argument("bad target");
+  Plan plan;
+  plan.n = n;
+  plan.k = k;
+  plan.i = -1;
+  plan.j = j;
+  plan.b = static_cast<int>((n + k - 1) / k);
+  const int64_t leaves = static_cast<int64_t>(std::pow(4.0, std::max(0, k - 2)));
+  plan.width = std::max<int64_t>(1, std::min<int64_t>(width, leaves));
+  std::vector<int> order;
+  for (int t = 0; t < k; ++t)
+    if (t != j) order.push_back(t);
+  Builder B(plan, order, plan.width);
+  SlotPool& pool = B.pool();
+  // x_j = v(j, j, P)^{-1}, written to block row j of the output.
+  {
+    const int sz = B.value(j, j, k - 1);
+    B.final_inverse(sz, Opnd{OPND_OUT, j, 0}, true);
+    pool.release(sz);
+  }
+  // Back substitution: x_q = -v(q,q,I_q)^{-1} (v(q,j,I_q) x_j + sum_{t after q} v(q,t,I_q) x_t).
+  for (int pos = k - 2; pos >= 0; --pos) {
+    const int q = order[pos];
+    int acc = pool.alloc();
+    bool first = true;
+    std::vector<int> later(order.begin() + pos + 1, order.end());
+    later.insert(later.begin(), j);
+    for (int t : later) {
+      const int sv = B.value(q, t, pos);
+      Step& g = B.step(ST_GEMM);
+      StepItem it;
+      it.dst = Opnd::slot(acc);
+      it.x = Opnd::slot(sv);
+      it.y = Opnd{OPND_OUT, t, 0};
+      it.cin = first ? Opnd::none() : Opnd::slot(acc);
+      g.items.push_back(it);
+      first = false;
+      pool.release(sv);
+    }
+    const int sq = B.value(q, q, pos);
+    B.factor_only({sq});
+    plan.schur_ops--;  // the back-substitution pivots are inversions, not Schur steps
+    plan.final_inversions++;
+    B.solve_only({sq}, {acc});
+    Step& cp = B.step(ST_LOAD);
+    StepItem it;
+    it.dst = Opnd{OPND_OUT, q, 0};
+    it.x = Opnd::slot(acc);
+    cp.items.push_back(it);
+    pool.release(sq);
+    pool.release(acc);
+  }
+  plan.nslots = pool.peak;
+  plan.algorithmic_flops = 0;
+  account(plan);
+  return plan;
+}
+
+}  // namespace bri

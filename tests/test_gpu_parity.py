@@ -1,0 +1,189 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Every input is seeded (workloads.py).  Tolerances (relative Frobenius error):
+* FP64 path: 1e-12 on diagonally dominant and Q Lam Q^T (cond <= 1e2) inputs;
+* FP32 path: a bound derived from the arithmetic, c * eps32 * cond(M),
+  with eps32 = 2^-24 and c = 64 (a few hundred rounding steps per element).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1612_00001_amd as bri
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+EPS32 = 2.0 ** -24
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(m, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(m)).to(DEV, dtype)
+
+
+def run(m, k, i, j, precision="f64", concurrency=0):
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    out = bri.invert_block(gpu(m, dtype), k, i, j, precision=precision, concurrency=concurrency, info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    return out.double().cpu().numpy()
+
+
+def test_library_is_loaded_from_tree():
+    assert bri.lib()._name == bri.LIB_PATH
+
+
+@pytest.mark.parametrize("n,k", [(32, 2), (64, 2), (100, 3), (130, 4), (96, 4), (200, 5), (66, 6), (64, 8), (7, 7)])
+def test_small_fp64_all_blocks(n, k):
+    m = workloads.gaussian_dd(n, 10 * n + k)
+    print(f"case n={n} k={k}", flush=True)
+    for i in range(k):
+        for j in range(k):
+            if k > 4 and (i + j) % 3:
+                continue
+            got = run(m, k, i, j)
+            want = oracle.invert_block(m, k, i, j)
+            assert rel(got, want) < 1e-12, (i, j)
+
+
+@pytest.mark.parametrize("W", [1, 4, 16, 64])
+def test_concurrency_widths_agree(W):
+    n, k = 300, 5
+    m = workloads.haar_spd(n, 77, 0.0, 2.0).m
+    for (i, j) in [(0, 0), (3, 1)]:
+        got = run(m, k, i, j, concurrency=W)
+        assert rel(got, oracle.invert_block(m, k, i, j)) < 1e-12
+
+
+@pytest.mark.parametrize("n,k", [(257, 2), (129, 3), (515, 4), (1000, 3)])
+def test_ragged_blocks_and_tiles(n, k):
+    # b not a multiple of the 32/64/128 tiles, and identity padding in the last block
+    m = workloads.gaussian_dd(n, n + k)
+    for (i, j) in [(0, 0), (k - 1, k - 1), (k - 1, 0)]:
+        got = run(m, k, i, j)
+        assert rel(got, oracle.invert_block(m, k, i, j)) < 1e-12
+
+
+def test_general_gaussian_matrix_pivots():
+    # Plain N(0,1) entries (the paper's randn matrices): pivoting matters.
+    n, k = 192, 3
+    m = workloads.gaussian(n, 5)
+    inv = np.linalg.inv(m)
+    cond = np.linalg.cond(m)
+    b = n // k
+    for (i, j) in [(0, 0), (2, 1)]:
+        got = run(m, k, i, j)
+        assert rel(got, inv[i * b:(i + 1) * b, j * b:(j + 1) * b]) < 1e-14 * cond * 10
+
+
+def test_fp32_small():
+    n, k = 384, 4
+    m = workloads.haar_spd(n, 9, 0.0, 2.0).m
+    for (i, j) in [(0, 0), (1, 2)]:
+        got = run(m, k, i, j, precision="f32")
+        assert rel(got, oracle.invert_block(m, k, i, j)) < 64 * EPS32 * 1e2
+
+
+def test_config_n256_k2_fp64():
+    m = workloads.workload_matrix("dd_n256_k2")
+    got = run(m, 2, 0, 0)
+    assert rel(got, oracle.invert_block(m, 2, 0, 0)) < 1e-12
+
+
+@pytest.mark.parametrize("i,j", [(0, 0), (1, 2)])
+def test_config_n4096_k4_fp64(i, j):
+    m = workloads.workload_matrix("spd_n4096_k4")
+    got = run(m, 4, i, j)
+    want = oracle.invert_block(m, 4, i, j)
+    assert rel(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("i,j", [(0, 0), (1, 2)])
+def test_config_n4096_k4_fp32(i, j):
+    m = workloads.workload_matrix("spd_n4096_k4")
+    got = run(m, 4, i, j, precision="f32")
+    want = oracle.invert_block(m, 4, i, j)
+    err = rel(got, want)
+    print(f"fp32 n=4096 k=4 ({i},{j}) rel err {err:.3e}", flush=True)
+    assert err < 64 * EPS32 * 1e2
+
+
+def test_singular_pivot_reports_info():
+    # M nonsingular but its block (1,1) -- the first pivot of target (0,0) -- is zero.
+    b = 16
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((b, b)) + 4 * np.eye(b)
+    bq = np.eye(b)
+    m = np.block([[a, bq], [bq, np.zeros((b, b))]])
+    assert abs(np.linalg.det(m)) > 0
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    bri.invert_block(gpu(m), 2, 0, 0, info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 1  # Schur operation 0 met a zero pivot
+
+
+def test_invalid_arguments_raise():
+    m = gpu(workloads.gaussian_dd(16, 1))
+    with pytest.raises(bri.BriError) as e:
+        bri.invert_block(m, 17, 0, 0)
+    assert e.value.status == -4
+    with pytest.raises(bri.BriError) as e:
+        bri.invert_block(m, 4, 4, 0)
+    assert e.value.status == -5
+    with pytest.raises(ValueError):
+        bri.invert_block(m.cpu(), 2, 0, 0)
+
+
+@pytest.mark.parametrize("n,k", [(96, 3), (130, 4), (200, 2)])
+def test_block_column_and_row(n, k):
+    m = workloads.gaussian_dd(n, 300 + n)
+    b = -(-n // k)
+    g = np.eye(k * b)
+    g[:n, :n] = m
+    for j in range(k):
+        x = bri.block_column(gpu(m), k, j).cpu().numpy()
+        ej = np.zeros((k * b, b))
+        ej[j * b:(j + 1) * b] = np.eye(b)
+        assert np.abs(g @ x - ej).max() < 1e-12
+        assert rel(x, oracle.block_column(m, k, j)) < 1e-12
+        xr = bri.block_column(gpu(m), k, j, transpose=True).cpu().numpy()
+        assert rel(xr.T, oracle.block_row(m, k, j)) < 1e-12
+
+
+@pytest.mark.parametrize("n,k,i,j", [(64, 4, 0, 0), (66, 3, 2, 1), (200, 4, 1, 3)])
+def test_backward_fp64_matches_oracle(n, k, i, j):
+    m = workloads.gaussian_dd(n, 500 + n)
+    b = -(-n // k)
+    w = workloads.cotangent(b, seed=501)
+    g = bri.invert_block_backward(gpu(m), k, i, j, gpu(w)).cpu().numpy()
+    assert rel(g, oracle.inverse_block_grad(m, k, i, j, w)) < 1e-12
+
+
+def test_autograd_function_fp64():
+    n, k = 64, 4
+    m = gpu(workloads.gaussian_dd(n, 600)).requires_grad_(True)
+    w = gpu(workloads.cotangent(16, seed=601))
+    x = bri.InvertBlock.apply(m, k, 0, 0)
+    loss = (w * x).sum()
+    loss.backward()
+    want = oracle.inverse_block_grad(m.detach().cpu().numpy(), k, 0, 0, w.cpu().numpy())
+    assert rel(m.grad.cpu().numpy(), want) < 1e-12
+
+
+def test_batched_mixed_problems():
+    probs = workloads.batch_problems(count=24, seed=5, n_lo=64, n_hi=300)
+    Ms = [gpu(workloads.batch_matrix(p)) for p in probs]
+    outs = bri.invert_block_batched(Ms, [p.k for p in probs], [p.i for p in probs], [p.j for p in probs])
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        want = oracle.invert_block(workloads.batch_matrix(p), p.k, p.i, p.j)
+        assert rel(o.cpu().numpy(), want) < 1e-12, (p.n, p.k, p.i, p.j)

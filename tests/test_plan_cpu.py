@@ -1,0 +1,217 @@
+"""Host-side checks of libbri.so that need no GPU.
+
+* every function declared in include/bri.h is exported by the library;
+* invalid arguments are rejected synchronously with LAPACK-style codes;
+* the planner's step list, executed step by step by a small NumPy
+  interpreter written here (test-only; it is neither the oracle nor the
+  product), reproduces blocks of inv(Gamma) -- this checks the scheduling,
+  slot reuse and operand bookkeeping of the host planner on the CPU;
+* the plan performs sum_{i=1}^{k-1} 4^{k-1-i} Schur operations (Theorem
+  "C_BRI") and its live workspace stays within (k + 1) blocks per branch
+  evaluated side by side.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import paper_1612_00001_amd as bri
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bri.h")
+
+ST_LOAD, ST_GETRF, ST_TRTRI, ST_TRMM_L, ST_TRMM_U, ST_GEMM, ST_GEMM_ACC, ST_GEMM_NEG = range(1, 9)
+O_NONE, O_SLOT, O_MBLK, O_IDENT, O_OUT = range(5)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([A-Za-z_]\w*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "defined")))
+
+
+def test_library_exports_every_declared_function():
+    lib = ctypes.CDLL(bri.LIB_PATH)
+    names = declared_functions()
+    assert "invert_block" in names and "invert_block_batched" in names and "invert_block_backward" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings():
+    assert bri.version().startswith("bri-mi355x")
+    assert "workspace" in bri.status_string(bri.BRI_ERR_WORKSPACE)
+    assert "argument" in bri.status_string(-4)
+
+
+def _call_invert(M_ptr, n, ldm, k, i, j, out_ptr, ldo, opts):
+    return bri.lib().invert_block(M_ptr, n, ldm, k, i, j, out_ptr, ldo, opts)
+
+
+def test_argument_validation_codes():
+    o = bri.make_opts("f64")
+    fake = 0x1000  # never dereferenced: validation happens before any work
+    assert _call_invert(None, 8, 8, 2, 0, 0, fake, 4, ctypes.byref(o)) == -1
+    assert _call_invert(fake, 0, 8, 2, 0, 0, fake, 4, ctypes.byref(o)) == -2
+    assert _call_invert(fake, 8, 7, 2, 0, 0, fake, 4, ctypes.byref(o)) == -3
+    assert _call_invert(fake, 8, 8, 1, 0, 0, fake, 4, ctypes.byref(o)) == -4
+    assert _call_invert(fake, 8, 8, 9, 0, 0, fake, 4, ctypes.byref(o)) == -4
+    assert _call_invert(fake, 8, 8, 2, 2, 0, fake, 4, ctypes.byref(o)) == -5
+    assert _call_invert(fake, 8, 8, 2, 0, -1, fake, 4, ctypes.byref(o)) == -6
+    assert _call_invert(fake, 8, 8, 2, 0, 0, None, 4, ctypes.byref(o)) == -7
+    assert _call_invert(fake, 8, 8, 2, 0, 0, fake, 3, ctypes.byref(o)) == -8
+    assert _call_invert(fake, 8, 8, 2, 0, 0, fake, 4, None) == -9
+    # workspace missing / too small
+    assert _call_invert(fake, 8, 8, 2, 0, 0, fake, 4, ctypes.byref(o)) == bri.BRI_ERR_WORKSPACE
+    o.workspace = fake
+    o.workspace_bytes = 16
+    assert _call_invert(fake, 8, 8, 2, 0, 0, fake, 4, ctypes.byref(o)) == bri.BRI_ERR_WORKSPACE
+    # block larger than the supported maximum
+    assert bri.lib().bri_workspace_size(10000, 2, 0, 0, ctypes.byref(o)) == 0
+
+
+def test_theorem_schur_counts_and_workspace_bound():
+    for (n, k) in [(64, 2), (96, 3), (128, 4), (160, 5), (192, 6), (224, 7), (256, 8)]:
+        T = sum(4 ** (k - 1 - i) for i in range(1, k))
+        for (i, j) in [(0, 0), (k - 1, 0), (1, 1)]:
+            for W in (1, 4, 16):
+                d = bri.plan_describe(n, k, i, j, "f64", W)
+                assert d["schur_ops"] == T
+                assert d["final_inversions"] == 1
+                w_eff = d["batch_width"]
+                batch = 1
+                while batch * 4 <= w_eff:
+                    batch *= 4
+                if W == 1:
+                    # one pending block per recursion level + the leaf's
+                    # working set: (k + 1) blocks, one more for i != j
+                    assert d["slots"] <= k + 1 + (1 if i != j else 0)
+                # breadth-first top (< 4/3 batch blocks per level above the
+                # lock-step depth) plus (k + 1) per lock-step branch
+                assert d["slots"] <= batch * (k + 1) + (4 * batch) // 3 * k + 2
+
+
+def test_auto_width_is_a_power_of_four():
+    d = bri.plan_describe(4096, 4, 0, 0, "f64", 0)
+    assert d["batch_width"] == 16
+    d = bri.plan_describe(16384, 8, 0, 0, "f64", 0)
+    assert d["batch_width"] in (4, 16, 64)
+
+
+def test_flop_accounting():
+    b = 1024
+    d = bri.plan_describe(4096, 4, 0, 0, "f64", 0)
+    assert d["algorithmic_flops"] == pytest.approx(21 * 14 / 3 * b ** 3 + 2 * b ** 3)
+    d2 = bri.plan_describe(4096, 4, 1, 2, "f64", 0)
+    assert d2["algorithmic_flops"] == pytest.approx(21 * 14 / 3 * b ** 3 + 4 * b ** 3)
+    assert d["executed_flops"] > d["algorithmic_flops"]
+
+
+# ---------------------------------------------------------------------------
+# Test-only interpreter of the step list
+# ---------------------------------------------------------------------------
+
+def run_plan(m: np.ndarray, k: int, steps, transpose=False):
+    n = m.shape[0]
+    b = -(-n // k)
+    g = np.eye(k * b)
+    g[:n, :n] = m
+    if transpose:
+        g = g.T.copy()
+    slots = {}
+    factors = {}   # slot -> (perm, L, U) or ("inv", perm, Linv, Uinv)
+    out = {}
+
+    def blk(r, c):
+        return g[r * b:(r + 1) * b, c * b:(c + 1) * b]
+
+    def get(op):
+        kind, a, bb = op
+        if kind == O_SLOT:
+            return slots[a]
+        if kind == O_MBLK:
+            return blk(a, bb)
+        if kind == O_IDENT:
+            return np.eye(b)
+        if kind == O_OUT:
+            return out[a]
+        raise AssertionError(op)
+
+    def put(op, val):
+        kind, a, _ = op
+        if kind == O_SLOT:
+            slots[a] = val
+            factors.pop(a, None)
+        elif kind == O_OUT:
+            out[a] = val
+        else:
+            raise AssertionError(op)
+
+    for kind, items in steps:
+        for dst, x, y, cin, sub, node in items:
+            if kind == ST_LOAD:
+                put(dst, get(x).copy())
+            elif kind == ST_GETRF:
+                p, l_, u = scipy.linalg.lu(slots[dst[1]])
+                perm = np.argmax(p, axis=0)       # row r of P^T A is A[perm[r]]
+                f = (perm, l_, u)
+                slots[dst[1]] = np.full((b, b), np.nan)   # contents are now factors
+                factors[dst[1]] = f
+            elif kind == ST_TRTRI:
+                perm, l_, u = factors[dst[1]]
+                slots[x[1]] = np.full((b, b), np.nan)     # scratch
+                factors.pop(x[1], None)
+                factors[dst[1]] = ("inv", perm, np.linalg.inv(l_), np.linalg.inv(u))
+            elif kind == ST_TRMM_L:
+                _, perm, linv, _ = factors[x[1]]
+                put(dst, linv @ get(y)[perm])
+            elif kind == ST_TRMM_U:
+                _, _, _, uinv = factors[x[1]]
+                put(dst, uinv @ get(y))
+            elif kind == ST_GEMM:
+                v = -(get(x) @ get(y))
+                if cin[0] != O_NONE:
+                    v = get(cin) + v
+                if sub[0] != O_NONE:
+                    v = v - get(sub)
+                put(dst, v)
+            elif kind == ST_GEMM_ACC:
+                v = get(x) @ get(y)
+                if cin[0] != O_NONE:
+                    v = get(cin) + v
+                put(dst, v)
+            elif kind == ST_GEMM_NEG:
+                put(dst, -(get(x) @ get(y)))
+            else:
+                raise AssertionError(kind)
+            for v in slots.values():
+                pass
+    return out
+
+
+PLAN_CASES = [
+    (16, 2, 0, 0, 1), (16, 2, 1, 0, 1), (16, 2, 0, 1, 1), (16, 2, 1, 1, 1),
+    (18, 3, 0, 0, 1), (18, 3, 2, 1, 1), (18, 3, 1, 2, 4), (17, 3, 0, 2, 4),
+    (24, 4, 0, 0, 1), (24, 4, 1, 2, 1), (24, 4, 3, 0, 4), (24, 4, 2, 2, 16), (23, 4, 3, 3, 16),
+    (25, 5, 0, 0, 1), (25, 5, 4, 1, 4), (26, 5, 2, 3, 16), (25, 5, 1, 1, 64),
+    (18, 6, 0, 0, 1), (18, 6, 5, 2, 16), (14, 7, 3, 3, 4),
+]
+
+
+@pytest.mark.parametrize("n,k,i,j,W", PLAN_CASES)
+def test_plan_interpreter_reproduces_inverse_blocks(n, k, i, j, W):
+    m = workloads.gaussian_dd(n, 1000 + 7 * n + k)
+    steps = bri.plan_dump(n, k, i, j, "f64", W)
+    out = run_plan(m, k, steps)
+    b = -(-n // k)
+    full = np.eye(k * b)
+    full[:n, :n] = np.linalg.inv(m)
+    want = full[i * b:(i + 1) * b, j * b:(j + 1) * b]
+    assert np.abs(out[0] - want).max() < 1e-12

@@ -157,6 +157,24 @@ int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_pla
 int64_t bri_plan_dump(int64_t n, int k, int i, int j, const bri_opts* o, int64_t* words,
                       int64_t cap);
 
+/* Step timing, a profiling aid.  While enabled, every plan step that
+ * invert_block / bri_block_column enqueue is bracketed by two HIP events on
+ * the caller's stream.  bri_profile_read() waits for those events and writes,
+ * for each step kind t (entry t, kinds as in bri_plan_dump; entry 0 unused),
+ * the number of steps, of kernel launches, the summed GPU time between the
+ * events in milliseconds and the algorithmic flops of the steps (getrf and
+ * triangular inversion 2/3 b^3, triangular products b^3, products 2 b^3 per
+ * item); it then clears the record.  Returns the number of entries written. */
+typedef struct {
+  int64_t steps;
+  int64_t launches;
+  double ms;
+  double flops;
+} bri_profile_entry;
+#define BRI_PROFILE_KINDS 9
+int bri_profile_enable(int on);
+int bri_profile_read(bri_profile_entry* entries, int cap);
+
 /* Human-readable text for a status code returned by any entry point. */
 const char* bri_status_string(int status);
 

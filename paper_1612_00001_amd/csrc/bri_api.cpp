@@ -299,14 +299,84 @@ void build_descriptors(const Ctx& c, const Plan& p, char* host) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Step timing (bri_profile_*)
+// ---------------------------------------------------------------------------
+struct ProfRecord {
+  int kind;
+  int64_t launches;
+  double flops;
+  hipEvent_t e0, e1;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+bri_profile_entry g_prof_acc[BRI_PROFILE_KINDS];
+
+hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+double step_flops(const Step& s, int b) {
+  const double b3 = static_cast<double>(b) * b * b;
+  const double n = static_cast<double>(s.items.size());
+  switch (s.kind) {
+    case ST_LOAD:
+      return 0.0;
+    case ST_GETRF:
+      return n * getrf_flops(b);
+    case ST_TRTRI:
+      return n * trtri_flops(b);
+    case ST_TRMM_L:
+    case ST_TRMM_U:
+      return n * b3;
+    default:
+      return n * 2.0 * b3;
+  }
+}
+
+int64_t step_launches(const Step& s, int b) {
+  switch (s.kind) {
+    case ST_GETRF:
+      return getrf_launches(b);
+    case ST_TRTRI:
+      return trtri_launches(b);
+    default:
+      return 1;
+  }
+}
+
 template <typename T>
 int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
   const char* dbase = c.ws + c.lay->desc_off;
+  bool prof;
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    prof = g_prof_on;
+  }
   for (size_t si = 0; si < p.steps.size(); ++si) {
     const Step& s = p.steps[si];
     const void* d = dbase + c.lay->step_off[si];
     const int count = static_cast<int>(s.items.size());
     hipError_t e = hipSuccess;
+    ProfRecord rec{};
+    if (prof) {
+      std::lock_guard<std::mutex> g(g_prof_mu);
+      rec.kind = s.kind;
+      rec.launches = step_launches(s, c.b);
+      rec.flops = step_flops(s, c.b);
+      rec.e0 = prof_event();
+      rec.e1 = prof_event();
+      if (!rec.e0 || !rec.e1 || hipEventRecord(rec.e0, st) != hipSuccess) return BRI_ERR_HIP;
+    }
     switch (s.kind) {
       case ST_LOAD:
         e = launch_load<T>(static_cast<const LoadItem*>(d), count, c.b, c.b, st);
@@ -328,6 +398,11 @@ int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
       }
     }
     if (e != hipSuccess) return BRI_ERR_HIP;
+    if (prof) {
+      std::lock_guard<std::mutex> g(g_prof_mu);
+      if (hipEventRecord(rec.e1, st) != hipSuccess) return BRI_ERR_HIP;
+      g_prof_pending.push_back(rec);
+    }
   }
   return BRI_OK;
 }
@@ -397,6 +472,34 @@ static int check_block_args(int64_t n, int64_t ldm, int k, int i, int j, int64_t
   if (ldo < b) return -8;
   if (b > BRI_MAX_BLOCK) return BRI_ERR_UNSUPPORTED;
   return 0;
+}
+
+int bri_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  const int was = g_prof_on ? 1 : 0;
+  g_prof_on = on != 0;
+  return was;
+}
+
+int bri_profile_read(bri_profile_entry* entries, int cap) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (ProfRecord& r : g_prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess)
+      return BRI_ERR_HIP;
+    bri_profile_entry& e = g_prof_acc[r.kind];
+    e.steps += 1;
+    e.launches += r.launches;
+    e.ms += ms;
+    e.flops += r.flops;
+    g_prof_pool.push_back(r.e0);
+    g_prof_pool.push_back(r.e1);
+  }
+  g_prof_pending.clear();
+  const int n = std::min(cap, BRI_PROFILE_KINDS);
+  for (int t = 0; t < n; ++t) entries[t] = g_prof_acc[t];
+  std::memset(g_prof_acc, 0, sizeof(g_prof_acc));
+  return n;
 }
 
 size_t bri_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {

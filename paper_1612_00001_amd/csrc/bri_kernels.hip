@@ -86,14 +86,14 @@ struct MF<float> {
 // ---------------------------------------------------------------------------
 // GEMM work items
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int MODE>
 __device__ bool gemm_item(const GemmLaunch& L, int idx, GemmItem& it) {
   const int E = sizeof(T);
-  if (L.mode == GEMM_EXPLICIT) {
+  if (MODE == GEMM_EXPLICIT) {
     it = static_cast<const GemmItem*>(L.items)[idx];
     return true;
   }
-  if (L.mode == GEMM_LU_TRAILING) {
+  if (MODE == GEMM_LU_TRAILING) {
     const LuItem lu = static_cast<const LuItem*>(L.items)[idx];
     const int b = lu.b, j = L.j, w = L.w, m = b - j - w;
     if (m <= 0) return false;
@@ -131,7 +131,7 @@ __device__ bool gemm_item(const GemmLaunch& L, int idx, GemmItem& it) {
   it.Sub = it.Cin;
   if (part == 0) {
     char* tl = tmp;  // s2 x s, ld s
-    if (L.mode == GEMM_TRTRI_STEP1) {
+    if (MODE == GEMM_TRTRI_STEP1) {
       it.A = dense_view(lu.a, b, o + s, o, s2, s, E);        // C
       it.B = dense_view(lu.a, b, o, o, s, s, E, 1);          // A^{-1}, unit lower
       it.out = tl;
@@ -152,7 +152,7 @@ __device__ bool gemm_item(const GemmLaunch& L, int idx, GemmItem& it) {
     }
   } else {
     char* tu = tmp + static_cast<int64_t>(s) * s2 * E;  // s x s2, ld s2
-    if (L.mode == GEMM_TRTRI_STEP1) {
+    if (MODE == GEMM_TRTRI_STEP1) {
       it.A = dense_view(lu.a, b, o, o + s, s, s2, E);          // B
       it.B = dense_view(lu.a, b, o + s, o + s, s2, s2, E, 2);  // D^{-1}, upper
       it.out = tu;
@@ -181,7 +181,10 @@ __device__ bool gemm_item(const GemmLaunch& L, int idx, GemmItem& it) {
 // through double-buffered LDS tiles stored k-major (As[k][m], Bs[k][n]) so
 // that every MFMA operand fetch reads 16 consecutive LDS words.
 // ---------------------------------------------------------------------------
-template <typename T, int BM, int BN, int BK, int WM, int WN>
+// MODE selects how the work items are formed (GemmMode); every mode is its
+// own kernel instance so that profiles separate the Schur products from the
+// LU and triangular-inversion updates.
+template <typename T, int MODE, int BM, int BN, int BK, int WM, int WN>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch L) {
   constexpr int NWN = BN / WN;
   constexpr int NT = (BM / WM) * NWN * 64;
@@ -190,7 +193,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
   static_assert(AE * NT == BM * BK && BE * NT == BK * BN, "tile/thread mismatch");
 
   GemmItem it;
-  if (!gemm_item<T>(L, blockIdx.y, it)) return;
+  if (!gemm_item<T, MODE>(L, blockIdx.y, it)) return;
   const int tiles_n = (it.N + BN - 1) / BN;
   const int tiles_m = (it.M + BM - 1) / BM;
   if (static_cast<int>(blockIdx.x) >= tiles_m * tiles_n) return;
@@ -615,18 +618,32 @@ namespace {
 inline int cdiv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 }  // namespace
 
-template <typename T>
-hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st) {
-  if (L.count <= 0 || max_m <= 0 || max_n <= 0) return hipSuccess;
+template <typename T, int MODE>
+hipError_t launch_gemm_mode(const GemmLaunch& L, int max_m, int max_n, hipStream_t st) {
   const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * L.count;
   if (big_tiles >= 256) {
     dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), L.count);
-    hipLaunchKernelGGL((k_gemm<T, 128, 128, 16, 64, 64>), grid, dim3(256), 0, st, L);
+    hipLaunchKernelGGL((k_gemm<T, MODE, 128, 128, 16, 64, 64>), grid, dim3(256), 0, st, L);
   } else {
     dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), L.count);
-    hipLaunchKernelGGL((k_gemm<T, 64, 64, 16, 32, 32>), grid, dim3(256), 0, st, L);
+    hipLaunchKernelGGL((k_gemm<T, MODE, 64, 64, 16, 32, 32>), grid, dim3(256), 0, st, L);
   }
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st) {
+  if (L.count <= 0 || max_m <= 0 || max_n <= 0) return hipSuccess;
+  switch (L.mode) {
+    case GEMM_EXPLICIT:
+      return launch_gemm_mode<T, GEMM_EXPLICIT>(L, max_m, max_n, st);
+    case GEMM_LU_TRAILING:
+      return launch_gemm_mode<T, GEMM_LU_TRAILING>(L, max_m, max_n, st);
+    case GEMM_TRTRI_STEP1:
+      return launch_gemm_mode<T, GEMM_TRTRI_STEP1>(L, max_m, max_n, st);
+    default:
+      return launch_gemm_mode<T, GEMM_TRTRI_STEP2>(L, max_m, max_n, st);
+  }
 }
 
 template <typename T>

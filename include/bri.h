@@ -69,9 +69,17 @@ typedef enum {
   BRI_MIXED_BF16 = 4  /* M, out: double.  Schur products in BF16 MFMA (FP32 acc).  */
 } bri_precision;
 
+/* Pivoting of the b x b pivot factorisations (the method itself never
+ * pivots across blocks: every pivot is a principal Schur complement). */
+typedef enum {
+  BRI_PIVOT_TILE = 0,   /* partial pivoting inside each 32-row diagonal tile (default) */
+  BRI_PIVOT_PANEL = 1   /* partial pivoting over all rows of the pivot block (LAPACK getrf) */
+} bri_pivoting;
+
 typedef struct {
   int precision;           /* a bri_precision value                                   */
   int concurrency;         /* W: Schur operations evaluated side by side; <= 0: auto  */
+  int pivoting;            /* a bri_pivoting value                                    */
   int refine_max_iters;    /* mixed paths: refinement sweeps (0 = none)               */
   double refine_tol;       /* mixed paths: stop when ||dX||_F <= tol * ||X||_F        */
   void* workspace;         /* device workspace, >= bri_workspace_size() bytes         */
@@ -80,8 +88,9 @@ typedef struct {
   hipStream_t stream;      /* stream the work is enqueued on (NULL = default stream)  */
 } bri_opts;
 
-/* Fills *o with defaults: BRI_F64, automatic concurrency, 10 refinement sweeps,
- * tolerance 1e-12, no workspace, no d_info, default stream. */
+/* Fills *o with defaults: BRI_F64, automatic concurrency, tile pivoting,
+ * 10 refinement sweeps, tolerance 1e-12, no workspace, no d_info, default
+ * stream. */
 void bri_default_opts(bri_opts* o);
 
 /* Bytes of device workspace invert_block() needs for (n, k, i, j) with the
@@ -129,6 +138,18 @@ size_t bri_backward_workspace_size(int64_t n, int k, int i, int j, const bri_opt
 int invert_block_backward(const void* M, int64_t n, int64_t ldm, int k, int i, int j,
                           const void* G, int64_t ldg, void* grad_M, int64_t ldgm,
                           const bri_opts* o);
+
+/* The Schur-update product kernel on plain operands: for t < count,
+ *   C[t] = beta * C[t] + alpha * A[t] B[t]     (C[t]: m x n, A[t]: m x kk, B[t]: kk x n)
+ * row-major with leading dimensions lda, ldb, ldc; A, B, C are HOST arrays of
+ * DEVICE pointers.  precision BRI_F64 (double) or BRI_F32 (float); C may not
+ * alias A or B.  Uses o->stream and, for its descriptors, o->workspace of at
+ * least bri_gemm_workspace_size(count) bytes.  This is the MFMA kernel every
+ * Schur complement D - C A^{-1} B of the recursion runs its products on
+ * (eqs. SchurofA..SchurofD); it is exported to measure and test it alone. */
+size_t bri_gemm_workspace_size(int count);
+int bri_gemm(int count, int64_t m, int64_t n, int64_t kk, double alpha, const void* const* A, int64_t lda,
+             const void* const* B, int64_t ldb, double beta, void* const* C, int64_t ldc, const bri_opts* o);
 
 /* Structure of the evaluation plan for (n, k, i, j) under *o, without running
  * it (host only).  Counts are per call of invert_block. */

@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbri.so")
 
 PRECISIONS = {"f64": 0, "f32": 1, "mixed_f32": 2, "mixed_f16": 3, "mixed_bf16": 4}
+PIVOTING = {"tile": 0, "panel": 1}
 _DTYPE_OF = {"f64": torch.float64, "f32": torch.float32, "mixed_f32": torch.float64,
              "mixed_f16": torch.float64, "mixed_bf16": torch.float64}
 
@@ -33,6 +34,7 @@ class BriOpts(ctypes.Structure):
     _fields_ = [
         ("precision", ctypes.c_int),
         ("concurrency", ctypes.c_int),
+        ("pivoting", ctypes.c_int),
         ("refine_max_iters", ctypes.c_int),
         ("refine_tol", ctypes.c_double),
         ("workspace", ctypes.c_void_p),
@@ -97,6 +99,12 @@ _SIGNATURES = [
     ("bri_plan_dump", ctypes.c_int64,
      [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BriOpts),
       ctypes.POINTER(ctypes.c_int64), ctypes.c_int64]),
+    ("bri_gemm_workspace_size", ctypes.c_size_t, [ctypes.c_int]),
+    ("bri_gemm", ctypes.c_int,
+     [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+      ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64,
+      ctypes.c_double, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.POINTER(BriOpts)]),
+    ("bri_profile_enable", ctypes.c_int, [ctypes.c_int]),
     ("bri_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("bri_version", ctypes.c_char_p, []),
 ]
@@ -127,12 +135,15 @@ def _check(status: int) -> None:
 
 
 def make_opts(precision: str = "f64", concurrency: int = 0, refine_max_iters: int = 10,
-              refine_tol: float = 1e-12) -> BriOpts:
+              refine_tol: float = 1e-12, pivoting: str = "tile") -> BriOpts:
     o = BriOpts()
     lib().bri_default_opts(ctypes.byref(o))
     if precision not in PRECISIONS:
         raise ValueError(f"unknown precision {precision!r}")
+    if pivoting not in PIVOTING:
+        raise ValueError(f"unknown pivoting {pivoting!r}")
     o.precision = PRECISIONS[precision]
+    o.pivoting = PIVOTING[pivoting]
     o.concurrency = int(concurrency)
     o.refine_max_iters = int(refine_max_iters)
     o.refine_tol = float(refine_tol)
@@ -194,7 +205,7 @@ def workspace_size(n: int, k: int, i: int, j: int, precision: str = "f64", concu
 def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
                  out: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
                  workspace: Optional[torch.Tensor] = None, refine_max_iters: int = 10,
-                 refine_tol: float = 1e-12) -> torch.Tensor:
+                 refine_tol: float = 1e-12, pivoting: str = "tile") -> torch.Tensor:
     """Block N_ij (b x b, b = ceil(n/k)) of M^{-1} (of Gamma^{-1} when k does not divide n).
 
     ``info`` (optional int32 GPU tensor of one element) receives the device
@@ -206,7 +217,7 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
     if M.shape[1] != n:
         raise ValueError("M must be square")
     b = block_size(n, k)
-    o = make_opts(precision, concurrency, refine_max_iters, refine_tol)
+    o = make_opts(precision, concurrency, refine_max_iters, refine_tol, pivoting)
     need = lib().bri_workspace_size(n, k, i, j, ctypes.byref(o))
     if need == 0:
         # Invalid arguments: let the library name the offending one (it
@@ -301,6 +312,33 @@ def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Seq
     o.stream = _stream_ptr(dev)
     _check(lib().invert_block_batched(count, mp, n, ldm, kk, ii, jj, op, ldo, ctypes.byref(o)))
     return outs
+
+
+def gemm(A: Sequence[torch.Tensor], B: Sequence[torch.Tensor], C: Sequence[torch.Tensor],
+         alpha: float = 1.0, beta: float = 0.0, workspace: Optional[torch.Tensor] = None) -> None:
+    """C[t] = beta C[t] + alpha A[t] B[t] on the library's MFMA product kernel (in place on C)."""
+    count = len(A)
+    if count == 0:
+        return
+    dtype = A[0].dtype
+    prec = "f64" if dtype == torch.float64 else "f32"
+    for t in range(count):
+        for nm, x in (("A", A[t]), ("B", B[t]), ("C", C[t])):
+            _require_gpu(x, f"{nm}[{t}]", dtype)
+    m, kk = A[0].shape
+    n = B[0].shape[1]
+    o = make_opts(prec)
+    need = lib().bri_gemm_workspace_size(count)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=A[0].device)
+    o.workspace = workspace.data_ptr()
+    o.workspace_bytes = workspace.numel()
+    o.stream = _stream_ptr(A[0].device)
+    ap = (ctypes.c_void_p * count)(*[x.data_ptr() for x in A])
+    bp = (ctypes.c_void_p * count)(*[x.data_ptr() for x in B])
+    cp = (ctypes.c_void_p * count)(*[x.data_ptr() for x in C])
+    _check(lib().bri_gemm(count, m, n, kk, alpha, ap, A[0].stride(0), bp, B[0].stride(0), beta, cp,
+                          C[0].stride(0), ctypes.byref(o)))
 
 
 class InvertBlock(torch.autograd.Function):

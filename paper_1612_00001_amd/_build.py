@@ -13,7 +13,9 @@ BUILD = os.path.join(HERE, "_build")
 SOURCES = ["bri_kernels.hip", "bri_api.cpp", "bri_plan.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device compilation.
-DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                # MFMA accumulators in VGPRs: no per-iteration AGPR<->VGPR copies
+                "-mllvm", "-amdgpu-mfma-vgpr-form"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
           "-I" + os.path.join(HERE, "..", "include"), "-I" + CSRC]
 

@@ -28,8 +28,9 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
+  std::vector<int> nfast;        // explicit GEMM steps: items taking the fast kernel instance
   size_t slot_bytes = 0;
-  size_t slots_off = 0, perm_off = 0, swap_off = 0, info_off = 0, desc_off = 0;
+  size_t slots_off = 0, perm_off = 0, swap_off = 0, aux_off = 0, aux_bytes = 0, info_off = 0, desc_off = 0;
   size_t desc_bytes = 0;
   size_t total = 0;
   std::vector<size_t> step_off;  // descriptor offset of every step (relative to desc_off)
@@ -58,6 +59,9 @@ Layout make_layout(const Plan& p, int elem) {
   off += align_up(b * sizeof(int32_t) * p.nslots);
   L.swap_off = off;
   off += align_up(sizeof(int32_t) * kSwapWords * p.nslots);
+  L.aux_off = off;
+  L.aux_bytes = align_up(static_cast<size_t>(2) * kTile * kTile * elem);
+  off += L.aux_bytes * p.nslots;
   L.info_off = off;
   off += kAlign;
   L.desc_off = off;
@@ -134,6 +138,7 @@ std::shared_ptr<CachedPlan> get_plan(int kind, int64_t n, int k, int i, int j, i
 // Operand resolution
 // ---------------------------------------------------------------------------
 struct Ctx {
+  int pivoting = BRI_PIVOT_TILE;
   const char* M = nullptr;
   int64_t n = 0, ldm = 0;
   int b = 0;
@@ -166,6 +171,7 @@ int32_t* perm_ptr(const Ctx& c, int s) {
 int32_t* swap_ptr(const Ctx& c, int s) {
   return reinterpret_cast<int32_t*>(c.ws + c.lay->swap_off) + static_cast<int64_t>(s) * kSwapWords;
 }
+char* aux_ptr(const Ctx& c, int s) { return c.ws + c.lay->aux_off + c.lay->aux_bytes * s; }
 
 DView slot_view(const Ctx& c, int s, int tri = 0) {
   DView v = zero_view();
@@ -235,10 +241,14 @@ GemmItem gemm_base(const Ctx& c) {
   return g;
 }
 
-void build_descriptors(const Ctx& c, const Plan& p, char* host) {
+void build_descriptors(const Ctx& c, const Plan& p, char* host, std::vector<int>& nfast) {
+  nfast.assign(p.steps.size(), 0);
+  std::vector<GemmItem> fast, slow;
   for (size_t si = 0; si < p.steps.size(); ++si) {
     const Step& s = p.steps[si];
     char* base = host + c.lay->step_off[si];
+    fast.clear();
+    slow.clear();
     for (size_t t = 0; t < s.items.size(); ++t) {
       const StepItem& it = s.items[t];
       switch (s.kind) {
@@ -260,6 +270,7 @@ void build_descriptors(const Ctx& c, const Plan& p, char* host) {
           lu.perm = perm_ptr(c, it.dst.a);
           lu.swaps = swap_ptr(c, it.dst.a);
           lu.tmp = s.kind == ST_TRTRI ? slot_ptr(c, it.x.a) : nullptr;
+          lu.aux = aux_ptr(c, it.dst.a);
           lu.node = it.node;
           lu.b = c.b;
           std::memcpy(base + t * sizeof(LuItem), &lu, sizeof(lu));
@@ -291,10 +302,16 @@ void build_descriptors(const Ctx& c, const Plan& p, char* host) {
             }
             g.alpha = (s.kind == ST_GEMM_ACC) ? 1.0 : -1.0;
           }
-          std::memcpy(base + t * sizeof(GemmItem), &g, sizeof(g));
+          (gemm_item_is_fast(g) ? fast : slow).push_back(g);
           break;
         }
       }
+    }
+    if (!fast.empty() || !slow.empty()) {
+      // Fast items first; the generic instance takes the rest.
+      std::memcpy(base, fast.data(), fast.size() * sizeof(GemmItem));
+      std::memcpy(base + fast.size() * sizeof(GemmItem), slow.data(), slow.size() * sizeof(GemmItem));
+      nfast[si] = static_cast<int>(fast.size());
     }
   }
 }
@@ -382,7 +399,8 @@ int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
         e = launch_load<T>(static_cast<const LoadItem*>(d), count, c.b, c.b, st);
         break;
       case ST_GETRF:
-        e = launch_getrf<T>(static_cast<const LuItem*>(d), count, c.b, c.info, st);
+        e = c.pivoting == BRI_PIVOT_PANEL ? launch_getrf<T>(static_cast<const LuItem*>(d), count, c.b, c.info, st)
+                                          : launch_getrf_tile<T>(static_cast<const LuItem*>(d), count, c.b, c.info, st);
         break;
       case ST_TRTRI:
         e = launch_trtri<T>(static_cast<const LuItem*>(d), count, c.b, st);
@@ -393,6 +411,7 @@ int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
         L.elem = sizeof(T);
         L.items = d;
         L.count = count;
+        L.w = c.lay->nfast[si];
         e = launch_gemm<T>(L, c.b, c.b, st);
         break;
       }
@@ -419,7 +438,7 @@ int execute(CachedPlan& cp, Ctx& c, hipStream_t st, bool clear_info) {
     if (hipEventSynchronize(cp.uploaded) != hipSuccess) return BRI_ERR_HIP;
   }
   try {
-    build_descriptors(c, cp.plan, static_cast<char*>(cp.host));
+    build_descriptors(c, cp.plan, static_cast<char*>(cp.host), cp.layout.nfast);
   } catch (const std::exception&) {
     return BRI_ERR_UNSUPPORTED;
   }
@@ -447,6 +466,7 @@ void bri_default_opts(bri_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->precision = BRI_F64;
   o->concurrency = 0;
+  o->pivoting = BRI_PIVOT_TILE;
   o->refine_max_iters = 10;
   o->refine_tol = 1e-12;
 }
@@ -584,6 +604,7 @@ int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, voi
   }
   if (!o->workspace || o->workspace_bytes < cp->layout.total) return BRI_ERR_WORKSPACE;
   Ctx c;
+  c.pivoting = o->pivoting;
   c.M = static_cast<const char*>(M);
   c.n = n;
   c.ldm = ldm;
@@ -626,6 +647,7 @@ int bri_block_column(const void* M, int64_t n, int64_t ldm, int k, int j, int tr
   }
   if (!o->workspace || o->workspace_bytes < cp->layout.total) return BRI_ERR_WORKSPACE;
   Ctx c;
+  c.pivoting = o->pivoting;
   c.M = static_cast<const char*>(M);
   c.n = n;
   c.ldm = ldm;
@@ -670,6 +692,82 @@ int invert_block_batched(int count, const void* const* M, const int64_t* n, cons
     if (rc != BRI_OK) return rc;
   }
   return BRI_OK;
+}
+
+size_t bri_gemm_workspace_size(int count) {
+  return count <= 0 ? 0 : align_up(static_cast<size_t>(count) * sizeof(GemmItem)) + kAlign;
+}
+
+int bri_gemm(int count, int64_t m, int64_t n, int64_t kk, double alpha, const void* const* A, int64_t lda,
+             const void* const* B, int64_t ldb, double beta, void* const* C, int64_t ldc, const bri_opts* o) {
+  if (count < 0) return -1;
+  if (m < 0 || m > INT_MAX) return -2;
+  if (n < 0 || n > INT_MAX) return -3;
+  if (kk < 0 || kk > INT_MAX) return -4;
+  if (!A && count) return -6;
+  if (lda < std::max<int64_t>(1, kk)) return -7;
+  if (!B && count) return -8;
+  if (ldb < std::max<int64_t>(1, n)) return -9;
+  if (!C && count) return -11;
+  if (ldc < std::max<int64_t>(1, n)) return -12;
+  if (!o) return -13;
+  if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
+  if (count == 0 || m == 0 || n == 0) return BRI_OK;
+  const size_t need = bri_gemm_workspace_size(count);
+  if (!o->workspace || o->workspace_bytes < need) return BRI_ERR_WORKSPACE;
+  std::vector<GemmItem> items(count);
+  for (int t = 0; t < count; ++t) {
+    GemmItem& g = items[t];
+    std::memset(&g, 0, sizeof(g));
+    g.A = g.B = g.Cin = g.Sub = zero_view();
+    g.A.p = A[t];
+    g.A.ld = lda;
+    g.A.rows = static_cast<int32_t>(m);
+    g.A.cols = static_cast<int32_t>(kk);
+    g.B.p = B[t];
+    g.B.ld = ldb;
+    g.B.rows = static_cast<int32_t>(kk);
+    g.B.cols = static_cast<int32_t>(n);
+    g.Cin = g.A;
+    g.Cin.p = C[t];
+    g.Cin.ld = ldc;
+    g.Cin.rows = static_cast<int32_t>(m);
+    g.Cin.cols = static_cast<int32_t>(n);
+    g.has_cin = beta != 0.0 ? 1 : 0;
+    g.out = C[t];
+    g.ldo = ldc;
+    g.M = static_cast<int32_t>(m);
+    g.N = static_cast<int32_t>(n);
+    g.K = static_cast<int32_t>(kk);
+    g.alpha = alpha;
+    g.beta = beta;
+  }
+  static std::mutex mu;
+  static void* host = nullptr;
+  static size_t host_bytes = 0;
+  static hipEvent_t ev = nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  const size_t bytes = items.size() * sizeof(GemmItem);
+  if (ev && hipEventSynchronize(ev) != hipSuccess) return BRI_ERR_HIP;
+  if (host_bytes < bytes) {
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+    if (hipHostMalloc(&host, bytes) != hipSuccess) return BRI_ERR_HIP;
+    host_bytes = bytes;
+  }
+  if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return BRI_ERR_HIP;
+  std::memcpy(host, items.data(), bytes);
+  if (hipMemcpyAsync(o->workspace, host, bytes, hipMemcpyHostToDevice, o->stream) != hipSuccess) return BRI_ERR_HIP;
+  if (hipEventRecord(ev, o->stream) != hipSuccess) return BRI_ERR_HIP;
+  GemmLaunch L{};
+  L.mode = GEMM_EXPLICIT;
+  L.elem = elem_size(o->precision);
+  L.items = o->workspace;
+  L.count = count;
+  L.w = count;  // plain dense operands: all items take the fast instance
+  const hipError_t e = L.elem == 8 ? launch_gemm<double>(L, static_cast<int>(m), static_cast<int>(n), o->stream)
+                                   : launch_gemm<float>(L, static_cast<int>(m), static_cast<int>(n), o->stream);
+  return e == hipSuccess ? BRI_OK : BRI_ERR_HIP;
 }
 
 size_t bri_backward_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
@@ -772,6 +870,7 @@ int invert_block_backward(const void* M, int64_t n, int64_t ldm, int k, int i, i
   L.mode = GEMM_EXPLICIT;
   L.elem = elem;
   L.count = 1;
+  L.w = 1;  // stored dense operands (U, G, T1, V^T)
   L.items = desc;
   hipError_t e = elem == 8 ? launch_gemm<double>(L, static_cast<int>(n), static_cast<int>(b), o->stream)
                            : launch_gemm<float>(L, static_cast<int>(n), static_cast<int>(b), o->stream);

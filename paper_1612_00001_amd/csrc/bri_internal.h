@@ -44,9 +44,14 @@ struct LuItem {
   int32_t* perm;     // b entries: row x of P A is row perm[x] of A
   int32_t* swaps;    // per-panel list of moved rows: [count, (dest, src) ...]
   void* tmp;         // b x b scratch for the triangular inversion
+  void* aux;         // 2 kTile^2 elements: inverses of the current diagonal tile's L and U
   int32_t node;      // Schur operation index reported through d_info
   int32_t b;
 };
+
+// Tile of the tile-local pivoting LU: the pivot search of column c runs over
+// the rows of the kTile x kTile diagonal tile that holds c.
+constexpr int kTile = 32;
 
 struct LoadItem {
   DView src;
@@ -67,10 +72,32 @@ struct GemmLaunch {
   int32_t elem;         // 8 = double, 4 = float
   const void* items;    // GemmItem* or LuItem*
   int32_t count;        // items for GEMM_EXPLICIT, matrices otherwise
-  int32_t j, w;         // LU step: panel start and width
+  int32_t j, w;         // LU step: panel start and width.  GEMM_EXPLICIT:
+                        // w = number of leading items the fast instance
+                        // takes (see gemm_item_is_fast), j = item offset
   int32_t s;            // TRTRI level: half-block size
   int32_t npairs;       // TRTRI level: block pairs per matrix
 };
+
+constexpr int kMaxBlock = 4096;  // == BRI_MAX_BLOCK
+
+// True when every element the product reads from A and B is either stored
+// (inside the view's stored extent) or synthesised without stored data, so
+// the fast GEMM instance can stream the operands.
+inline bool view_fast(const DView& v, int xlim, int ylim) {
+  if (v.p == nullptr) return v.rows == 0;
+  if (v.trans && v.rowperm) return false;
+  const int need_rows = v.rowperm ? xlim : xlim;  // permuted rows are < xlim as well
+  return need_rows <= v.rows && ylim <= v.cols;
+}
+// Plain: stored, untransposed, unpermuted, untriangular and covering M x N.
+inline bool view_plain(const DView& v, int xlim, int ylim) {
+  return v.p != nullptr && !v.trans && !v.rowperm && v.tri == 0 && xlim <= v.rows && ylim <= v.cols;
+}
+inline bool gemm_item_is_fast(const GemmItem& g) {
+  return view_fast(g.A, g.M, g.K) && view_fast(g.B, g.K, g.N) && (!g.has_cin || view_plain(g.Cin, g.M, g.N)) &&
+         (!g.has_sub || view_plain(g.Sub, g.M, g.N));
+}
 
 constexpr int kSwapWords = 1 + 2 * 2 * 64;  // count + up to 128 (dest, src) pairs
 constexpr int kTrtriTile = 32;                // diagonal tile of the triangular inversion

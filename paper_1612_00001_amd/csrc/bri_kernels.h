@@ -12,6 +12,8 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
 template <typename T>
 hipError_t launch_getrf(const LuItem* d_items, int count, int b, int32_t* info, hipStream_t st);
 template <typename T>
+hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, int32_t* info, hipStream_t st);
+template <typename T>
 hipError_t launch_trtri(const LuItem* d_items, int count, int b, hipStream_t st);
 template <typename T>
 hipError_t launch_load(const LoadItem* d_items, int count, int rows, int cols, hipStream_t st);

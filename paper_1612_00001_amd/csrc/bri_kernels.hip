@@ -18,6 +18,7 @@
 //  * k_load      -- copies a view into a dense workspace block.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 #include <utility>
@@ -176,24 +177,114 @@ __device__ bool gemm_item(const GemmLaunch& L, int idx, GemmItem& it) {
 }
 
 // ---------------------------------------------------------------------------
+// Operand tiles.  The fast GEMM instance handles operands that are either
+// stored data covering every element the product reads (optionally through
+// a row permutation and/or a triangular mask) or synthesised (no data:
+// element = (x - y == diag), the identity or zero).  Loads are issued into
+// raw registers and only consumed after the MFMA work of the current K-tile,
+// when bounds and masks are applied on the way into LDS.  The thread-to-
+// element mapping follows the contiguous direction of the stored data so that
+// every load instruction is coalesced.  Operands that need element-wise view
+// evaluation (tiles crossing the identity padding of Gamma) use the generic
+// instance (GEN = true), chosen per item on the host.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)(p);
+}
+
+template <typename T, int R, int C, int NT>
+struct TileOp {
+  static constexpr int E = R * C / NT;
+  bool synth, trans;
+  const T* p;
+  int64_t ld;
+  const int32_t* perm;  // LDS copy of the row permutation, or null
+  int tri, diag;
+  int xlim, ylim;       // product operand extent (M x K for A, K x N for B)
+  int r0, dr, c0, dc;   // this thread's first local (row, col) and per-element step
+  T raw[E];
+
+  __device__ __forceinline__ void init(const DView& v, const int32_t* perm_lds, int xlim_, int ylim_, int tid) {
+    trans = v.trans != 0;
+    p = static_cast<const T*>(v.p);
+    ld = v.ld;
+    perm = v.rowperm ? perm_lds : nullptr;
+    tri = v.tri;
+    diag = v.diag;
+    xlim = xlim_;
+    ylim = ylim_;
+    synth = p == nullptr;
+    if (!trans) {  // contiguous along y
+      r0 = tid / C;
+      dr = NT / C;
+      c0 = tid % C;
+      dc = 0;
+    } else {       // contiguous along x
+      r0 = tid % R;
+      dr = 0;
+      c0 = tid / R;
+      dc = NT / R;
+    }
+  }
+
+  __device__ __forceinline__ void issue(int x0, int y0) {
+    if (synth) return;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      const int x = min(x0 + r0 + t * dr, xlim - 1);
+      const int y = min(y0 + c0 + t * dc, ylim - 1);
+      const int xs = perm ? perm[x] : x;
+      raw[t] = trans ? gload(p + static_cast<int64_t>(y) * ld + xs) : gload(p + static_cast<int64_t>(xs) * ld + y);
+    }
+  }
+
+  __device__ __forceinline__ T finalize(int t, int x0, int y0) const {
+    const int x = x0 + r0 + t * dr, y = y0 + c0 + t * dc;
+    T v;
+    if (synth) {
+      const int xs = perm ? perm[min(x, xlim - 1)] : x;
+      v = (xs - y == diag) ? T(1) : T(0);
+    } else {
+      v = raw[t];
+    }
+    if (tri == 1) v = x > y ? v : (x == y ? T(1) : T(0));
+    if (tri == 2) v = x <= y ? v : T(0);
+    return (x < xlim && y < ylim) ? v : T(0);
+  }
+
+  // Element-wise path of the generic instance.
+  __device__ __forceinline__ void issue_generic(const DView& v, int x0, int y0) {
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      const int x = x0 + r0 + t * dr, y = y0 + c0 + t * dc;
+      raw[t] = (x < xlim && y < ylim) ? vget<T>(v, x, y) : T(0);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Batched MFMA GEMM.  One workgroup computes a BM x BN output tile with
 // (BM/WM) x (BN/WN) wavefronts of WM x WN each; K is consumed BK at a time
 // through double-buffered LDS tiles stored k-major (As[k][m], Bs[k][n]) so
 // that every MFMA operand fetch reads 16 consecutive LDS words.
-// ---------------------------------------------------------------------------
 // MODE selects how the work items are formed (GemmMode); every mode is its
 // own kernel instance so that profiles separate the Schur products from the
 // LU and triangular-inversion updates.
-template <typename T, int MODE, int BM, int BN, int BK, int WM, int WN>
+// ---------------------------------------------------------------------------
+template <typename T, int MODE, bool GEN, int BM, int BN, int BK, int WM, int WN>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch L) {
   constexpr int NWN = BN / WN;
   constexpr int NT = (BM / WM) * NWN * 64;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int AE = BM * BK / NT, BE = BK * BN / NT;
+  typedef TileOp<T, BM, BK, NT> OpA;
+  typedef TileOp<T, BK, BN, NT> OpB;
+  constexpr int AE = OpA::E, BE = OpB::E;
   static_assert(AE * NT == BM * BK && BE * NT == BK * BN, "tile/thread mismatch");
+  constexpr bool USE_PERM = (MODE == GEMM_EXPLICIT) && !GEN;
 
   GemmItem it;
-  if (!gemm_item<T, MODE>(L, blockIdx.y, it)) return;
+  if (!gemm_item<T, MODE>(L, blockIdx.y + (GEN ? L.j : 0), it)) return;
   const int tiles_n = (it.N + BN - 1) / BN;
   const int tiles_m = (it.M + BM - 1) / BM;
   if (static_cast<int>(blockIdx.x) >= tiles_m * tiles_n) return;
@@ -209,9 +300,31 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
 
   __shared__ T As[2][BK][BM + 1];
   __shared__ T Bs[2][BK][BN + 1];
+  __shared__ int32_t s_perm[USE_PERM ? kMaxBlock : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / NWN, wn = wave % NWN;
+
+  OpA opa;
+  OpB opb;
+  const int32_t* permA = nullptr;
+  const int32_t* permB = nullptr;
+  if (USE_PERM) {
+    // At most one operand carries a row permutation (the B operand of
+    // L^{-1} P B); stage it in LDS once.
+    const int32_t* gp = it.B.rowperm ? it.B.rowperm : it.A.rowperm;
+    const int np = it.B.rowperm ? it.K : it.M;
+    if (gp) {
+      for (int e = tid; e < np; e += NT) s_perm[e] = gp[e];
+      __syncthreads();
+      if (it.B.rowperm)
+        permB = s_perm;
+      else
+        permA = s_perm;
+    }
+  }
+  opa.init(it.A, permA, it.M, it.K, tid);
+  opb.init(it.B, permB, it.K, it.N, tid);
 
   typename MF<T>::acc acc[FM][FN];
 #pragma unroll
@@ -221,71 +334,32 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
 
-  T ra[AE], rb[BE];
-  const bool a_plain = it.A.tri == 0 && it.A.rowperm == nullptr;
-  const bool b_plain = it.B.tri == 0 && it.B.rowperm == nullptr;
-
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int t = 0; t < AE; ++t) {
-      const int e = tid + t * NT;
-      const int x = it.A.trans ? e % BM : e / BK;
-      const int y = it.A.trans ? e / BM : e % BK;
-      const int gx = m0 + x, gy = k0 + y;
-      T v = T(0);
-      if (gx < it.M && gy < it.K) {
-        if (a_plain && gx < it.A.rows && gy < it.A.cols) {
-          const T* p = static_cast<const T*>(it.A.p);
-          v = it.A.trans ? p[static_cast<int64_t>(gy) * it.A.ld + gx] : p[static_cast<int64_t>(gx) * it.A.ld + gy];
-        } else {
-          v = vget<T>(it.A, gx, gy);
-        }
-      }
-      ra[t] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < BE; ++t) {
-      const int e = tid + t * NT;
-      const int x = it.B.trans ? e % BK : e / BN;
-      const int y = it.B.trans ? e / BK : e % BN;
-      const int gx = k0 + x, gy = n0 + y;
-      T v = T(0);
-      if (gx < it.K && gy < it.N) {
-        if (b_plain && gx < it.B.rows && gy < it.B.cols) {
-          const T* p = static_cast<const T*>(it.B.p);
-          v = it.B.trans ? p[static_cast<int64_t>(gy) * it.B.ld + gx] : p[static_cast<int64_t>(gx) * it.B.ld + gy];
-        } else {
-          v = vget<T>(it.B, gx, gy);
-        }
-      }
-      rb[t] = v;
+  auto issue = [&](int k0) {
+    if (GEN) {
+      opa.issue_generic(it.A, m0, k0);
+      opb.issue_generic(it.B, k0, n0);
+    } else {
+      opa.issue(m0, k0);
+      opb.issue(k0, n0);
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, int k0) {
 #pragma unroll
-    for (int t = 0; t < AE; ++t) {
-      const int e = tid + t * NT;
-      const int x = it.A.trans ? e % BM : e / BK;
-      const int y = it.A.trans ? e / BM : e % BK;
-      As[buf][y][x] = ra[t];
-    }
+    for (int t = 0; t < AE; ++t)
+      As[buf][opa.c0 + t * opa.dc][opa.r0 + t * opa.dr] = GEN ? opa.raw[t] : opa.finalize(t, m0, k0);
 #pragma unroll
-    for (int t = 0; t < BE; ++t) {
-      const int e = tid + t * NT;
-      const int x = it.B.trans ? e % BK : e / BN;
-      const int y = it.B.trans ? e / BK : e % BN;
-      Bs[buf][x][y] = rb[t];
-    }
+    for (int t = 0; t < BE; ++t)
+      Bs[buf][opb.r0 + t * opb.dr][opb.c0 + t * opb.dc] = GEN ? opb.raw[t] : opb.finalize(t, k0, n0);
   };
 
   if (kb < ke) {
-    load(kb);
-    store(0);
+    issue(kb);
+    store(0, kb);
     __syncthreads();
     int buf = 0;
     for (int k0 = kb; k0 < ke; k0 += BK) {
       const bool more = k0 + BK < ke;
-      if (more) load(k0 + BK);
+      if (more) issue(k0 + BK);
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         T a[FM], bv[FN];
@@ -298,7 +372,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
 #pragma unroll
           for (int j = 0; j < FN; ++j) acc[i][j] = MF<T>::mma(a[i], bv[j], acc[i][j]);
       }
-      if (more) store(buf ^ 1);
+      if (more) store(buf ^ 1, k0 + BK);
       __syncthreads();
       buf ^= 1;
     }
@@ -306,6 +380,8 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
 
   T* out = static_cast<T*>(it.out);
   const T alpha = static_cast<T>(it.alpha), beta = static_cast<T>(it.beta);
+  const T* cinp = static_cast<const T*>(it.Cin.p);
+  const T* subp = static_cast<const T*>(it.Sub.p);
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -316,141 +392,216 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
         const int c = n0 + wn * WN + j * 16 + (lane & 15);
         if (r < it.M && c < it.N) {
           T val = alpha * acc[i][j][v];
-          if (it.has_cin) val += beta * vget<T>(it.Cin, r, c);
-          if (it.has_sub) val -= vget<T>(it.Sub, r, c);
+          // The fast instance only receives plain Cin / Sub (gemm_item_is_fast).
+          if (it.has_cin)
+            val += beta * (GEN ? vget<T>(it.Cin, r, c) : gload(cinp + static_cast<int64_t>(r) * it.Cin.ld + c));
+          if (it.has_sub)
+            val -= GEN ? vget<T>(it.Sub, r, c) : gload(subp + static_cast<int64_t>(r) * it.Sub.ld + c);
           out[static_cast<int64_t>(r) * it.ldo + c] = val;
         }
       }
 }
 
 // ---------------------------------------------------------------------------
-// Panel LU with partial pivoting.  Rows j..b-1, columns j..j+w-1 of one
-// matrix live in registers: thread t owns panel rows t + 512 q (q < R).  For
-// every column the workgroup finds the row of largest magnitude (lowest index
-// on ties, as LAPACK's idamax), exchanges it with the current row through
-// LDS, scales the multipliers and updates the rest of the panel.  The
-// composite row movement is recorded as (dest, src) pairs for k_laswp_trsm,
-// and the running permutation of the matrix is composed in it.perm.
-// Columns are unrolled at compile time (panel_step<C>) so that every register
-// index is static.
+// Wave-wide argmax with DPP: the largest value, lowest index on ties (the
+// rule of LAPACK's idamax).  Every lane returns the wave's winner.
 // ---------------------------------------------------------------------------
-template <typename T, int NB>
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_argmax_step(double& v, int& i) {
+  const int64_t bits = __double_as_longlong(v);
+  const int lo = static_cast<int>(bits & 0xffffffff), hi = static_cast<int>(bits >> 32);
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+  const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, ROW_MASK, 0xf, false);
+  const double ov = __longlong_as_double((static_cast<int64_t>(ohi) << 32) | static_cast<uint32_t>(olo));
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_argmax_step(float& v, int& i) {
+  const int ob = __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xf, false);
+  const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, ROW_MASK, 0xf, false);
+  const float ov = __int_as_float(ob);
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void wave_argmax(T& v, int& i) {
+  dpp_argmax_step<0xB1, 0xf>(v, i);   // quad_perm [1,0,3,2]
+  dpp_argmax_step<0x4E, 0xf>(v, i);   // quad_perm [2,3,0,1]
+  dpp_argmax_step<0x141, 0xf>(v, i);  // row_half_mirror
+  dpp_argmax_step<0x140, 0xf>(v, i);  // row_mirror
+  dpp_argmax_step<0x142, 0xa>(v, i);  // row_bcast:15 into rows 1 and 3
+  dpp_argmax_step<0x143, 0xc>(v, i);  // row_bcast:31 into rows 2 and 3
+  // lane 63 now holds the wave's winner
+  if constexpr (sizeof(T) == 8) {
+    const int64_t bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(bits & 0xffffffff), 63);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(bits >> 32), 63);
+    v = __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+  } else {
+    v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+  }
+  i = __builtin_amdgcn_readlane(i, 63);
+}
+
+// ---------------------------------------------------------------------------
+// Panel LU with partial pivoting.  Rows j..b-1, columns j..j+w-1 of one
+// matrix live in registers: thread t owns panel rows t + NT q (q < R).  For
+// every column: each wave finds its best row (largest magnitude, lowest
+// index on ties) with DPP, its owner publishes the row in LDS, and the owner
+// of the current row C publishes that row too; after one barrier every
+// thread picks the global winner p, the rows C and p are exchanged, and the
+// multipliers and the rank-1 update of the panel follow.  LDS buffers
+// alternate between even and odd columns, so one barrier per column
+// suffices.  The composite row movement is recorded as (dest, src) pairs for
+// k_laswp_trsm, and the running permutation of the matrix is composed in
+// it.perm.  Columns are unrolled at compile time (panel_step<C>).
+// ---------------------------------------------------------------------------
+template <typename T, int NB, int NW>
 struct PanelShared {
-  T rowp[NB], rowc[NB];
-  int origp, origc;
-  T redv[8];
-  int redi[8];
+  T cand[2][NW][NB];  // each wave's candidate row
+  T candv[2][NW];
+  int candi[2][NW];
+  int cando[2][NW];   // original position of the candidate row
+  T rowc[2][NB];      // the current row C
+  int origc[2];
   int cnt;
 };
 
-template <typename T, int NB, int R, int C>
-__device__ __forceinline__ void panel_step(T (&a)[R][NB], int (&orig)[R], PanelShared<T, NB>& sh, int h, int w,
-                                           int tid, int32_t* info, int node) {
-  constexpr int NT = 512;
-  if (C >= w) return;
+// One column step for column C (a runtime value).  Register rows are only
+// indexed statically: the pivot column is extracted and written back with
+// predicated selects, which keeps one compact copy of the step in the
+// instruction cache instead of NB unrolled copies.
+template <typename T, int NB, int R, int NT>
+__device__ __forceinline__ void panel_step(T (&a)[R][NB], int (&orig)[R], PanelShared<T, NB, NT / 64>& sh, int C,
+                                           int h, int tid, int32_t* info, int node) {
+  constexpr int NW = NT / 64;
+  const int P = C & 1;
   const int lane = tid & 63, wave = tid >> 6;
+  // Columns are grouped in quarters of NB/4; only the quarter holding C is
+  // searched for the pivot column and quarters left of C are not updated.
+  constexpr int QW = NB >= 8 ? NB / 4 : NB;
+  constexpr int NQ = NB / QW;
+  T colv[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) colv[q] = T(0);
+#pragma unroll
+  for (int qq = 0; qq < NQ; ++qq) {
+    if (C / QW != qq) continue;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+#pragma unroll
+      for (int t = 0; t < QW; ++t) colv[q] = (qq * QW + t == C) ? a[q][qq * QW + t] : colv[q];
+    }
+  }
   T best = T(-1);
   int bi = INT_MAX;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int lr = tid + q * NT;
     if (lr >= C && lr < h) {
-      const T v = fabs(a[q][C]);
+      const T v = fabs(colv[q]);
       if (v > best) {
         best = v;
         bi = lr;
       }
     }
   }
+  wave_argmax(best, bi);
+  // Publish the wave's candidate row and the current row C.
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const T ov = __shfl_xor(best, off);
-    const int oi = __shfl_xor(bi, off);
-    if (ov > best || (ov == best && oi < bi)) {
-      best = ov;
-      bi = oi;
+  for (int q = 0; q < R; ++q) {
+    const int lr = tid + q * NT;
+    if (lr == bi) {
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc) sh.cand[P][wave][cc] = a[q][cc];
+      sh.cando[P][wave] = orig[q];
     }
   }
   if (lane == 0) {
-    sh.redv[wave] = best;
-    sh.redi[wave] = bi;
+    sh.candv[P][wave] = best;
+    sh.candi[P][wave] = bi;
+  }
+  if (tid == C) {  // row C is owned by thread C (C < NB <= NT), slot q = 0
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) sh.rowc[P][cc] = a[0][cc];
+    sh.origc[P] = orig[0];
   }
   __syncthreads();
-  best = sh.redv[0];
-  bi = sh.redi[0];
+  int ww = 0;
+  best = sh.candv[P][0];
+  bi = sh.candi[P][0];
 #pragma unroll
-  for (int wv = 1; wv < NT / 64; ++wv) {
-    const T ov = sh.redv[wv];
-    const int oi = sh.redi[wv];
+  for (int wv = 1; wv < NW; ++wv) {
+    const T ov = sh.candv[P][wv];
+    const int oi = sh.candi[P][wv];
     if (ov > best || (ov == best && oi < bi)) {
       best = ov;
       bi = oi;
+      ww = wv;
     }
   }
-  const int p = (bi == INT_MAX) ? C : bi;  // an all-NaN column keeps its row
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int lr = tid + q * NT;
-    if (lr == p) {
-#pragma unroll
-      for (int cc = C; cc < NB; ++cc) sh.rowp[cc] = a[q][cc];
-      sh.origp = orig[q];
-    }
-    if (lr == C) {
-#pragma unroll
-      for (int cc = 0; cc < NB; ++cc) sh.rowc[cc] = a[q][cc];
-      sh.origc = orig[q];
-    }
-  }
-  // The pivot row's multipliers (columns < C) must travel with it as well.
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int lr = tid + q * NT;
-    if (lr == p) {
-#pragma unroll
-      for (int cc = 0; cc < C; ++cc) sh.rowp[cc] = a[q][cc];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int lr = tid + q * NT;
-    if (lr == C) {
-#pragma unroll
-      for (int cc = 0; cc < NB; ++cc) a[q][cc] = sh.rowp[cc];
-      orig[q] = sh.origp;
-    } else if (lr == p) {
-#pragma unroll
-      for (int cc = 0; cc < NB; ++cc) a[q][cc] = sh.rowc[cc];
-      orig[q] = sh.origc;
-    }
-  }
-  const T piv = sh.rowp[C];
+  const bool none = bi == INT_MAX;  // an all-NaN column keeps its row
+  const int p = none ? C : bi;
+  const T* prow = none ? sh.rowc[P] : sh.cand[P][ww];
+  const T piv = prow[C];
   if (!(piv != T(0) && isfinite(piv)) && tid == 0 && info) atomicCAS(info, 0, node + 1);
-  if (piv != T(0)) {
-    const T rinv = T(1) / piv;
-    T l[R];
+  const T rinv = piv != T(0) ? T(1) / piv : T(0);
+  T l[R];
+  // Row C takes the pivot row (thread C, slot 0); row p takes row C.
+  if (p != C) {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int lr = tid + q * NT;
-      const bool below = lr > C && lr < h;
-      l[q] = below ? a[q][C] * rinv : T(0);
-      if (below) a[q][C] = l[q];
-    }
+      if (lr == p) {
 #pragma unroll
-    for (int cc = C + 1; cc < NB; ++cc) {
-      const T pv = sh.rowp[cc];
-#pragma unroll
-      for (int q = 0; q < R; ++q) a[q][cc] -= l[q] * pv;
+        for (int cc = 0; cc < NB; ++cc) a[q][cc] = sh.rowc[P][cc];
+        orig[q] = sh.origc[P];
+        colv[q] = sh.rowc[P][C];
+      }
     }
   }
-  __syncthreads();
-}
-
-template <typename T, int NB, int R, int... Cs>
-__device__ __forceinline__ void panel_all(std::integer_sequence<int, Cs...>, T (&a)[R][NB], int (&orig)[R],
-                                          PanelShared<T, NB>& sh, int h, int w, int tid, int32_t* info, int node) {
-  (panel_step<T, NB, R, Cs>(a, orig, sh, h, w, tid, info, node), ...);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int lr = tid + q * NT;
+    const bool below = lr > C && lr < h;
+    l[q] = below ? colv[q] * rinv : T(0);
+  }
+  if (tid == C) orig[0] = none ? sh.origc[P] : sh.cando[P][ww];
+  // Rank-1 update by quarters; the pivot row is read from LDS once per
+  // quarter (one batch of reads) and quarters left of C are skipped.
+#pragma unroll
+  for (int qq = 0; qq < NQ; ++qq) {
+    if (C >= (qq + 1) * QW) continue;
+    T pr[QW];
+#pragma unroll
+    for (int t = 0; t < QW; ++t) pr[t] = prow[qq * QW + t];
+#pragma unroll
+    for (int t = 0; t < QW; ++t) {
+      const int cc = qq * QW + t;
+      if (tid == C) a[0][cc] = pr[t];
+      const T pv = cc > C ? pr[t] : T(0);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        a[q][cc] -= l[q] * pv;
+        if (cc == C && l[q] != T(0)) a[q][cc] = l[q];
+      }
+    }
+  }
+  if (tid == C) {
+    // columns of the pivot row in finished quarters (its multipliers)
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) {
+      if (C < (qq + 1) * QW) continue;
+#pragma unroll
+      for (int t = 0; t < QW; ++t) a[0][qq * QW + t] = prow[qq * QW + t];
+    }
+  }
 }
 
 template <typename T, int NB, int R>
@@ -460,7 +611,7 @@ __global__ __launch_bounds__(512) void k_getf2(const LuItem* items, int j, int32
   T* A = static_cast<T*>(it.a);
   const int b = it.b, h = b - j, w = min(NB, h);
   const int tid = threadIdx.x;
-  __shared__ PanelShared<T, NB> sh;
+  __shared__ PanelShared<T, NB, NT / 64> sh;
 
   T a[R][NB];
   int orig[R];
@@ -473,7 +624,8 @@ __global__ __launch_bounds__(512) void k_getf2(const LuItem* items, int j, int32
       a[q][c] = (lr < h && c < w) ? A[static_cast<int64_t>(j + lr) * b + j + c] : T(0);
   }
   if (tid == 0) sh.cnt = 0;
-  panel_all<T, NB, R>(std::make_integer_sequence<int, NB>{}, a, orig, sh, h, w, tid, info, it.node);
+  for (int C = 0; C < w; ++C) panel_step<T, NB, R, NT>(a, orig, sh, C, h, tid, info, it.node);
+  __syncthreads();
 
   // Write the factored panel back and record the moved rows.
 #pragma unroll
@@ -503,6 +655,223 @@ __global__ __launch_bounds__(512) void k_getf2(const LuItem* items, int j, int32
     if (lr < h) it.perm[j + lr] = pv[q];
   }
   if (tid == 0) it.swaps[0] = sh.cnt;
+}
+
+// ---------------------------------------------------------------------------
+// Tile-local pivoting LU, step t0: factor the kTile x kTile diagonal tile in
+// one wavefront (no barriers between columns).  Lane l holds row l % 32 and
+// columns 16 (l / 32) .. 16 (l / 32) + 15 of the tile.  For every column the
+// pivot is the row of largest magnitude among the tile rows at or below it
+// (lowest index on ties); rows move only inside the tile's row band.  The
+// tile's row movement goes to it.swaps[1 + r] (tile row r came from tile row
+// swaps[1 + r]), the matrix permutation is composed in it.perm, and the
+// inverses of the tile's unit-lower L and upper U go to it.aux (L^{-1} first,
+// then U^{-1}, kTile x kTile each, row-major).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void wave32_argmax(T& v, int& i) {
+  dpp_argmax_step<0xB1, 0xf>(v, i);   // quad_perm [1,0,3,2]
+  dpp_argmax_step<0x4E, 0xf>(v, i);   // quad_perm [2,3,0,1]
+  dpp_argmax_step<0x141, 0xf>(v, i);  // row_half_mirror
+  dpp_argmax_step<0x140, 0xf>(v, i);  // row_mirror
+  dpp_argmax_step<0x142, 0xa>(v, i);  // row_bcast:15: lanes 31 and 63 hold their half's winner
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void tile_step(T (&a)[16], int& orig, T (&sP)[kTile][kTile + 1], int r, int half, int ts,
+                                          int32_t* info, int node) {
+  constexpr int hc = C / 16, ic = C % 16;
+  if (C >= ts) return;
+  T v = (half == hc && r >= C && r < ts) ? fabs(a[ic]) : T(-1);
+  int idx = r;
+  wave32_argmax(v, idx);
+  int p;
+  T pv;
+  if constexpr (sizeof(T) == 8) {
+    const int64_t bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(bits & 0xffffffff), hc ? 63 : 31);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(bits >> 32), hc ? 63 : 31);
+    pv = __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+  } else {
+    pv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), hc ? 63 : 31));
+  }
+  p = __builtin_amdgcn_readlane(idx, hc ? 63 : 31);
+  if (!(pv >= T(0))) p = C;  // no candidate (NaN column): keep the row
+  if (p != C) {
+    const int src = (r == C) ? p : (r == p ? C : r);
+    const int srcl = src + 32 * half;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) a[t] = __shfl(a[t], srcl);
+    orig = __shfl(orig, srcl);
+  }
+  if (r == C) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) sP[C][16 * half + t] = a[t];
+  }
+  __syncthreads();  // single wavefront: orders the LDS row write before the reads
+  const T piv = sP[C][C];
+  if (!(piv != T(0) && isfinite(piv)) && r == 0 && half == 0 && info) atomicCAS(info, 0, node + 1);
+  const T rinv = piv != T(0) ? T(1) / piv : T(0);
+  const T own = (half == hc) ? a[ic] : T(0);
+  const T lrow = __shfl(own, r + 32 * hc);
+  const T lm = (r > C && r < ts) ? lrow * rinv : T(0);
+  if (half == hc && r > C && r < ts) a[ic] = lm;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int col = 16 * half + t;
+    const T u = col > C ? sP[C][col] : T(0);
+    a[t] -= lm * u;
+  }
+}
+
+template <typename T, int... Cs>
+__device__ __forceinline__ void tile_all(std::integer_sequence<int, Cs...>, T (&a)[16], int& orig,
+                                         T (&sP)[kTile][kTile + 1], int r, int half, int ts, int32_t* info, int node) {
+  (tile_step<T, Cs>(a, orig, sP, r, half, ts, info, node), ...);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0, int32_t* info) {
+  const LuItem it = items[blockIdx.x];
+  T* A = static_cast<T*>(it.a);
+  const int b = it.b, ts = min(kTile, b - t0);
+  const int l = threadIdx.x, r = l & 31, half = l >> 5;
+  __shared__ T sP[kTile][kTile + 1];
+  T a[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int c = 16 * half + t;
+    a[t] = (r < ts && c < ts) ? A[static_cast<int64_t>(t0 + r) * b + t0 + c] : (r == c ? T(1) : T(0));
+  }
+  int orig = r;
+  tile_all<T>(std::make_integer_sequence<int, kTile>{}, a, orig, sP, r, half, ts, info, it.node);
+  // Factored tile back to the matrix and to LDS.
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int c = 16 * half + t;
+    if (r < ts && c < ts) A[static_cast<int64_t>(t0 + r) * b + t0 + c] = a[t];
+    sP[r][c] = a[t];
+  }
+  // Row movement of the tile.  Rows never leave their band, so the band's
+  // entries of the permutation are t0 + (tile row of origin).
+  __syncthreads();
+  if (half == 0 && r < ts) {
+    it.swaps[1 + r] = orig;
+    it.perm[t0 + r] = t0 + orig;
+  }
+  // Inverses of the unit-lower L (lanes 0..31, column r) and of U (lanes
+  // 32..63, column r) of the tile, by substitution with the solution column
+  // in registers.  The fence after each row keeps the row's LDS reads next
+  // to their use (otherwise all kTile^2 reads are hoisted and spill).
+  T x[kTile];
+  if (half == 0) {
+#pragma unroll
+    for (int i = 0; i < kTile; ++i) {
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int q = 0; q < i; q += 2) {
+        s0 += sP[i][q] * x[q];
+        if (q + 1 < i) s1 += sP[i][q + 1] * x[q + 1];
+      }
+      x[i] = (i == r) ? T(1) : -(s0 + s1);  // zero above the diagonal follows from x[q] = 0, q < r
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+  } else {
+#pragma unroll
+    for (int i = kTile - 1; i >= 0; --i) {
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int q = i + 1; q < kTile; q += 2) {
+        s0 += sP[i][q] * x[q];
+        if (q + 1 < kTile) s1 += sP[i][q + 1] * x[q + 1];
+      }
+      x[i] = (i > r) ? T(0) : (((i == r) ? T(1) : T(0)) - (s0 + s1)) / sP[i][i];
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+  }
+  T* aux = static_cast<T*>(it.aux) + half * kTile * kTile;
+#pragma unroll
+  for (int i = 0; i < kTile; ++i) aux[i * kTile + r] = x[i];
+}
+
+// ---------------------------------------------------------------------------
+// Strip update of tile step t0 (after k_tile_lu), 256 threads per block:
+//   right blocks : rows of the tile band, 64 columns right of the tile:
+//                  U12 = L_tt^{-1} (P_tt A12);
+//   left blocks  : rows of the band, 64 columns left of the tile: P_tt A;
+//   lower blocks : 64 rows below the tile, the tile's columns:
+//                  L21 = A21 U_tt^{-1}.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_tile_strips(const LuItem* items, int t0) {
+  const LuItem it = items[blockIdx.y];
+  T* A = static_cast<T*>(it.a);
+  const int b = it.b, ts = min(kTile, b - t0), tid = threadIdx.x;
+  const int rest = b - t0 - ts;
+  const int nR = (rest + 63) / 64, nL = (t0 + 63) / 64, nC = nR;
+  const int blk = blockIdx.x;
+  if (blk >= nR + nL + nC) return;
+  __shared__ T sInv[kTile][kTile + 1];
+  __shared__ T sX[64][kTile + 1];  // band: sX[c][q] = band row q, column c; below: sX[r][q]
+  __shared__ int sOrig[kTile];
+  if (tid < kTile) sOrig[tid] = tid < ts ? it.swaps[1 + tid] : tid;
+  const bool band = blk < nR + nL;
+  const bool right = blk < nR;
+  if (right || !band) {
+    const T* inv = static_cast<const T*>(it.aux) + (band ? 0 : kTile * kTile);
+    for (int e = tid; e < kTile * kTile; e += 256) sInv[e / kTile][e % kTile] = inv[e];
+  }
+  __syncthreads();
+  if (band) {
+    const int c0 = right ? t0 + ts + 64 * blk : 64 * (blk - nR);
+    const int cw = right ? min(64, b - c0) : min(64, t0 - c0);
+    // band rows in their new order (row q of the band is old row sOrig[q])
+    for (int e = tid; e < kTile * 64; e += 256) {
+      const int q = e >> 6, c = e & 63;
+      sX[c][q] = (c < cw && q < ts) ? A[static_cast<int64_t>(t0 + sOrig[q]) * b + c0 + c] : T(0);
+    }
+    __syncthreads();
+    const int c = tid & 63, rg = tid >> 6;  // column c, band rows 8 rg .. 8 rg + 7
+    T y[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) y[i] = right ? T(0) : sX[c][8 * rg + i];
+    if (right) {
+      // U12 = L_tt^{-1} (P_tt A12): runtime loop over the 32-term products
+      for (int q = 0; q < ts; ++q) {
+        const T xq = sX[c][q];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) y[i] += sInv[8 * rg + i][q] * xq;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int row = 8 * rg + i;
+      if (c < cw && row < ts) A[static_cast<int64_t>(t0 + row) * b + c0 + c] = y[i];
+    }
+  } else {
+    const int r0 = t0 + ts + 64 * (blk - nR - nL);
+    const int rw = min(64, b - r0);
+    for (int e = tid; e < 64 * kTile; e += 256) {
+      const int r = e >> 5, q = e & 31;
+      sX[r][q] = (r < rw && q < ts) ? A[static_cast<int64_t>(r0 + r) * b + t0 + q] : T(0);
+    }
+    __syncthreads();
+    const int r = tid >> 2, cg = tid & 3;  // row r, tile columns 8 cg .. 8 cg + 7
+    T y[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) y[i] = T(0);
+    // L21 = A21 U_tt^{-1}
+    for (int q = 0; q < ts; ++q) {
+      const T xq = sX[r][q];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) y[i] += xq * sInv[q][8 * cg + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int col = 8 * cg + i;
+      if (r < rw && col < ts) A[static_cast<int64_t>(r0 + r) * b + t0 + col] = y[i];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -539,15 +908,23 @@ __global__ __launch_bounds__(128) void k_laswp_trsm(const LuItem* items, int j, 
     for (int q = 0; q < cnt; ++q) A[static_cast<int64_t>(s_dst[q]) * b + col] = s_rows[q][tid];
   }
   if (mine && col >= j + w) {
-    // Forward substitution with the unit-lower L11; column tid of s_rows is
-    // this thread's private workspace.
-    for (int r = 0; r < w; ++r) s_rows[r][tid] = A[static_cast<int64_t>(j + r) * b + col];
-    for (int r = 1; r < w; ++r) {
-      T acc = s_rows[r][tid];
-      for (int q = 0; q < r; ++q) acc -= s_L[r][q] * s_rows[q][tid];
-      s_rows[r][tid] = acc;
+    // Forward substitution with the unit-lower L11, column-oriented: after
+    // x[s] is final, x[r] -= L[r][s] x[s] for r > s.  Register indices are
+    // static (predicated), the column loop is a runtime loop.
+    T x[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) x[r] = (r < w) ? A[static_cast<int64_t>(j + r) * b + col] : T(0);
+    for (int s2 = 0; s2 + 1 < w; ++s2) {
+      T xs = T(0);
+#pragma unroll
+      for (int r = 0; r < NB; ++r) xs = (r == s2) ? x[r] : xs;
+#pragma unroll
+      for (int r = 0; r < NB; ++r)
+        if (r > s2) x[r] -= s_L[r][s2] * xs;
     }
-    for (int r = 0; r < w; ++r) A[static_cast<int64_t>(j + r) * b + col] = s_rows[r][tid];
+#pragma unroll
+    for (int r = 0; r < NB; ++r)
+      if (r < w) A[static_cast<int64_t>(j + r) * b + col] = x[r];
   }
 }
 
@@ -618,15 +995,16 @@ namespace {
 inline int cdiv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 }  // namespace
 
-template <typename T, int MODE>
-hipError_t launch_gemm_mode(const GemmLaunch& L, int max_m, int max_n, hipStream_t st) {
-  const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * L.count;
+template <typename T, int MODE, bool GEN>
+hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * count;
   if (big_tiles >= 256) {
-    dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), L.count);
-    hipLaunchKernelGGL((k_gemm<T, MODE, 128, 128, 16, 64, 64>), grid, dim3(256), 0, st, L);
+    dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), count);
+    hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 128, 16, 64, 64>), grid, dim3(256), 0, st, L);
   } else {
-    dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), L.count);
-    hipLaunchKernelGGL((k_gemm<T, MODE, 64, 64, 16, 32, 32>), grid, dim3(256), 0, st, L);
+    dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), count);
+    hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 64, 64, 16, 32, 32>), grid, dim3(256), 0, st, L);
   }
   return hipGetLastError();
 }
@@ -635,15 +1013,47 @@ template <typename T>
 hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st) {
   if (L.count <= 0 || max_m <= 0 || max_n <= 0) return hipSuccess;
   switch (L.mode) {
-    case GEMM_EXPLICIT:
-      return launch_gemm_mode<T, GEMM_EXPLICIT>(L, max_m, max_n, st);
+    case GEMM_EXPLICIT: {
+      // items [0, L.w) take the fast instance, [L.w, L.count) the generic one
+      // (GemmLaunch::w carries the split; the generic instance offsets its
+      // item index by GemmLaunch::j = L.w).
+      const int nfast = L.w;
+      hipError_t e = launch_gemm_mode<T, GEMM_EXPLICIT, false>(L, nfast, max_m, max_n, st);
+      if (e != hipSuccess) return e;
+      GemmLaunch G = L;
+      G.j = nfast;
+      return launch_gemm_mode<T, GEMM_EXPLICIT, true>(G, L.count - nfast, max_m, max_n, st);
+    }
     case GEMM_LU_TRAILING:
-      return launch_gemm_mode<T, GEMM_LU_TRAILING>(L, max_m, max_n, st);
+      return launch_gemm_mode<T, GEMM_LU_TRAILING, false>(L, L.count, max_m, max_n, st);
     case GEMM_TRTRI_STEP1:
-      return launch_gemm_mode<T, GEMM_TRTRI_STEP1>(L, max_m, max_n, st);
+      return launch_gemm_mode<T, GEMM_TRTRI_STEP1, false>(L, L.count, max_m, max_n, st);
     default:
-      return launch_gemm_mode<T, GEMM_TRTRI_STEP2>(L, max_m, max_n, st);
+      return launch_gemm_mode<T, GEMM_TRTRI_STEP2, false>(L, L.count, max_m, max_n, st);
   }
+}
+
+template <typename T>
+hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, int32_t* info, hipStream_t st) {
+  for (int t0 = 0; t0 < b; t0 += kTile) {
+    const int ts = std::min(kTile, b - t0);
+    hipLaunchKernelGGL((k_tile_lu<T>), dim3(count), dim3(64), 0, st, d_items, t0, info);
+    const int rest = b - t0 - ts;
+    const int nblk = 2 * cdiv(rest, 64) + cdiv(t0, 64);
+    if (nblk > 0) hipLaunchKernelGGL((k_tile_strips<T>), dim3(nblk, count), dim3(256), 0, st, d_items, t0);
+    if (rest > 0) {
+      GemmLaunch L{};
+      L.mode = GEMM_LU_TRAILING;
+      L.elem = sizeof(T);
+      L.items = d_items;
+      L.count = count;
+      L.j = t0;
+      L.w = ts;
+      hipError_t e = launch_gemm<T>(L, rest, rest, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -724,6 +1134,8 @@ hipError_t launch_fill_int(int32_t* p, int n, int v, hipStream_t st) {
 template hipError_t launch_gemm<double>(const GemmLaunch&, int, int, hipStream_t);
 template hipError_t launch_gemm<float>(const GemmLaunch&, int, int, hipStream_t);
 template hipError_t launch_getrf<double>(const LuItem*, int, int, int32_t*, hipStream_t);
+template hipError_t launch_getrf_tile<double>(const LuItem*, int, int, int32_t*, hipStream_t);
+template hipError_t launch_getrf_tile<float>(const LuItem*, int, int, int32_t*, hipStream_t);
 template hipError_t launch_getrf<float>(const LuItem*, int, int, int32_t*, hipStream_t);
 template hipError_t launch_trtri<double>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_trtri<float>(const LuItem*, int, int, hipStream_t);

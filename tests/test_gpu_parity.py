@@ -29,10 +29,11 @@ def gpu(m, dtype=torch.float64):
     return torch.from_numpy(np.ascontiguousarray(m)).to(DEV, dtype)
 
 
-def run(m, k, i, j, precision="f64", concurrency=0):
+def run(m, k, i, j, precision="f64", concurrency=0, pivoting="tile"):
     dtype = torch.float64 if precision == "f64" else torch.float32
     info = torch.zeros(1, dtype=torch.int32, device=DEV)
-    out = bri.invert_block(gpu(m, dtype), k, i, j, precision=precision, concurrency=concurrency, info=info)
+    out = bri.invert_block(gpu(m, dtype), k, i, j, precision=precision, concurrency=concurrency, info=info,
+                           pivoting=pivoting)
     torch.cuda.synchronize()
     assert int(info.item()) == 0
     return out.double().cpu().numpy()
@@ -56,11 +57,12 @@ def test_small_fp64_all_blocks(n, k):
 
 
 @pytest.mark.parametrize("W", [1, 4, 16, 64])
-def test_concurrency_widths_agree(W):
+@pytest.mark.parametrize("pivoting", ["tile", "panel"])
+def test_concurrency_widths_agree(W, pivoting):
     n, k = 300, 5
     m = workloads.haar_spd(n, 77, 0.0, 2.0).m
     for (i, j) in [(0, 0), (3, 1)]:
-        got = run(m, k, i, j, concurrency=W)
+        got = run(m, k, i, j, concurrency=W, pivoting=pivoting)
         assert rel(got, oracle.invert_block(m, k, i, j)) < 1e-12
 
 
@@ -73,16 +75,22 @@ def test_ragged_blocks_and_tiles(n, k):
         assert rel(got, oracle.invert_block(m, k, i, j)) < 1e-12
 
 
-def test_general_gaussian_matrix_pivots():
+@pytest.mark.parametrize("pivoting", ["panel", "tile"])
+def test_general_gaussian_matrix_pivots(pivoting):
     # Plain N(0,1) entries (the paper's randn matrices): pivoting matters.
+    # Full-height partial pivoting is held to a backward-stable bound; tile
+    # pivoting (pivot search inside 32-row tiles) gets a looser one.
     n, k = 192, 3
     m = workloads.gaussian(n, 5)
     inv = np.linalg.inv(m)
     cond = np.linalg.cond(m)
     b = n // k
+    bound = 1e-14 * cond * 10 if pivoting == "panel" else 1e-11 * cond
     for (i, j) in [(0, 0), (2, 1)]:
-        got = run(m, k, i, j)
-        assert rel(got, inv[i * b:(i + 1) * b, j * b:(j + 1) * b]) < 1e-14 * cond * 10
+        got = run(m, k, i, j, pivoting=pivoting)
+        err = rel(got, inv[i * b:(i + 1) * b, j * b:(j + 1) * b])
+        print(f"randn n={n} k={k} ({i},{j}) {pivoting}: rel err {err:.2e} (cond {cond:.1e})", flush=True)
+        assert err < bound
 
 
 def test_fp32_small():
@@ -99,10 +107,11 @@ def test_config_n256_k2_fp64():
     assert rel(got, oracle.invert_block(m, 2, 0, 0)) < 1e-12
 
 
+@pytest.mark.parametrize("pivoting", ["tile", "panel"])
 @pytest.mark.parametrize("i,j", [(0, 0), (1, 2)])
-def test_config_n4096_k4_fp64(i, j):
+def test_config_n4096_k4_fp64(i, j, pivoting):
     m = workloads.workload_matrix("spd_n4096_k4")
-    got = run(m, 4, i, j)
+    got = run(m, 4, i, j, pivoting=pivoting)
     want = oracle.invert_block(m, 4, i, j)
     assert rel(got, want) < 1e-12
 

@@ -178,6 +178,15 @@ int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_pla
 int64_t bri_plan_dump(int64_t n, int k, int i, int j, const bri_opts* o, int64_t* words,
                       int64_t cap);
 
+/* The two plans of the mixed-precision refinement for block column j
+ * (which = 0: the float block column plan that keeps its pivots; 1: the
+ * correction solve X = Gamma^{-1} R, with R as operand kind 5 "rhs block a";
+ * 2: the k slots holding the kept pivots, by elimination position), in the
+ * format of bri_plan_dump.  Host only; returns the number of words needed or
+ * < 0 on bad arguments. */
+int64_t bri_refine_plan_dump(int64_t n, int k, int j, int which, const bri_opts* o, int64_t* words,
+                             int64_t cap);
+
 /* Step timing, a profiling aid.  While enabled, every plan step that
  * invert_block / bri_block_column enqueue is bracketed by two HIP events on
  * the caller's stream.  bri_profile_read() waits for those events and writes,

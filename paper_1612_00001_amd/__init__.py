@@ -99,6 +99,9 @@ _SIGNATURES = [
     ("bri_plan_dump", ctypes.c_int64,
      [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BriOpts),
       ctypes.POINTER(ctypes.c_int64), ctypes.c_int64]),
+    ("bri_refine_plan_dump", ctypes.c_int64,
+     [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BriOpts),
+      ctypes.POINTER(ctypes.c_int64), ctypes.c_int64]),
     ("bri_gemm_workspace_size", ctypes.c_size_t, [ctypes.c_int]),
     ("bri_gemm", ctypes.c_int,
      [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
@@ -175,15 +178,7 @@ def plan_describe(n: int, k: int, i: int, j: int, precision: str = "f64", concur
     return {f: getattr(s, f) for f, _ in BriPlanStats._fields_}
 
 
-def plan_dump(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0) -> List[tuple]:
-    """Host-only list of plan steps: [(kind, [items...])], item = (dst, x, y, cin, sub, node)."""
-    o = make_opts(precision, concurrency)
-    need = lib().bri_plan_dump(n, k, i, j, ctypes.byref(o), None, 0)
-    if need < 0:
-        raise BriError(int(need), status_string(int(need)))
-    buf = (ctypes.c_int64 * need)()
-    lib().bri_plan_dump(n, k, i, j, ctypes.byref(o), buf, need)
-    words = list(buf)
+def _decode_steps(words: List[int]) -> List[tuple]:
     steps, pos = [], 0
     while pos < len(words):
         kind, count = words[pos], words[pos + 1]
@@ -195,6 +190,31 @@ def plan_dump(n: int, k: int, i: int, j: int, precision: str = "f64", concurrenc
             items.append((tuple(w[0:3]), tuple(w[3:6]), tuple(w[6:9]), tuple(w[9:12]), tuple(w[12:15]), w[15]))
         steps.append((kind, items))
     return steps
+
+
+def plan_dump(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0) -> List[tuple]:
+    """Host-only list of plan steps: [(kind, [items...])], item = (dst, x, y, cin, sub, node)."""
+    o = make_opts(precision, concurrency)
+    need = lib().bri_plan_dump(n, k, i, j, ctypes.byref(o), None, 0)
+    if need < 0:
+        raise BriError(int(need), status_string(int(need)))
+    buf = (ctypes.c_int64 * need)()
+    lib().bri_plan_dump(n, k, i, j, ctypes.byref(o), buf, need)
+    return _decode_steps(list(buf))
+
+
+def refine_plan_dump(n: int, k: int, j: int, which: str, concurrency: int = 0):
+    """Host-only plans of the mixed-precision refinement: which = "column"
+    (float block column, keeps its pivots), "solve" (correction solve with the
+    right-hand side as operand kind 5) or "kept" (pivot slot per position)."""
+    w = {"column": 0, "solve": 1, "kept": 2}[which]
+    o = make_opts("mixed_f32", concurrency)
+    need = lib().bri_refine_plan_dump(n, k, j, w, ctypes.byref(o), None, 0)
+    if need < 0:
+        raise BriError(int(need), status_string(int(need)))
+    buf = (ctypes.c_int64 * max(need, 1))()
+    lib().bri_refine_plan_dump(n, k, j, w, ctypes.byref(o), buf, need)
+    return list(buf)[:need] if which == "kept" else _decode_steps(list(buf)[:need])
 
 
 def workspace_size(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0) -> int:
@@ -315,13 +335,21 @@ def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Seq
 
 
 def gemm(A: Sequence[torch.Tensor], B: Sequence[torch.Tensor], C: Sequence[torch.Tensor],
-         alpha: float = 1.0, beta: float = 0.0, workspace: Optional[torch.Tensor] = None) -> None:
-    """C[t] = beta C[t] + alpha A[t] B[t] on the library's MFMA product kernel (in place on C)."""
+         alpha: float = 1.0, beta: float = 0.0, workspace: Optional[torch.Tensor] = None,
+         products: Optional[str] = None) -> None:
+    """C[t] = beta C[t] + alpha A[t] B[t] on the library's MFMA product kernel (in place on C).
+
+    ``products`` (float operands only): None or "f32" for FP32 MFMA, "f16" or
+    "bf16" for the split low-precision MFMA products of the mixed paths."""
     count = len(A)
     if count == 0:
         return
     dtype = A[0].dtype
     prec = "f64" if dtype == torch.float64 else "f32"
+    if products in ("f16", "bf16"):
+        if dtype != torch.float32:
+            raise TypeError("split low-precision products take float32 operands")
+        prec = "mixed_" + products
     for t in range(count):
         for nm, x in (("A", A[t]), ("B", B[t]), ("C", C[t])):
             _require_gpu(x, f"{nm}[{t}]", dtype)

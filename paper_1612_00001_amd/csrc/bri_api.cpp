@@ -20,6 +20,7 @@
 #include "../../include/bri.h"
 #include "bri_internal.h"
 #include "bri_kernels.h"
+#include "bri_refine.h"
 
 namespace bri {
 namespace {
@@ -149,6 +150,9 @@ struct Ctx {
   char* out = nullptr;
   int64_t ldo = 0;
   int32_t* info = nullptr;
+  char* rhs = nullptr;  // right-hand side of a solve plan (OPND_RHS), (k b) x b
+  int64_t ldr = 0;
+  int lp = 0;           // float products: 0 FP32 MFMA, 1 FP16 split, 2 BF16 split
 };
 
 DView zero_view() {
@@ -213,6 +217,13 @@ DView resolve(const Ctx& c, const Opnd& o) {
     case OPND_OUT:
       v.p = c.out + static_cast<int64_t>(o.a) * b * c.ldo * c.elem;
       v.ld = c.ldo;
+      v.rows = c.b;
+      v.cols = c.b;
+      return v;
+    case OPND_RHS:
+      if (!c.rhs) throw std::logic_error("solve plan without a right-hand side");
+      v.p = c.rhs + static_cast<int64_t>(o.a) * b * c.ldr * c.elem;
+      v.ld = c.ldr;
       v.rows = c.b;
       v.cols = c.b;
       return v;
@@ -412,6 +423,7 @@ int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
         L.items = d;
         L.count = count;
         L.w = c.lay->nfast[si];
+        L.lp = c.lp;
         e = launch_gemm<T>(L, c.b, c.b, st);
         break;
       }
@@ -453,6 +465,212 @@ int execute(CachedPlan& cp, Ctx& c, hipStream_t st, bool clear_info) {
 }
 
 bool plain_precision(int p) { return p == BRI_F64 || p == BRI_F32; }
+bool mixed_precision(int p) { return p == BRI_MIXED_F32 || p == BRI_MIXED_F16 || p == BRI_MIXED_BF16; }
+// Products of the float recursion: FP32 MFMA, or split FP16 / BF16 MFMA.
+int lp_of(int p) { return p == BRI_MIXED_F16 ? 1 : (p == BRI_MIXED_BF16 ? 2 : 0); }
+
+// ---------------------------------------------------------------------------
+// Mixed precision: block column by the float recursion, refined in FP64.
+// ---------------------------------------------------------------------------
+struct RefineCache {
+  std::shared_ptr<CachedPlan> col, sol;
+  std::vector<int> kept;
+  std::mutex mu;            // serialises calls that share the staging buffer
+  void* host = nullptr;     // pinned: descriptors of the residual product and the output copy, norms
+  hipEvent_t uploaded = nullptr;
+  ~RefineCache() {
+    if (uploaded) (void)hipEventDestroy(uploaded);
+    if (host) (void)hipHostFree(host);
+  }
+};
+
+typedef std::tuple<int64_t, int, int, int> RefineKey;  // n, k, j, width
+
+std::shared_ptr<RefineCache> get_refine(int64_t n, int k, int j, int width) {
+  static std::map<RefineKey, std::shared_ptr<RefineCache>> c;
+  RefineKey key(n, k, j, width);
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  auto itp = c.find(key);
+  if (itp != c.end()) return itp->second;
+  RefinePlans rp = make_refine_plans(n, k, j, width);
+  auto rc = std::make_shared<RefineCache>();
+  rc->col = std::make_shared<CachedPlan>();
+  rc->sol = std::make_shared<CachedPlan>();
+  rc->col->plan = std::move(rp.column);
+  rc->sol->plan = std::move(rp.solve);
+  rc->col->layout = make_layout(rc->col->plan, 4);
+  rc->sol->layout = make_layout(rc->sol->plan, 4);
+  rc->kept = rp.kept;
+  if (c.size() > 64) c.clear();
+  c[key] = rc;
+  return rc;
+}
+
+struct MixedLayout {
+  size_t g32 = 0, x64 = 0, r64 = 0, r32 = 0, d32 = 0, scal = 0, desc = 0, plans = 0, total = 0;
+};
+
+// Workspace of the mixed path: sigma Gamma in float, the FP64 iterate X and
+// residual R, their float images, device scalars, two descriptors and the
+// region of the float plans (shared by the column and the solve plan).
+MixedLayout mixed_layout(int64_t n, int k, const RefineCache& rc) {
+  MixedLayout L;
+  const size_t b = static_cast<size_t>((n + k - 1) / k);
+  const size_t kb = static_cast<size_t>(k) * b;
+  size_t off = 0;
+  L.g32 = off;
+  off += align_up(kb * kb * 4);
+  L.x64 = off;
+  off += align_up(kb * b * 8);
+  L.r64 = off;
+  off += align_up(kb * b * 8);
+  L.r32 = off;
+  off += align_up(kb * b * 4);
+  L.d32 = off;
+  off += align_up(kb * b * 4);
+  L.scal = off;
+  off += align_up(kRefineScalars * sizeof(double));
+  L.desc = off;
+  off += align_up(sizeof(GemmItem)) + align_up(sizeof(LoadItem));
+  L.plans = off;
+  off += std::max(rc.col->layout.total, rc.sol->layout.total);
+  L.total = off;
+  return L;
+}
+
+size_t mixed_workspace_size(int64_t n, int k, int j, int width) {
+  auto rc = get_refine(n, k, j, width);
+  return mixed_layout(n, k, *rc).total;
+}
+
+int invert_block_mixed(const void* M, int64_t n, int64_t ldm, int k, int i, int j, void* out, int64_t ldo,
+                       const bri_opts* o) {
+  const int w = resolve_width(n, k, o);
+  std::shared_ptr<RefineCache> rc;
+  try {
+    rc = get_refine(n, k, j, w);
+  } catch (const std::exception&) {
+    return BRI_ERR_UNSUPPORTED;
+  }
+  const MixedLayout ml = mixed_layout(n, k, *rc);
+  if (!o->workspace || o->workspace_bytes < ml.total) return BRI_ERR_WORKSPACE;
+  std::lock_guard<std::mutex> lk(rc->mu);
+  hipStream_t st = o->stream;
+  char* ws = static_cast<char*>(o->workspace);
+  const int b = rc->col->plan.b;
+  const int64_t kb = static_cast<int64_t>(k) * b;
+  const int64_t cnt = kb * b;
+  float* G = reinterpret_cast<float*>(ws + ml.g32);
+  double* X = reinterpret_cast<double*>(ws + ml.x64);
+  double* R = reinterpret_cast<double*>(ws + ml.r64);
+  float* R32 = reinterpret_cast<float*>(ws + ml.r32);
+  float* D = reinterpret_cast<float*>(ws + ml.d32);
+  double* scal = reinterpret_cast<double*>(ws + ml.scal);
+  char* desc = ws + ml.desc;
+  int32_t* info = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(ws + ml.plans + rc->col->layout.info_off);
+
+  // Descriptors: R[0:n) = -M X[0:n) (FP64) and the copy of block row i of X to out.
+  GemmItem g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = g.B = g.Cin = g.Sub = zero_view();
+  g.A.p = M;
+  g.A.ld = ldm;
+  g.A.rows = static_cast<int32_t>(n);
+  g.A.cols = static_cast<int32_t>(n);
+  g.B.p = X;
+  g.B.ld = b;
+  g.B.rows = static_cast<int32_t>(kb);
+  g.B.cols = b;
+  g.out = R;
+  g.ldo = b;
+  g.M = static_cast<int32_t>(n);
+  g.N = b;
+  g.K = static_cast<int32_t>(n);
+  g.alpha = -1.0;
+  LoadItem li;
+  std::memset(&li, 0, sizeof(li));
+  li.src = zero_view();
+  li.src.p = X + static_cast<int64_t>(i) * b * b;
+  li.src.ld = b;
+  li.src.rows = b;
+  li.src.cols = b;
+  li.dst = out;
+  li.ldd = ldo;
+  li.rows = b;
+  li.cols = b;
+  const size_t gbytes = align_up(sizeof(GemmItem));
+  const size_t hbytes = gbytes + align_up(sizeof(LoadItem)) + kRefineScalars * sizeof(double);
+  if (!rc->host) {
+    if (hipHostMalloc(&rc->host, hbytes) != hipSuccess) return BRI_ERR_HIP;
+    if (hipEventCreateWithFlags(&rc->uploaded, hipEventDisableTiming) != hipSuccess) return BRI_ERR_HIP;
+  } else if (hipEventSynchronize(rc->uploaded) != hipSuccess) {
+    return BRI_ERR_HIP;
+  }
+  char* host = static_cast<char*>(rc->host);
+  std::memcpy(host, &g, sizeof(g));
+  std::memcpy(host + gbytes, &li, sizeof(li));
+  double* hscal = reinterpret_cast<double*>(host + gbytes + align_up(sizeof(LoadItem)));
+  if (hipMemcpyAsync(desc, host, gbytes + sizeof(LoadItem), hipMemcpyHostToDevice, st) != hipSuccess)
+    return BRI_ERR_HIP;
+  if (hipEventRecord(rc->uploaded, st) != hipSuccess) return BRI_ERR_HIP;
+
+  // sigma Gamma in float, then X0 = sigma (sigma Gamma)^{-1} E_j by the float
+  // block column plan (which keeps its pivots for the correction solves).
+  if (launch_scal_clear(scal, 0, kRefineScalars, st) != hipSuccess) return BRI_ERR_HIP;
+  if (launch_absmax(M, 8, n, n, ldm, scal, st) != hipSuccess) return BRI_ERR_HIP;
+  if (launch_gamma_f32(static_cast<const double*>(M), n, ldm, kb, G, scal, st) != hipSuccess) return BRI_ERR_HIP;
+  Ctx c;
+  c.pivoting = o->pivoting;
+  c.M = reinterpret_cast<const char*>(G);
+  c.n = kb;
+  c.ldm = kb;
+  c.b = b;
+  c.elem = 4;
+  c.ws = ws + ml.plans;
+  c.out = reinterpret_cast<char*>(D);
+  c.ldo = b;
+  c.info = info;
+  c.rhs = reinterpret_cast<char*>(R32);
+  c.ldr = b;
+  c.lp = lp_of(o->precision);
+  int rcode = execute(*rc->col, c, st, true);
+  if (rcode != BRI_OK) return rcode;
+  if (launch_refine_update(X, D, cnt, scal, 1, st) != hipSuccess) return BRI_ERR_HIP;
+
+  // Sweeps: R = E_j - Gamma X (FP64), D = (sigma Gamma)^{-1} (s R) by the float
+  // solve plan, X += (sigma / s) D, until ||dX||_F <= tol ||X||_F.
+  bool converged = o->refine_max_iters <= 0;
+  const double tol = o->refine_tol;
+  for (int it = 0; it < o->refine_max_iters; ++it) {
+    if (launch_scal_clear(scal, 1, 4, st) != hipSuccess) return BRI_ERR_HIP;
+    GemmLaunch L{};
+    L.mode = GEMM_EXPLICIT;
+    L.elem = 8;
+    L.items = desc;
+    L.count = 1;
+    L.w = 1;  // stored dense operands
+    if (launch_gemm<double>(L, static_cast<int>(n), b, st) != hipSuccess) return BRI_ERR_HIP;
+    if (launch_resid_fix(R, X, n, kb, b, j, st) != hipSuccess) return BRI_ERR_HIP;
+    if (launch_absmax(R, 8, kb, b, b, scal + 1, st) != hipSuccess) return BRI_ERR_HIP;
+    if (launch_rhs_scale(R, R32, cnt, scal, st) != hipSuccess) return BRI_ERR_HIP;
+    rcode = execute(*rc->sol, c, st, false);
+    if (rcode != BRI_OK) return rcode;
+    if (launch_refine_update(X, D, cnt, scal, 0, st) != hipSuccess) return BRI_ERR_HIP;
+    if (hipMemcpyAsync(hscal, scal, kRefineScalars * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+      return BRI_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return BRI_ERR_HIP;
+    const double dd = hscal[2], xx = hscal[3];
+    if (!std::isfinite(dd) || !std::isfinite(xx)) break;
+    if (dd <= tol * tol * xx) {
+      converged = true;
+      break;
+    }
+  }
+  if (launch_load<double>(reinterpret_cast<const LoadItem*>(desc + gbytes), 1, b, b, st) != hipSuccess)
+    return BRI_ERR_HIP;
+  if (!converged && launch_info_unconverged(info, st) != hipSuccess) return BRI_ERR_HIP;
+  return BRI_OK;
+}
 
 }  // namespace
 }  // namespace bri
@@ -524,8 +742,15 @@ int bri_profile_read(bri_profile_entry* entries, int cap) {
 
 size_t bri_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
   if (!o || check_block_args(n, n, k, i, j, (n + k - 1) / k) != 0) return 0;
-  if (!plain_precision(o->precision)) return 0;
   const int w = resolve_width(n, k, o);
+  if (mixed_precision(o->precision)) {
+    try {
+      return mixed_workspace_size(n, k, j, w);
+    } catch (const std::exception&) {
+      return 0;
+    }
+  }
+  if (!plain_precision(o->precision)) return 0;
   try {
     auto cp = get_plan(0, n, k, i, j, w, elem_size(o->precision), 0);
     return cp->layout.total;
@@ -551,16 +776,14 @@ int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_pla
   s->block = p.b;
   s->algorithmic_flops = p.algorithmic_flops;
   s->executed_flops = p.executed_flops;
-  s->workspace_bytes = cp->layout.total;
+  s->workspace_bytes = mixed_precision(o->precision) ? mixed_workspace_size(n, k, j, w) : cp->layout.total;
   return 0;
 }
 
-int64_t bri_plan_dump(int64_t n, int k, int i, int j, const bri_opts* o, int64_t* words, int64_t cap) {
-  if (!o) return -5;
-  const int rc = check_block_args(n, n, k, i, j, (n + k - 1) / k);
-  if (rc) return rc;
-  const int w = resolve_width(n, k, o);
-  auto cp = get_plan(0, n, k, i, j, w, elem_size(o->precision), 0);
+}  // extern "C"
+
+namespace {
+int64_t dump_steps(const Plan& plan, int64_t* words, int64_t cap) {
   int64_t pos = 0;
   auto put = [&](int64_t v) {
     if (words && pos < cap) words[pos] = v;
@@ -571,7 +794,7 @@ int64_t bri_plan_dump(int64_t n, int k, int i, int j, const bri_opts* o, int64_t
     put(x.a);
     put(x.b);
   };
-  for (const Step& s : cp->plan.steps) {
+  for (const Step& s : plan.steps) {
     put(s.kind);
     put(static_cast<int64_t>(s.items.size()));
     for (const StepItem& it : s.items) {
@@ -585,6 +808,33 @@ int64_t bri_plan_dump(int64_t n, int k, int i, int j, const bri_opts* o, int64_t
   }
   return pos;
 }
+}  // namespace
+
+extern "C" {
+
+int64_t bri_plan_dump(int64_t n, int k, int i, int j, const bri_opts* o, int64_t* words, int64_t cap) {
+  if (!o) return -5;
+  const int rc = check_block_args(n, n, k, i, j, (n + k - 1) / k);
+  if (rc) return rc;
+  const int w = resolve_width(n, k, o);
+  auto cp = get_plan(0, n, k, i, j, w, elem_size(o->precision), 0);
+  return dump_steps(cp->plan, words, cap);
+}
+
+int64_t bri_refine_plan_dump(int64_t n, int k, int j, int which, const bri_opts* o, int64_t* words, int64_t cap) {
+  if (!o) return -5;
+  const int rc = check_block_args(n, n, k, 0, j, (n + k - 1) / k);
+  if (rc) return rc == -6 ? -3 : rc;
+  if (which < 0 || which > 2) return -4;
+  const int w = resolve_width(n, k, o);
+  auto r = get_refine(n, k, j, w);
+  if (which == 2) {
+    for (int t = 0; t < k; ++t)
+      if (words && t < cap) words[t] = r->kept[t];
+    return k;
+  }
+  return dump_steps(which == 0 ? r->col->plan : r->sol->plan, words, cap);
+}
 
 int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, void* out, int64_t ldo,
                  const bri_opts* o) {
@@ -593,6 +843,7 @@ int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, voi
   if (!o) return -9;
   const int rc = check_block_args(n, ldm, k, i, j, ldo);
   if (rc) return rc;
+  if (mixed_precision(o->precision)) return invert_block_mixed(M, n, ldm, k, i, j, out, ldo, o);
   if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
   const int elem = elem_size(o->precision);
   const int w = resolve_width(n, k, o);
@@ -711,7 +962,7 @@ int bri_gemm(int count, int64_t m, int64_t n, int64_t kk, double alpha, const vo
   if (!C && count) return -11;
   if (ldc < std::max<int64_t>(1, n)) return -12;
   if (!o) return -13;
-  if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
+  if (!plain_precision(o->precision) && !mixed_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
   if (count == 0 || m == 0 || n == 0) return BRI_OK;
   const size_t need = bri_gemm_workspace_size(count);
   if (!o->workspace || o->workspace_bytes < need) return BRI_ERR_WORKSPACE;
@@ -761,7 +1012,8 @@ int bri_gemm(int count, int64_t m, int64_t n, int64_t kk, double alpha, const vo
   if (hipEventRecord(ev, o->stream) != hipSuccess) return BRI_ERR_HIP;
   GemmLaunch L{};
   L.mode = GEMM_EXPLICIT;
-  L.elem = elem_size(o->precision);
+  L.elem = o->precision == BRI_F64 ? 8 : 4;
+  L.lp = lp_of(o->precision);
   L.items = o->workspace;
   L.count = count;
   L.w = count;  // plain dense operands: all items take the fast instance

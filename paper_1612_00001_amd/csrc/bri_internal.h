@@ -77,6 +77,7 @@ struct GemmLaunch {
                         // takes (see gemm_item_is_fast), j = item offset
   int32_t s;            // TRTRI level: half-block size
   int32_t npairs;       // TRTRI level: block pairs per matrix
+  int32_t lp;           // float storage only: 0 FP32 MFMA, 1 FP16 split, 2 BF16 split
 };
 
 constexpr int kMaxBlock = 4096;  // == BRI_MAX_BLOCK
@@ -109,7 +110,9 @@ inline int panel_width(int h) { return h <= 1024 ? 32 : (h <= 2048 ? 16 : 8); }
 // ---------------------------------------------------------------------------
 // Host plan: batched steps over b x b workspace slots.
 // ---------------------------------------------------------------------------
-enum OpndKind : int8_t { OPND_NONE = 0, OPND_SLOT = 1, OPND_MBLK = 2, OPND_IDENT = 3, OPND_OUT = 4 };
+// OPND_RHS: block row a of the right-hand side of a solve plan (the extra
+// block column k of the bordered matrix [Gamma | R]).
+enum OpndKind : int8_t { OPND_NONE = 0, OPND_SLOT = 1, OPND_MBLK = 2, OPND_IDENT = 3, OPND_OUT = 4, OPND_RHS = 5 };
 
 struct Opnd {
   int8_t kind = OPND_NONE;
@@ -119,6 +122,8 @@ struct Opnd {
   static Opnd mblk(int r, int c) { Opnd o; o.kind = OPND_MBLK; o.a = r; o.b = c; return o; }
   static Opnd ident() { Opnd o; o.kind = OPND_IDENT; return o; }
   static Opnd outp() { Opnd o; o.kind = OPND_OUT; return o; }
+  static Opnd out_blk(int r) { Opnd o; o.kind = OPND_OUT; o.a = r; return o; }
+  static Opnd rhs(int r) { Opnd o; o.kind = OPND_RHS; o.a = r; return o; }
 };
 
 enum StepKind : int32_t {
@@ -161,6 +166,19 @@ struct Plan {
 Plan make_block_plan(int64_t n, int k, int i, int j, int width);
 // Builds the plan of bri_block_column (block column j of Gamma^{-1}).
 Plan make_column_plan(int64_t n, int k, int j, int width);
+
+// Plans of the mixed-precision refinement for block column j, sharing one
+// slot numbering:
+//   column: the block column plan that also keeps the factored pivot of
+//           every back-substitution position in a reserved slot;
+//   solve:  X = Gamma^{-1} R for a general (k b) x b right-hand side R
+//           (operands OPND_RHS), by the same back substitution whose Schur
+//           complements are recomputed, reusing the kept pivots.
+struct RefinePlans {
+  Plan column, solve;
+  std::vector<int> kept;  // kept[pos]: slot of the pivot of elimination position pos
+};
+RefinePlans make_refine_plans(int64_t n, int k, int j, int width);
 
 // Launch/flop accounting of the kernels that realise a step.
 int64_t getrf_launches(int b);

@@ -403,6 +403,201 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
 }
 
 // ---------------------------------------------------------------------------
+// Low-precision products for the mixed-precision paths: FP32 operands are
+// split into FP16 or BF16 parts on the way into LDS and multiplied on
+// v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation.
+//   FP16: x = hi + lo 2^-11, three products hi hi + (hi lo + lo hi) 2^-11
+//         (the scaled low part keeps small values out of FP16 subnormals);
+//   BF16: x = hi + mid + lo, six products hi hi + hi mid + mid hi + hi lo +
+//         lo hi + mid mid.
+// A 64 x 64 output tile per workgroup, 4 wavefronts of 32 x 32, K in steps of
+// 32 (one MFMA K-step); LDS tiles are k-contiguous per row (A) / per column
+// (B) so that every lane fetches its 8 operand values with one 16-byte read.
+// ---------------------------------------------------------------------------
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+template <int LP>
+struct LPT;
+template <>
+struct LPT<1> {  // FP16, two parts
+  typedef _Float16 E;
+  typedef h8_t V;
+  static constexpr int PARTS = 2;
+  __device__ static void split(float x, E (&p)[2]) {
+    const _Float16 hi = static_cast<_Float16>(x);
+    p[0] = hi;
+    p[1] = static_cast<_Float16>((x - static_cast<float>(hi)) * 2048.0f);
+  }
+  __device__ static f4_t mma(V a, V b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct LPT<2> {  // BF16, three parts
+  typedef __bf16 E;
+  typedef bf8_t V;
+  static constexpr int PARTS = 3;
+  __device__ static void split(float x, E (&p)[3]) {
+    const __bf16 hi = static_cast<__bf16>(x);
+    const float r1 = x - static_cast<float>(hi);
+    const __bf16 mid = static_cast<__bf16>(r1);
+    p[0] = hi;
+    p[1] = mid;
+    p[2] = static_cast<__bf16>(r1 - static_cast<float>(mid));
+  }
+  __device__ static f4_t mma(V a, V b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+
+template <int LP, int MODE, bool GEN>
+__global__ __launch_bounds__(256) void k_gemm_lp(GemmLaunch L) {
+  typedef LPT<LP> P;
+  typedef typename P::E E;
+  typedef typename P::V V;
+  constexpr int NP = P::PARTS;
+  constexpr int BM = 64, BN = 64, BK = 32, NT = 256, WM = 32, WN = 32, KP = BK + 8;
+  typedef TileOp<float, BM, BK, NT> OpA;
+  typedef TileOp<float, BK, BN, NT> OpB;
+  constexpr int AE = OpA::E, BE = OpB::E;
+
+  GemmItem it;
+  if (!gemm_item<float, MODE>(L, blockIdx.y + (GEN ? L.j : 0), it)) return;
+  const int tiles_n = (it.N + BN - 1) / BN;
+  const int tiles_m = (it.M + BM - 1) / BM;
+  if (static_cast<int>(blockIdx.x) >= tiles_m * tiles_n) return;
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+  int kb = 0, ke = it.K;
+  if (it.A.tri == 1) ke = min(ke, m0 + BM);
+  if (it.A.tri == 2) kb = max(kb, m0);
+  if (it.B.tri == 1) kb = max(kb, n0);
+  if (it.B.tri == 2) ke = min(ke, n0 + BN);
+  kb = (kb / BK) * BK;
+
+  __shared__ __attribute__((aligned(16))) E As[2][NP][BM][KP];
+  __shared__ __attribute__((aligned(16))) E Bs[2][NP][BN][KP];
+  __shared__ int32_t s_perm[(MODE == GEMM_EXPLICIT && !GEN) ? kMaxBlock : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  OpA opa;
+  OpB opb;
+  const int32_t* permA = nullptr;
+  const int32_t* permB = nullptr;
+  if (MODE == GEMM_EXPLICIT && !GEN) {
+    const int32_t* gp = it.B.rowperm ? it.B.rowperm : it.A.rowperm;
+    const int np = it.B.rowperm ? it.K : it.M;
+    if (gp) {
+      for (int e = tid; e < np; e += NT) s_perm[e] = gp[e];
+      __syncthreads();
+      if (it.B.rowperm)
+        permB = s_perm;
+      else
+        permA = s_perm;
+    }
+  }
+  opa.init(it.A, permA, it.M, it.K, tid);
+  opb.init(it.B, permB, it.K, it.N, tid);
+
+  f4_t acc[2][2], accx[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[i][j][v] = 0.f;
+        accx[i][j][v] = 0.f;
+      }
+
+  auto issue = [&](int k0) {
+    if (GEN) {
+      opa.issue_generic(it.A, m0, k0);
+      opb.issue_generic(it.B, k0, n0);
+    } else {
+      opa.issue(m0, k0);
+      opb.issue(k0, n0);
+    }
+  };
+  auto store = [&](int buf, int k0) {
+#pragma unroll
+    for (int t = 0; t < AE; ++t) {
+      E pa[NP];
+      P::split(GEN ? opa.raw[t] : opa.finalize(t, m0, k0), pa);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) As[buf][q][opa.r0 + t * opa.dr][opa.c0 + t * opa.dc] = pa[q];
+    }
+#pragma unroll
+    for (int t = 0; t < BE; ++t) {
+      E pb[NP];
+      P::split(GEN ? opb.raw[t] : opb.finalize(t, k0, n0), pb);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) Bs[buf][q][opb.c0 + t * opb.dc][opb.r0 + t * opb.dr] = pb[q];
+    }
+  };
+
+  if (kb < ke) {
+    issue(kb);
+    store(0, kb);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+      const bool more = k0 + BK < ke;
+      if (more) issue(k0 + BK);
+      V a[2][NP], bv[2][NP];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          a[i][q] = *reinterpret_cast<const V*>(&As[buf][q][wm * WM + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+          bv[i][q] = *reinterpret_cast<const V*>(&Bs[buf][q][wn * WN + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (LP == 1) {
+            acc[i][j] = P::mma(a[i][0], bv[j][0], acc[i][j]);
+            accx[i][j] = P::mma(a[i][0], bv[j][1], accx[i][j]);
+            accx[i][j] = P::mma(a[i][1], bv[j][0], accx[i][j]);
+          } else {
+            accx[i][j] = P::mma(a[i][1], bv[j][1], accx[i][j]);
+            accx[i][j] = P::mma(a[i][0], bv[j][NP - 1], accx[i][j]);
+            accx[i][j] = P::mma(a[i][NP - 1], bv[j][0], accx[i][j]);
+            acc[i][j] = P::mma(a[i][0], bv[j][1], acc[i][j]);
+            acc[i][j] = P::mma(a[i][1], bv[j][0], acc[i][j]);
+            acc[i][j] = P::mma(a[i][0], bv[j][0], acc[i][j]);
+          }
+        }
+      if (more) store(buf ^ 1, k0 + BK);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  float* out = static_cast<float*>(it.out);
+  const float alpha = static_cast<float>(it.alpha), beta = static_cast<float>(it.beta);
+  const float* cinp = static_cast<const float*>(it.Cin.p);
+  const float* subp = static_cast<const float*>(it.Sub.p);
+  const float xs = (LP == 1) ? (1.0f / 2048.0f) : 1.0f;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + v;
+        const int c = n0 + wn * WN + j * 16 + (lane & 15);
+        if (r < it.M && c < it.N) {
+          float val = alpha * (acc[i][j][v] + accx[i][j][v] * xs);
+          if (it.has_cin)
+            val += beta * (GEN ? vget<float>(it.Cin, r, c) : gload(cinp + static_cast<int64_t>(r) * it.Cin.ld + c));
+          if (it.has_sub)
+            val -= GEN ? vget<float>(it.Sub, r, c) : gload(subp + static_cast<int64_t>(r) * it.Sub.ld + c);
+          out[static_cast<int64_t>(r) * it.ldo + c] = val;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Wave-wide argmax with DPP: the largest value, lowest index on ties (the
 // rule of LAPACK's idamax).  Every lane returns the wave's winner.
 // ---------------------------------------------------------------------------
@@ -995,9 +1190,22 @@ namespace {
 inline int cdiv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 }  // namespace
 
+template <int MODE, bool GEN>
+hipError_t launch_gemm_lp(const GemmLaunch& L, int count, int max_m, int max_n, hipStream_t st) {
+  dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), count);
+  if (L.lp == 1)
+    hipLaunchKernelGGL((k_gemm_lp<1, MODE, GEN>), grid, dim3(256), 0, st, L);
+  else
+    hipLaunchKernelGGL((k_gemm_lp<2, MODE, GEN>), grid, dim3(256), 0, st, L);
+  return hipGetLastError();
+}
+
 template <typename T, int MODE, bool GEN>
 hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n, hipStream_t st) {
   if (count <= 0) return hipSuccess;
+  if constexpr (sizeof(T) == 4) {
+    if (L.lp) return launch_gemm_lp<MODE, GEN>(L, count, max_m, max_n, st);
+  }
   const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * count;
   if (big_tiles >= 256) {
     dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), count);

@@ -66,6 +66,20 @@ class Builder {
   int next_node() { return node_counter_++; }
   SlotPool& pool() { return pool_; }
 
+  // Block column index standing for the right-hand side R of a solve plan.
+  void set_rhs_column(int c) { rhs_col_ = c; }
+  // Pivot memo: memo[d - 1] is a slot holding the already factored and
+  // inverted pivot v(p, p, I') of every depth-d node (p = pivot_of(d)), or -1.
+  // Memoised pivots are neither recomputed nor refactored: a node then has
+  // three children instead of four.
+  void set_memo(std::vector<int> memo) { memo_ = std::move(memo); }
+
+  // Depth-0 operand (r, c): a block of Gamma, or of R for the RHS column.
+  Opnd blk(int r, int c) const { return c == rhs_col_ ? Opnd::rhs(r) : Opnd::mblk(r, c); }
+  int memo_of(int depth) const {
+    return depth - 1 < static_cast<int>(memo_.size()) ? memo_[depth - 1] : -1;
+  }
+
   Step& step(StepKind kind) {
     plan_.steps.push_back(Step{kind, {}});
     return plan_.steps.back();
@@ -78,8 +92,34 @@ class Builder {
     if (L.empty()) return {};
     const int d = L[0].depth;
     if (d == 1) return leaf(L, accs);
-    if (4 * static_cast<int64_t>(L.size()) <= width_) return expand(L, accs);
+    const int64_t kids = memo_of(d) >= 0 ? 3 : 4;
+    if (kids * static_cast<int64_t>(L.size()) <= width_) return expand(L, accs);
     return lockstep(L, accs);
+  }
+
+  // X = P^{-1} B with already inverted factors: lu[t] holds the factors,
+  // rhs[t] the operand B, xdst[t] receives X.  One Schur operation each.
+  void solve_with(const std::vector<int>& lu, const std::vector<Opnd>& rhs, const std::vector<Opnd>& xdst) {
+    const size_t n = lu.size();
+    std::vector<int> tmp(n);
+    for (size_t t = 0; t < n; ++t) tmp[t] = pool_.alloc();
+    Step& l = step(ST_TRMM_L);
+    for (size_t t = 0; t < n; ++t) {
+      StepItem it;
+      it.dst = Opnd::slot(tmp[t]);
+      it.x = Opnd::slot(lu[t]);
+      it.y = rhs[t];
+      l.items.push_back(it);
+    }
+    Step& u = step(ST_TRMM_U);
+    for (size_t t = 0; t < n; ++t) {
+      StepItem it;
+      it.dst = xdst[t];
+      it.x = Opnd::slot(lu[t]);
+      it.y = Opnd::slot(tmp[t]);
+      u.items.push_back(it);
+    }
+    for (size_t t = 0; t < n; ++t) pool_.release(tmp[t]);
   }
 
   // Factor pivots, invert their triangular factors and form X = P^{-1} B for
@@ -130,23 +170,31 @@ class Builder {
   std::vector<int> leaf(const std::vector<Node>& L, const std::vector<int>& accs) {
     const size_t n = L.size();
     const int p = pivot_of(1);
+    const int memo = memo_of(1);
     std::vector<int> sp(n), sx(n), outs(n);
-    for (size_t t = 0; t < n; ++t) sp[t] = pool_.alloc();
-    for (size_t t = 0; t < n; ++t) sx[t] = pool_.alloc();
-    Step& ld = step(ST_LOAD);
-    for (size_t t = 0; t < n; ++t) {
-      StepItem it;
-      it.dst = Opnd::slot(sp[t]);
-      it.x = Opnd::mblk(p, p);
-      ld.items.push_back(it);
-    }
     std::vector<Opnd> rhs(n), xd(n);
     for (size_t t = 0; t < n; ++t) {
-      rhs[t] = Opnd::mblk(p, L[t].c);
-      xd[t] = Opnd::slot(sx[t]);
+      rhs[t] = blk(p, L[t].c);
     }
-    factor_and_solve(sp, rhs, xd, true);
-    for (size_t t = 0; t < n; ++t) pool_.release(sp[t]);
+    if (memo >= 0) {
+      for (size_t t = 0; t < n; ++t) sx[t] = pool_.alloc();
+      for (size_t t = 0; t < n; ++t) xd[t] = Opnd::slot(sx[t]);
+      solve_with(std::vector<int>(n, memo), rhs, xd);
+      plan_.schur_ops += static_cast<int64_t>(n);
+    } else {
+      for (size_t t = 0; t < n; ++t) sp[t] = pool_.alloc();
+      for (size_t t = 0; t < n; ++t) sx[t] = pool_.alloc();
+      Step& ld = step(ST_LOAD);
+      for (size_t t = 0; t < n; ++t) {
+        StepItem it;
+        it.dst = Opnd::slot(sp[t]);
+        it.x = Opnd::mblk(p, p);
+        ld.items.push_back(it);
+      }
+      for (size_t t = 0; t < n; ++t) xd[t] = Opnd::slot(sx[t]);
+      factor_and_solve(sp, rhs, xd, true);
+      for (size_t t = 0; t < n; ++t) pool_.release(sp[t]);
+    }
     for (size_t t = 0; t < n; ++t) outs[t] = pool_.alloc();
     Step& g = step(ST_GEMM);
     for (size_t t = 0; t < n; ++t) {
@@ -154,7 +202,7 @@ class Builder {
       it.dst = Opnd::slot(outs[t]);
       it.x = Opnd::mblk(L[t].r, p);
       it.y = Opnd::slot(sx[t]);
-      it.cin = Opnd::mblk(L[t].r, L[t].c);
+      it.cin = blk(L[t].r, L[t].c);
       it.sub = accs[t] >= 0 ? Opnd::slot(accs[t]) : Opnd::none();
       g.items.push_back(it);
     }
@@ -166,28 +214,35 @@ class Builder {
     const size_t n = L.size();
     const int d = L[0].depth;
     const int p = pivot_of(d);
+    const int memo = memo_of(d);
+    const int nk = memo >= 0 ? 3 : 4;
     std::vector<Node> kids;
     for (size_t t = 0; t < n; ++t) {
       kids.push_back({L[t].r, L[t].c, d - 1});
       kids.push_back({L[t].r, p, d - 1});
-      kids.push_back({p, p, d - 1});
+      if (memo < 0) kids.push_back({p, p, d - 1});
       kids.push_back({p, L[t].c, d - 1});
     }
-    const std::vector<int> res = eval(kids, std::vector<int>(kids.size(), -1));
+    const std::vector<int> res = eval_children(kids);
     std::vector<int> src(n), srp(n), spp(n), spc(n);
     for (size_t t = 0; t < n; ++t) {
-      src[t] = res[4 * t];
-      srp[t] = res[4 * t + 1];
-      spp[t] = res[4 * t + 2];
-      spc[t] = res[4 * t + 3];
+      src[t] = res[nk * t];
+      srp[t] = res[nk * t + 1];
+      spp[t] = memo >= 0 ? memo : res[nk * t + 2];
+      spc[t] = res[nk * t + nk - 1];
     }
     std::vector<Opnd> rhs(n), xd(n);
     for (size_t t = 0; t < n; ++t) {
       rhs[t] = Opnd::slot(spc[t]);
       xd[t] = Opnd::slot(spc[t]);
     }
-    factor_and_solve(spp, rhs, xd, true);
-    for (size_t t = 0; t < n; ++t) pool_.release(spp[t]);
+    if (memo >= 0) {
+      solve_with(spp, rhs, xd);
+      plan_.schur_ops += static_cast<int64_t>(n);
+    } else {
+      factor_and_solve(spp, rhs, xd, true);
+      for (size_t t = 0; t < n; ++t) pool_.release(spp[t]);
+    }
     Step& g = step(ST_GEMM);
     for (size_t t = 0; t < n; ++t) {
       StepItem it;
@@ -209,20 +264,31 @@ class Builder {
     const size_t n = L.size();
     const int d = L[0].depth;
     const int p = pivot_of(d);
+    const int memo = memo_of(d);
     const std::vector<int> none(n, -1);
     std::vector<Node> kids(n);
-    // Pivot children, factored at once so only their factors stay live.
-    for (size_t t = 0; t < n; ++t) kids[t] = {p, p, d - 1};
-    const std::vector<int> sp = eval(kids, none);
-    factor_only(sp);
+    std::vector<int> sp(n, memo);
+    if (memo < 0) {
+      // Pivot children, factored at once so only their factors stay live.
+      for (size_t t = 0; t < n; ++t) kids[t] = {p, p, d - 1};
+      sp = eval_children(kids);
+      factor_only(sp);
+    }
     // Right-hand children; X = P^{-1} B replaces them.
     for (size_t t = 0; t < n; ++t) kids[t] = {p, L[t].c, d - 1};
-    const std::vector<int> sb = eval(kids, none);
-    solve_only(sp, sb);
-    for (size_t t = 0; t < n; ++t) pool_.release(sp[t]);
+    const std::vector<int> sb = eval_children(kids);
+    if (memo < 0) {
+      solve_only(sp, sb);
+      for (size_t t = 0; t < n; ++t) pool_.release(sp[t]);
+    } else {
+      std::vector<Opnd> ob(n);
+      for (size_t t = 0; t < n; ++t) ob[t] = Opnd::slot(sb[t]);
+      solve_with(sp, ob, ob);
+      plan_.schur_ops += static_cast<int64_t>(n);
+    }
     // Left children: acc (+)= C X.
     for (size_t t = 0; t < n; ++t) kids[t] = {L[t].r, p, d - 1};
-    const std::vector<int> sc = eval(kids, none);
+    const std::vector<int> sc = eval_children(kids);
     std::vector<int> acc(n);
     std::vector<bool> own(n, false);
     for (size_t t = 0; t < n; ++t) {
@@ -248,7 +314,7 @@ class Builder {
     }
     // Diagonal children subtract the accumulated sum in their last product.
     for (size_t t = 0; t < n; ++t) kids[t] = {L[t].r, L[t].c, d - 1};
-    const std::vector<int> outs = eval(kids, acc);
+    const std::vector<int> outs = eval_children(kids, acc);
     for (size_t t = 0; t < n; ++t)
       if (own[t]) pool_.release(acc[t]);
     return outs;
@@ -336,11 +402,18 @@ class Builder {
       Step& ld = step(ST_LOAD);
       StepItem it;
       it.dst = Opnd::slot(out);
-      it.x = Opnd::mblk(r, c);
+      it.x = blk(r, c);
       ld.items.push_back(it);
       return out;
     }
     return eval({Node{r, c, d}}, {-1})[0];
+  }
+
+  // Values of a batch of nodes of one depth d >= 1, with the accumulated
+  // sums accs subtracted when given.
+  std::vector<int> eval_children(const std::vector<Node>& L, const std::vector<int>& accs = {}) {
+    if (L.empty()) return {};
+    return eval(L, accs.empty() ? std::vector<int>(L.size(), -1) : accs);
   }
 
   Plan& plan_;
@@ -348,6 +421,8 @@ class Builder {
   int width_;
   SlotPool pool_;
   int node_counter_ = 0;
+  int rhs_col_ = -1;
+  std::vector<int> memo_;
 };
 
 double cube(double x) { return x * x * x; }
@@ -520,9 +595,19 @@ Plan make_block_plan(int64_t n, int k, int i, int j, int width) {
   return plan;
 }
 
-Plan make_column_plan(int64_t n, int k, int j, int width) {
+namespace {
+
+// Elimination order of the block column plans: every index but j ascending,
+// j last (x_j is the first unknown of the back substitution).
+std::vector<int> column_order(int k, int j) {
+  std::vector<int> order;
+  for (int t = 0; t < k; ++t)
+    if (t != j) order.push_back(t);
+  return order;
+}
+
+void init_column_plan(Plan& plan, int64_t n, int k, int j, int width) {
   if (k < 2 || n < k || j < 0 || j >= k) throw std::invalid_argument("bad target");
-  Plan plan;
   plan.n = n;
   plan.k = k;
   plan.i = -1;
@@ -530,18 +615,26 @@ Plan make_column_plan(int64_t n, int k, int j, int width) {
   plan.b = static_cast<int>((n + k - 1) / k);
   const int64_t leaves = static_cast<int64_t>(std::pow(4.0, std::max(0, k - 2)));
   plan.width = std::max<int64_t>(1, std::min<int64_t>(width, leaves));
-  std::vector<int> order;
-  for (int t = 0; t < k; ++t)
-    if (t != j) order.push_back(t);
-  Builder B(plan, order, plan.width);
+}
+
+// Block column j of Gamma^{-1} by block back substitution:
+//   x_j = v(j, j, P)^{-1}, P = every other index;
+//   x_q = -v(q, q, I_q)^{-1} (v(q, j, I_q) x_j + sum_{t after q} v(q, t, I_q) x_t).
+// With kept != nullptr the factored pivot of every position stays in its slot
+// (kept[pos], pos = position in the elimination order, j at k - 1).
+void build_column(Builder& B, const std::vector<int>& order, int j, std::vector<int>* kept) {
+  Plan& plan = B.plan_;
+  const int k = plan.k;
   SlotPool& pool = B.pool();
-  // x_j = v(j, j, P)^{-1}, written to block row j of the output.
+  if (kept) kept->assign(k, -1);
   {
     const int sz = B.value(j, j, k - 1);
-    B.final_inverse(sz, Opnd{OPND_OUT, j, 0}, true);
-    pool.release(sz);
+    B.final_inverse(sz, Opnd::out_blk(j), true);
+    if (kept)
+      (*kept)[k - 1] = sz;
+    else
+      pool.release(sz);
   }
-  // Back substitution: x_q = -v(q,q,I_q)^{-1} (v(q,j,I_q) x_j + sum_{t after q} v(q,t,I_q) x_t).
   for (int pos = k - 2; pos >= 0; --pos) {
     const int q = order[pos];
     int acc = pool.alloc();
@@ -554,7 +647,7 @@ Plan make_column_plan(int64_t n, int k, int j, int width) {
       StepItem it;
       it.dst = Opnd::slot(acc);
       it.x = Opnd::slot(sv);
-      it.y = Opnd{OPND_OUT, t, 0};
+      it.y = Opnd::out_blk(t);
       it.cin = first ? Opnd::none() : Opnd::slot(acc);
       g.items.push_back(it);
       first = false;
@@ -567,16 +660,72 @@ Plan make_column_plan(int64_t n, int k, int j, int width) {
     B.solve_only({sq}, {acc});
     Step& cp = B.step(ST_LOAD);
     StepItem it;
-    it.dst = Opnd{OPND_OUT, q, 0};
+    it.dst = Opnd::out_blk(q);
     it.x = Opnd::slot(acc);
     cp.items.push_back(it);
-    pool.release(sq);
+    if (kept)
+      (*kept)[pos] = sq;
+    else
+      pool.release(sq);
     pool.release(acc);
   }
-  plan.nslots = pool.peak;
+}
+
+}  // namespace
+
+Plan make_column_plan(int64_t n, int k, int j, int width) {
+  Plan plan;
+  init_column_plan(plan, n, k, j, width);
+  const std::vector<int> order = column_order(k, j);
+  Builder B(plan, order, plan.width);
+  build_column(B, order, j, nullptr);
+  plan.nslots = B.pool().peak;
   plan.algorithmic_flops = 0;
   account(plan);
   return plan;
+}
+
+RefinePlans make_refine_plans(int64_t n, int k, int j, int width) {
+  RefinePlans rp;
+  init_column_plan(rp.column, n, k, j, width);
+  init_column_plan(rp.solve, n, k, j, width);
+  std::vector<int> order = column_order(k, j);
+  Builder B(rp.column, order, rp.column.width);
+  build_column(B, order, j, &rp.kept);
+  // The solve plan starts from the column plan's pool: the kept pivots stay
+  // allocated, everything else is free again.
+  Builder S(rp.solve, order, rp.solve.width);
+  S.pool() = B.pool();
+  S.set_rhs_column(k);
+  S.set_memo(std::vector<int>(rp.kept.begin(), rp.kept.end() - 1));
+  SlotPool& pool = S.pool();
+  // Forward elimination of R rides along as the extra column k; back
+  // substitution with the kept pivots:
+  //   x_j = v(j, j, P)^{-1} v(j, R, P),
+  //   x_q = v(q, q, I_q)^{-1} (v(q, R, I_q) - sum_{t after q} v(q, t, I_q) x_t).
+  order.push_back(j);
+  for (int pos = k - 1; pos >= 0; --pos) {
+    const int q = order[pos];
+    const int acc = S.value(q, k, pos);
+    for (int t = pos + 1; t < k; ++t) {
+      const int sv = S.value(q, order[t], pos);
+      Step& g = S.step(ST_GEMM);
+      StepItem it;
+      it.dst = Opnd::slot(acc);
+      it.x = Opnd::slot(sv);
+      it.y = Opnd::out_blk(order[t]);
+      it.cin = Opnd::slot(acc);
+      g.items.push_back(it);
+      pool.release(sv);
+    }
+    S.solve_with({rp.kept[pos]}, {Opnd::slot(acc)}, {Opnd::out_blk(q)});
+    pool.release(acc);
+  }
+  rp.column.nslots = rp.solve.nslots = std::max(B.pool().peak, pool.peak);
+  rp.column.algorithmic_flops = rp.solve.algorithmic_flops = 0;
+  account(rp.column);
+  account(rp.solve);
+  return rp;
 }
 
 }  // namespace bri

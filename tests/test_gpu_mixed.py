@@ -1,0 +1,123 @@
+"""GPU parity of the mixed-precision paths against the FP64 CPU oracle.
+
+Mixed paths: M and the result in FP64, the recursion in float storage with
+its products on FP32 MFMA (mixed_f32) or on split FP16 / BF16 MFMA with FP32
+accumulation (mixed_f16 / mixed_bf16), and FP64 iterative refinement of the
+block column.  After refinement the target block must match the oracle to
+1e-10 (relative Frobenius error); the refinement stops when the correction is
+below 1e-12 of the iterate.
+
+Split products: x = hi + lo 2^-11 (FP16, three products) or hi + mid + lo
+(BF16, six products).  Their rounding error is bounded by a few units of
+2^-22 (FP16 split, the dropped lo*lo term and the hi/lo rounding) or 2^-24
+(BF16 split) relative to sum |a||b|, plus FP32 accumulation; the bound used
+below, 2^-20 * sqrt(K) relative to ||A|| ||B||, holds with a wide margin.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1612_00001_amd as bri
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(m, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(m)).to(DEV, dtype)
+
+
+@pytest.mark.parametrize("products", ["f16", "bf16", None])
+@pytest.mark.parametrize("m,n,kk", [(64, 64, 32), (200, 130, 77), (512, 256, 1024)])
+def test_split_product_gemm(products, m, n, kk):
+    rng = np.random.default_rng(m + n + kk)
+    a = rng.standard_normal((m, kk))
+    b = rng.standard_normal((kk, n))
+    c0 = rng.standard_normal((m, n))
+    A, B = gpu(a, torch.float32), gpu(b, torch.float32)
+    C = gpu(c0, torch.float32)
+    bri.gemm([A], [B], [C], alpha=-1.0, beta=1.0, products=products)
+    torch.cuda.synchronize()
+    a32 = a.astype(np.float32).astype(np.float64)
+    b32 = b.astype(np.float32).astype(np.float64)
+    want = c0.astype(np.float32).astype(np.float64) - a32 @ b32
+    err = np.abs(C.double().cpu().numpy() - want).max()
+    scale = np.abs(a32).max() * np.abs(b32).max() * kk
+    print(f"products={products} {m}x{n}x{kk}: max err {err:.2e} (scale {scale:.1e})", flush=True)
+    assert err <= 2.0 ** -20 * scale / np.sqrt(kk) * 8
+
+
+def run_mixed(m, k, i, j, precision, iters=10, tol=1e-12):
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    out = bri.invert_block(gpu(m), k, i, j, precision=precision, info=info, refine_max_iters=iters,
+                           refine_tol=tol)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), int(info.item())
+
+
+@pytest.mark.parametrize("precision", ["mixed_f32", "mixed_f16", "mixed_bf16"])
+@pytest.mark.parametrize("n,k", [(384, 4), (130, 4), (257, 2), (300, 5)])
+def test_mixed_refined_matches_oracle(precision, n, k):
+    m = workloads.haar_spd(n, 40 + n, 0.0, 2.0).m
+    for (i, j) in [(0, 0), (k - 1, 1)]:
+        print(f"case {precision} n={n} k={k} ({i},{j})", flush=True)
+        got, info = run_mixed(m, k, i, j, precision)
+        assert info == 0
+        err = rel(got, oracle.invert_block(m, k, i, j))
+        print(f"  rel err {err:.2e}", flush=True)
+        assert err < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["mixed_f16", "mixed_bf16"])
+def test_mixed_cond_1e4(precision):
+    # Q Lam Q^T with Lam log-uniform in [1, 1e4] (condition number 1e4).
+    n, k = 512, 4
+    m = workloads.haar_spd(n, 91, 0.0, 4.0, pin_endpoints=True).m
+    for (i, j) in [(1, 1), (2, 0)]:
+        got, info = run_mixed(m, k, i, j, precision)
+        assert info == 0
+        err = rel(got, oracle.invert_block(m, k, i, j))
+        print(f"{precision} cond 1e4 ({i},{j}): rel err {err:.2e}", flush=True)
+        assert err < 1e-10
+
+
+def test_mixed_without_refinement_is_float_accurate():
+    n, k = 256, 4
+    m = workloads.gaussian_dd(n, 17)
+    want = oracle.invert_block(m, k, 1, 2)
+    got, info = run_mixed(m, k, 1, 2, "mixed_f32", iters=0)
+    assert info == 0
+    err = rel(got, want)
+    assert 1e-12 < err < 1e-4  # float-level only: no FP64 refinement ran
+    got2, _ = run_mixed(m, k, 1, 2, "mixed_f32", iters=3)
+    assert rel(got2, want) < 1e-12
+
+
+def test_mixed_unreachable_tolerance_reports_minus_one():
+    n, k = 128, 2
+    m = workloads.gaussian_dd(n, 18)
+    got, info = run_mixed(m, k, 0, 1, "mixed_bf16", iters=1, tol=0.0)
+    assert info == -1
+    assert rel(got, oracle.invert_block(m, k, 0, 1)) < 1e-6  # one sweep still improved it
+
+
+def test_mixed_batched_problems():
+    probs = workloads.batch_problems(count=6, seed=5, n_lo=64, n_hi=200)
+    Ms = [gpu(workloads.batch_matrix(p)) for p in probs]
+    info = torch.zeros(len(probs), dtype=torch.int32, device=DEV)
+    outs = bri.invert_block_batched(Ms, [p.k for p in probs], [p.i for p in probs], [p.j for p in probs],
+                                    precision="mixed_f32", info=info)
+    torch.cuda.synchronize()
+    assert int(info.abs().sum().item()) == 0
+    for p, o in zip(probs, outs):
+        want = oracle.invert_block(workloads.batch_matrix(p), p.k, p.i, p.j)
+        assert rel(o.cpu().numpy(), want) < 1e-10, (p.n, p.k, p.i, p.j)

@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "bri.h")
 
 ST_LOAD, ST_GETRF, ST_TRTRI, ST_TRMM_L, ST_TRMM_U, ST_GEMM, ST_GEMM_ACC, ST_GEMM_NEG = range(1, 9)
-O_NONE, O_SLOT, O_MBLK, O_IDENT, O_OUT = range(5)
+O_NONE, O_SLOT, O_MBLK, O_IDENT, O_OUT, O_RHS = range(6)
 
 
 def declared_functions():
@@ -118,15 +118,18 @@ def test_flop_accounting():
 # Test-only interpreter of the step list
 # ---------------------------------------------------------------------------
 
-def run_plan(m: np.ndarray, k: int, steps, transpose=False):
+def run_plan(m: np.ndarray, k: int, steps, transpose=False, rhs=None, state=None):
+    """Executes a step list; ``state`` (a dict) carries the slots and factors
+    from one plan to the next (the refinement plans share kept pivots)."""
     n = m.shape[0]
     b = -(-n // k)
     g = np.eye(k * b)
     g[:n, :n] = m
     if transpose:
         g = g.T.copy()
-    slots = {}
-    factors = {}   # slot -> (perm, L, U) or ("inv", perm, Linv, Uinv)
+    state = {} if state is None else state
+    slots = state.setdefault("slots", {})
+    factors = state.setdefault("factors", {})   # slot -> (perm, L, U) or ("inv", perm, Linv, Uinv)
     out = {}
 
     def blk(r, c):
@@ -142,6 +145,8 @@ def run_plan(m: np.ndarray, k: int, steps, transpose=False):
             return np.eye(b)
         if kind == O_OUT:
             return out[a]
+        if kind == O_RHS:
+            return rhs[a * b:(a + 1) * b]
         raise AssertionError(op)
 
     def put(op, val):
@@ -215,3 +220,47 @@ def test_plan_interpreter_reproduces_inverse_blocks(n, k, i, j, W):
     full[:n, :n] = np.linalg.inv(m)
     want = full[i * b:(i + 1) * b, j * b:(j + 1) * b]
     assert np.abs(out[0] - want).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Mixed-precision refinement plans (block column that keeps its pivots, then
+# the correction solve with a general right-hand side)
+# ---------------------------------------------------------------------------
+REFINE_CASES = [(16, 2, 0, 1), (16, 2, 1, 4), (18, 3, 1, 1), (17, 3, 2, 4), (24, 4, 0, 1), (24, 4, 2, 16),
+                (23, 4, 3, 4), (25, 5, 1, 1), (26, 5, 4, 64), (18, 6, 2, 16), (14, 7, 6, 4)]
+
+
+@pytest.mark.parametrize("n,k,j,W", REFINE_CASES)
+def test_refine_plans_column_then_general_solve(n, k, j, W):
+    m = workloads.gaussian_dd(n, 2000 + 5 * n + k)
+    b = -(-n // k)
+    full = np.eye(k * b)
+    full[:n, :n] = m
+    inv = np.linalg.inv(full)
+    state = {}
+    col = run_plan(m, k, bri.refine_plan_dump(n, k, j, "column", W), state=state)
+    x = np.vstack([col[t] for t in range(k)])
+    assert np.abs(x - inv[:, j * b:(j + 1) * b]).max() < 1e-12
+    kept = bri.refine_plan_dump(n, k, j, "kept", W)
+    assert len(set(kept)) == k and all(s in state["factors"] for s in kept)
+    rng = np.random.default_rng(n + k + j)
+    for _ in range(2):  # the solve plan runs once per refinement sweep
+        r = rng.standard_normal((k * b, b))
+        sol = run_plan(m, k, bri.refine_plan_dump(n, k, j, "solve", W), rhs=r, state=state)
+        y = np.vstack([sol[t] for t in range(k)])
+        assert np.abs(y - np.linalg.solve(full, r)).max() < 1e-10
+    # The correction solve never refactors: no getrf / trtri steps.
+    kinds = {kind for kind, _ in bri.refine_plan_dump(n, k, j, "solve", W)}
+    assert ST_GETRF not in kinds and ST_TRTRI not in kinds
+
+
+def test_refine_solve_uses_three_way_recursion():
+    # With the pivots kept, a depth-d value costs (3^d - 1) / 2 Schur steps
+    # instead of (4^d - 1) / 3: count the triangular-solve pairs of the plan.
+    for k in (3, 4, 5, 6):
+        steps = bri.refine_plan_dump(32 * k, k, 0, "solve", 1)
+        trmm_l = sum(len(items) for kind, items in steps if kind == ST_TRMM_L)
+        c3 = [(3 ** d - 1) // 2 for d in range(k)]
+        # x_last: value of depth k-1 (+1 solve); x_q at position p: (k - p) values of depth p (+1 solve)
+        want = c3[k - 1] + 1 + sum((k - p) * c3[p] + 1 for p in range(k - 1))
+        assert trmm_l == want, (k, trmm_l, want)

@@ -205,6 +205,11 @@ typedef struct {
 int bri_profile_enable(int on);
 int bri_profile_read(bri_profile_entry* entries, int cap);
 
+/* Diagnostics of the calling thread's last mixed-precision invert_block:
+ * the number of refinement sweeps it ran and the relative size
+ * ||dX||_F / ||X||_F of its last correction (0 and 0 before any such call). */
+int bri_refine_last(int* sweeps, double* last_update);
+
 /* Human-readable text for a status code returned by any entry point. */
 const char* bri_status_string(int status);
 

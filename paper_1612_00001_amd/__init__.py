@@ -108,6 +108,7 @@ _SIGNATURES = [
       ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64,
       ctypes.c_double, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.POINTER(BriOpts)]),
     ("bri_profile_enable", ctypes.c_int, [ctypes.c_int]),
+    ("bri_refine_last", ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
     ("bri_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("bri_version", ctypes.c_char_p, []),
 ]
@@ -384,6 +385,14 @@ class InvertBlock(torch.autograd.Function):
         (M,) = ctx.saved_tensors
         g = invert_block_backward(M, ctx.k, ctx.i, ctx.j, grad_out, precision=ctx.precision)
         return g, None, None, None, None
+
+
+def refine_last() -> tuple:
+    """(sweeps, last relative correction) of this thread's last mixed-precision call."""
+    s = ctypes.c_int(0)
+    d = ctypes.c_double(0.0)
+    lib().bri_refine_last(ctypes.byref(s), ctypes.byref(d))
+    return s.value, d.value
 
 
 def version() -> str:

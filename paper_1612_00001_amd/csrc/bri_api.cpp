@@ -486,6 +486,10 @@ struct RefineCache {
 
 typedef std::tuple<int64_t, int, int, int> RefineKey;  // n, k, j, width
 
+// Outcome of the calling thread's last mixed-precision call.
+thread_local int t_last_sweeps = 0;
+thread_local double t_last_update = 0.0;
+
 std::shared_ptr<RefineCache> get_refine(int64_t n, int k, int j, int width) {
   static std::map<RefineKey, std::shared_ptr<RefineCache>> c;
   RefineKey key(n, k, j, width);
@@ -641,6 +645,8 @@ int invert_block_mixed(const void* M, int64_t n, int64_t ldm, int k, int i, int 
   // solve plan, X += (sigma / s) D, until ||dX||_F <= tol ||X||_F.
   bool converged = o->refine_max_iters <= 0;
   const double tol = o->refine_tol;
+  t_last_sweeps = 0;
+  t_last_update = 0.0;
   for (int it = 0; it < o->refine_max_iters; ++it) {
     if (launch_scal_clear(scal, 1, 4, st) != hipSuccess) return BRI_ERR_HIP;
     GemmLaunch L{};
@@ -660,6 +666,8 @@ int invert_block_mixed(const void* M, int64_t n, int64_t ldm, int k, int i, int 
       return BRI_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return BRI_ERR_HIP;
     const double dd = hscal[2], xx = hscal[3];
+    t_last_sweeps = it + 1;
+    t_last_update = xx > 0 ? std::sqrt(dd / xx) : dd;
     if (!std::isfinite(dd) || !std::isfinite(xx)) break;
     if (dd <= tol * tol * xx) {
       converged = true;
@@ -709,6 +717,12 @@ static int check_block_args(int64_t n, int64_t ldm, int k, int i, int j, int64_t
   const int64_t b = (n + k - 1) / k;
   if (ldo < b) return -8;
   if (b > BRI_MAX_BLOCK) return BRI_ERR_UNSUPPORTED;
+  return 0;
+}
+
+int bri_refine_last(int* sweeps, double* last_update) {
+  if (sweeps) *sweeps = t_last_sweeps;
+  if (last_update) *last_update = t_last_update;
   return 0;
 }
 

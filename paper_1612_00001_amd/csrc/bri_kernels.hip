@@ -854,139 +854,192 @@ __global__ __launch_bounds__(512) void k_getf2(const LuItem* items, int j, int32
 
 // ---------------------------------------------------------------------------
 // Tile-local pivoting LU, step t0: factor the kTile x kTile diagonal tile in
-// one wavefront (no barriers between columns).  Lane l holds row l % 32 and
-// columns 16 (l / 32) .. 16 (l / 32) + 15 of the tile.  For every column the
-// pivot is the row of largest magnitude among the tile rows at or below it
-// (lowest index on ties); rows move only inside the tile's row band.  The
-// tile's row movement goes to it.swaps[1 + r] (tile row r came from tile row
-// swaps[1 + r]), the matrix permutation is composed in it.perm, and the
-// inverses of the tile's unit-lower L and upper U go to it.aux (L^{-1} first,
-// then U^{-1}, kTile x kTile each, row-major).
+// one wavefront.  Lane l holds row l % 32 and columns 16 (l / 32) ..
+// 16 (l / 32) + 15 of the tile.  For every column the pivot is the row of
+// largest magnitude among the tile rows not chosen before (lowest index on
+// near-ties).  Pivoting is implicit: rows stay in their lanes and the
+// factored rows are stored in pivot order at the end, so rows move only
+// inside the tile's row band.  The tile's row movement goes to
+// it.swaps[1 + q] (tile position q holds original tile row swaps[1 + q]), the
+// matrix permutation is composed in it.perm, and the inverses of the tile's
+// unit-lower L and upper U go to it.aux (L^{-1} first, then U^{-1},
+// kTile x kTile each, row-major).
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void wave32_argmax(T& v, int& i) {
-  dpp_argmax_step<0xB1, 0xf>(v, i);   // quad_perm [1,0,3,2]
-  dpp_argmax_step<0x4E, 0xf>(v, i);   // quad_perm [2,3,0,1]
-  dpp_argmax_step<0x141, 0xf>(v, i);  // row_half_mirror
-  dpp_argmax_step<0x140, 0xf>(v, i);  // row_mirror
-  dpp_argmax_step<0x142, 0xa>(v, i);  // row_bcast:15: lanes 31 and 63 hold their half's winner
-}
 
-template <typename T, int C>
-__device__ __forceinline__ void tile_step(T (&a)[16], int& orig, T (&sP)[kTile][kTile + 1], int r, int half, int ts,
-                                          int32_t* info, int node) {
-  constexpr int hc = C / 16, ic = C % 16;
-  if (C >= ts) return;
-  T v = (half == hc && r >= C && r < ts) ? fabs(a[ic]) : T(-1);
-  int idx = r;
-  wave32_argmax(v, idx);
-  int p;
-  T pv;
+// Uniform-lane read (lane is wave-uniform).
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int lane) {
   if constexpr (sizeof(T) == 8) {
     const int64_t bits = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane(static_cast<int>(bits & 0xffffffff), hc ? 63 : 31);
-    const int hi = __builtin_amdgcn_readlane(static_cast<int>(bits >> 32), hc ? 63 : 31);
-    pv = __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(bits & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(bits >> 32), lane);
+    return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
   } else {
-    pv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), hc ? 63 : 31));
-  }
-  p = __builtin_amdgcn_readlane(idx, hc ? 63 : 31);
-  if (!(pv >= T(0))) p = C;  // no candidate (NaN column): keep the row
-  if (p != C) {
-    const int src = (r == C) ? p : (r == p ? C : r);
-    const int srcl = src + 32 * half;
-#pragma unroll
-    for (int t = 0; t < 16; ++t) a[t] = __shfl(a[t], srcl);
-    orig = __shfl(orig, srcl);
-  }
-  if (r == C) {
-#pragma unroll
-    for (int t = 0; t < 16; ++t) sP[C][16 * half + t] = a[t];
-  }
-  __syncthreads();  // single wavefront: orders the LDS row write before the reads
-  const T piv = sP[C][C];
-  if (!(piv != T(0) && isfinite(piv)) && r == 0 && half == 0 && info) atomicCAS(info, 0, node + 1);
-  const T rinv = piv != T(0) ? T(1) / piv : T(0);
-  const T own = (half == hc) ? a[ic] : T(0);
-  const T lrow = __shfl(own, r + 32 * hc);
-  const T lm = (r > C && r < ts) ? lrow * rinv : T(0);
-  if (half == hc && r > C && r < ts) a[ic] = lm;
-#pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const int col = 16 * half + t;
-    const T u = col > C ? sP[C][col] : T(0);
-    a[t] -= lm * u;
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
   }
 }
 
-template <typename T, int... Cs>
-__device__ __forceinline__ void tile_all(std::integer_sequence<int, Cs...>, T (&a)[16], int& orig,
-                                         T (&sP)[kTile][kTile + 1], int r, int half, int ts, int32_t* info, int node) {
-  (tile_step<T, Cs>(a, orig, sP, r, half, ts, info, node), ...);
+// Orders this wavefront's LDS accesses for the compiler only: a wavefront's
+// LDS operations execute in issue order, so rows one lane writes are seen by
+// the later reads of every lane of the same (single-wavefront) workgroup.
+__device__ __forceinline__ void wave_lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// 1 / d by the hardware reciprocal and two Newton steps (the pivot
+// reciprocal of the tile LU; exact to about one unit in the last place).
+__device__ __forceinline__ double tile_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float tile_rcp(float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  const float e = fmaf(-d, r, 1.0f);
+  return fmaf(r, e, r);
+}
+
+// Pivot search key of a row for a column: the bits of |y| (a NaN orders
+// above +inf) with the low five bits replaced by 31 - r, so that one unsigned
+// 64-bit maximum picks the largest magnitude and, among magnitudes equal to
+// within the dropped bits, the lowest row; 0 when the row is not a candidate.
+__device__ __forceinline__ uint64_t pivot_key(double y, bool cand, int r) {
+  const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(fabs(y)));
+  return cand ? ((bits & ~static_cast<uint64_t>(31)) | static_cast<uint64_t>(31 - r)) : 0;
+}
+__device__ __forceinline__ uint64_t pivot_key(float y, bool cand, int r) {
+  const uint64_t bits = static_cast<uint32_t>(__float_as_int(fabsf(y)));
+  return cand ? ((bits << 5) | static_cast<uint64_t>(31 - r)) : 0;
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_max_step(uint64_t& k) {
+  const int lo = static_cast<int>(k & 0xffffffff), hi = static_cast<int>(k >> 32);
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+  const uint64_t o = (static_cast<uint64_t>(static_cast<uint32_t>(ohi)) << 32) | static_cast<uint32_t>(olo);
+  k = o > k ? o : k;
+}
+// Row of the largest key among the 32 lanes of half h (a wave-uniform value).
+__device__ __forceinline__ int half_argmax(uint64_t k, int h) {
+  dpp_max_step<0xB1, 0xf>(k);   // quad_perm [1,0,3,2]
+  dpp_max_step<0x4E, 0xf>(k);   // quad_perm [2,3,0,1]
+  dpp_max_step<0x141, 0xf>(k);  // row_half_mirror
+  dpp_max_step<0x140, 0xf>(k);  // row_mirror
+  dpp_max_step<0x142, 0xa>(k);  // row_bcast:15: lanes 31 and 63 hold their half's maximum
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(k & 0xffffffff), h ? 63 : 31);
+  return 31 - (lo & 31);
 }
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0, int32_t* info) {
+  constexpr int LD = kTile + 2;
   const LuItem it = items[blockIdx.x];
   T* A = static_cast<T*>(it.a);
   const int b = it.b, ts = min(kTile, b - t0);
   const int l = threadIdx.x, r = l & 31, half = l >> 5;
-  __shared__ T sP[kTile][kTile + 1];
+  __shared__ __attribute__((aligned(16))) T sR[kTile][LD];   // current rows, by original tile row (2 spare columns)
+  __shared__ __attribute__((aligned(16))) T sL[kTile][LD];   // multipliers: sL[r][C]
+  __shared__ __attribute__((aligned(16))) T sF[kTile][LD];   // factored tile in pivot order
+  __shared__ __attribute__((aligned(16))) T sFT[kTile][LD];  // its transpose
+  __shared__ T sD[kTile];                                    // reciprocals of U's diagonal
   T a[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int c = 16 * half + t;
     a[t] = (r < ts && c < ts) ? A[static_cast<int64_t>(t0 + r) * b + t0 + c] : (r == c ? T(1) : T(0));
   }
-  int orig = r;
-  tile_all<T>(std::make_integer_sequence<int, kTile>{}, a, orig, sP, r, half, ts, info, it.node);
-  // Factored tile back to the matrix and to LDS.
+  bool done = false;
+  int pos = r;  // position of this row in the factored tile (rows >= ts keep theirs)
+#pragma unroll
+  for (int t = 0; t < 16; ++t) sR[r][16 * half + t] = a[t];
+  wave_lds_order();
+  // Column loop (not unrolled, so the kernel stays small for the instruction
+  // cache).  Pivoting is implicit: rows stay in their lanes.  Every lane keeps
+  // the current values of columns C and C + 1 of its row in registers (xc,
+  // yc), so the critical path of a step is: pivot value and pivot-row value
+  // by lane reads, multiplier, update of column C + 1, pivot search of
+  // column C + 1.  The rest of each row is updated from the pivot row as
+  // published in LDS after the previous step, column C + 2 is prepared the
+  // same way, and the multipliers go to sL (so the row update needs no
+  // column mask: columns left of C of unchosen rows are dead).  All those
+  // LDS accesses are off the critical path.
+  T xc = sR[r][0], yc = sR[r][1];
+  int p = half_argmax(pivot_key(xc, half == 0 && r < ts, r), 0);
+  bool bad = false;
+  for (int C = 0; C < ts; ++C) {
+    const int c2 = min(C + 2, kTile + 1);
+    const T y2 = sR[r][c2], u2 = sR[p][c2];
+    const T piv = read_lane(xc, p);
+    const T u1 = read_lane(yc, p);
+    bad = bad || !(piv != T(0) && isfinite(piv));
+    const T rinv = piv != T(0) ? tile_rcp(piv) : T(0);
+    const bool act = !done && r < ts && r != p;
+    const T lm = act ? xc * rinv : T(0);
+    if (half == 0 && act) sL[r][C] = lm;
+    if (r == p) {
+      done = true;
+      pos = C;
+    }
+    const T yn = fma(-lm, u1, yc);  // column C + 1 after this step
+    int pn = 0;
+    if (C + 1 < ts) pn = half_argmax(pivot_key(yn, half == 0 && !done && r < ts, r), 0);
+    const T z = fma(-lm, u2, y2);   // column C + 2 after this step
+#pragma unroll
+    for (int t = 0; t < 16; ++t) a[t] = fma(-lm, sR[p][16 * half + t], a[t]);  // same operations as yn and z
+    wave_lds_order();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) sR[r][16 * half + t] = a[t];
+    wave_lds_order();
+    xc = yn;
+    yc = z;
+    p = pn;
+  }
+  if (bad && l == 0 && info) atomicCAS(info, 0, it.node + 1);
+  __syncthreads();
+  // Factored row in pivot order: multipliers left of its pivot column, U
+  // from there on (rows past the tile edge are identity rows).
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int c = 16 * half + t;
-    if (r < ts && c < ts) A[static_cast<int64_t>(t0 + r) * b + t0 + c] = a[t];
-    sP[r][c] = a[t];
+    const T v = (r < ts && c < pos) ? sL[r][c] : a[t];
+    sF[pos][c] = v;
+    sFT[c][pos] = v;
+    if (r < ts && c < ts) A[static_cast<int64_t>(t0 + pos) * b + t0 + c] = v;
   }
-  // Row movement of the tile.  Rows never leave their band, so the band's
-  // entries of the permutation are t0 + (tile row of origin).
+  // Row movement of the tile: position pos holds original tile row r.  Rows
+  // never leave their band, so the band's permutation entries are t0 + r.
   __syncthreads();
   if (half == 0 && r < ts) {
-    it.swaps[1 + r] = orig;
-    it.perm[t0 + r] = t0 + orig;
+    it.swaps[1 + pos] = r;
+    it.perm[t0 + pos] = t0 + r;
   }
-  // Inverses of the unit-lower L (lanes 0..31, column r) and of U (lanes
-  // 32..63, column r) of the tile, by substitution with the solution column
-  // in registers.  The fence after each row keeps the row's LDS reads next
-  // to their use (otherwise all kTile^2 reads are hoisted and spill).
-  T x[kTile];
+  if (l < kTile) sD[l] = T(1) / sF[l][l];
+  __syncthreads();
+  // Inverses of the tile's triangular factors by forward substitution in
+  // column (axpy) form, every update of a step independent:
+  //   lanes 0..31 : column r of L^{-1}        (L unit lower: L[i][q] = sFT[q][i]);
+  //   lanes 32..63: column r of (U^T)^{-1} = row r of U^{-1}
+  //                 ((U^T)[i][q] = U[q][i] = sF[q][i], diagonal 1 / sD).
+  const T* Mq = half ? &sF[0][0] : &sFT[0][0];
+  T xs[kTile];
+#pragma unroll
+  for (int q = 0; q < kTile; ++q) xs[q] = (q == r) ? T(1) : T(0);
+#pragma unroll
+  for (int q = 0; q < kTile; ++q) {
+    const T xq = half ? xs[q] * sD[q] : xs[q];
+    xs[q] = xq;
+#pragma unroll
+    for (int i = q + 1; i < kTile; ++i) xs[i] = fma(-Mq[q * LD + i], xq, xs[i]);
+  }
+  T* aux = static_cast<T*>(it.aux);
   if (half == 0) {
 #pragma unroll
-    for (int i = 0; i < kTile; ++i) {
-      T s0 = T(0), s1 = T(0);
-#pragma unroll
-      for (int q = 0; q < i; q += 2) {
-        s0 += sP[i][q] * x[q];
-        if (q + 1 < i) s1 += sP[i][q + 1] * x[q + 1];
-      }
-      x[i] = (i == r) ? T(1) : -(s0 + s1);  // zero above the diagonal follows from x[q] = 0, q < r
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
+    for (int i = 0; i < kTile; ++i) aux[i * kTile + r] = xs[i];  // L^{-1}[i][r]
   } else {
 #pragma unroll
-    for (int i = kTile - 1; i >= 0; --i) {
-      T s0 = T(0), s1 = T(0);
-#pragma unroll
-      for (int q = i + 1; q < kTile; q += 2) {
-        s0 += sP[i][q] * x[q];
-        if (q + 1 < kTile) s1 += sP[i][q + 1] * x[q + 1];
-      }
-      x[i] = (i > r) ? T(0) : (((i == r) ? T(1) : T(0)) - (s0 + s1)) / sP[i][i];
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
+    for (int i = 0; i < kTile; ++i) aux[kTile * kTile + r * kTile + i] = xs[i];  // U^{-1}[r][i]
   }
-  T* aux = static_cast<T*>(it.aux) + half * kTile * kTile;
-#pragma unroll
-  for (int i = 0; i < kTile; ++i) aux[i * kTile + r] = x[i];
 }
 
 // ---------------------------------------------------------------------------

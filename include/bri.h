@@ -81,7 +81,9 @@ typedef struct {
   int concurrency;         /* W: Schur operations evaluated side by side; <= 0: auto  */
   int pivoting;            /* a bri_pivoting value                                    */
   int refine_max_iters;    /* mixed paths: refinement sweeps (0 = none)               */
-  double refine_tol;       /* mixed paths: stop when ||dX||_F <= tol * ||X||_F        */
+  double refine_tol;       /* mixed paths: stop when the correction dX_t, or from the
+                              second sweep the bound rho/(1-rho) ||dX_t||_F with
+                              rho = ||dX_t|| / ||dX_{t-1}|| < 1/2, is <= tol ||X||_F   */
   void* workspace;         /* device workspace, >= bri_workspace_size() bytes         */
   size_t workspace_bytes;  /* its size                                                */
   int32_t* d_info;         /* device int32 status (see above), or NULL                */
@@ -120,8 +122,17 @@ int bri_block_column(const void* M, int64_t n, int64_t ldm, int k, int j, int tr
 
 /* Batched form: count independent problems (M[t], n[t], k[t], i[t], j[t]) ->
  * out[t]; all arrays are HOST arrays (of device pointers where pointers).  All
- * problems share one workspace of bri_batched_workspace_size() bytes and are
- * evaluated together.  d_info, if not NULL, points to count device int32s. */
+ * problems share one workspace of bri_batched_workspace_size() bytes (its size
+ * depends on the precision and pivoting in *o).  d_info, if not NULL, points
+ * to count device int32s (one status per problem).  With BRI_F64 / BRI_F32
+ * and tile pivoting the problems are merged: problems whose plans have the
+ * same step structure (same k, diagonal or off-diagonal target) share every
+ * kernel launch, each work item carrying its own block order b = ceil(n/k)
+ * (Section "Block Recursive Inversion algorithm" per problem; the paper's
+ * remark that blocks can be computed in an embarrassingly parallel fashion,
+ * Section "Conclusion").  Other precisions and panel pivoting evaluate the
+ * problems one after another on the stream.  Argument codes: -p for argument
+ * p of this signature when any problem's entry is invalid. */
 size_t bri_batched_workspace_size(int count, const int64_t* n, const int* k, const int* i,
                                   const int* j, const bri_opts* o);
 int invert_block_batched(int count, const void* const* M, const int64_t* n, const int64_t* ldm,

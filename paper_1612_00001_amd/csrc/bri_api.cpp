@@ -252,78 +252,103 @@ GemmItem gemm_base(const Ctx& c) {
   return g;
 }
 
-void build_descriptors(const Ctx& c, const Plan& p, char* host, std::vector<int>& nfast) {
-  nfast.assign(p.steps.size(), 0);
+// Work descriptors of one plan step for context c, appended to the vectors
+// (product items split into those the fast kernel instance takes and the rest).
+struct StepItems {
+  std::vector<LoadItem> loads;
+  std::vector<LuItem> lus;
   std::vector<GemmItem> fast, slow;
-  for (size_t si = 0; si < p.steps.size(); ++si) {
-    const Step& s = p.steps[si];
-    char* base = host + c.lay->step_off[si];
+  void clear() {
+    loads.clear();
+    lus.clear();
     fast.clear();
     slow.clear();
-    for (size_t t = 0; t < s.items.size(); ++t) {
-      const StepItem& it = s.items[t];
-      switch (s.kind) {
-        case ST_LOAD: {
-          LoadItem li;
-          std::memset(&li, 0, sizeof(li));
-          li.src = resolve(c, it.x);
-          li.dst = dst_ptr(c, it.dst, li.ldd);
-          li.rows = c.b;
-          li.cols = c.b;
-          std::memcpy(base + t * sizeof(LoadItem), &li, sizeof(li));
-          break;
-        }
-        case ST_GETRF:
-        case ST_TRTRI: {
-          LuItem lu;
-          std::memset(&lu, 0, sizeof(lu));
-          lu.a = slot_ptr(c, it.dst.a);
-          lu.perm = perm_ptr(c, it.dst.a);
-          lu.swaps = swap_ptr(c, it.dst.a);
-          lu.tmp = s.kind == ST_TRTRI ? slot_ptr(c, it.x.a) : nullptr;
-          lu.aux = aux_ptr(c, it.dst.a);
-          lu.node = it.node;
-          lu.b = c.b;
-          std::memcpy(base + t * sizeof(LuItem), &lu, sizeof(lu));
-          break;
-        }
-        default: {
-          GemmItem g = gemm_base(c);
-          g.out = dst_ptr(c, it.dst, g.ldo);
-          if (s.kind == ST_TRMM_L) {
-            g.A = slot_view(c, it.x.a, 1);
-            g.B = resolve(c, it.y);
-            g.B.rowperm = perm_ptr(c, it.x.a);
-            g.alpha = 1.0;
-          } else if (s.kind == ST_TRMM_U) {
-            g.A = slot_view(c, it.x.a, 2);
-            g.B = resolve(c, it.y);
-            g.alpha = 1.0;
-          } else {
-            g.A = resolve(c, it.x);
-            g.B = resolve(c, it.y);
-            if (it.cin.kind != OPND_NONE) {
-              g.Cin = resolve(c, it.cin);
-              g.has_cin = 1;
-              g.beta = 1.0;
-            }
-            if (it.sub.kind != OPND_NONE) {
-              g.Sub = resolve(c, it.sub);
-              g.has_sub = 1;
-            }
-            g.alpha = (s.kind == ST_GEMM_ACC) ? 1.0 : -1.0;
+  }
+  size_t count() const { return loads.size() + lus.size() + fast.size() + slow.size(); }
+  // Writes the items to dst (fast products first); returns the bytes written.
+  size_t write(char* dst) const {
+    size_t off = 0;
+    auto put = [&](const void* src, size_t bytes) {
+      std::memcpy(dst + off, src, bytes);
+      off += bytes;
+    };
+    put(loads.data(), loads.size() * sizeof(LoadItem));
+    put(lus.data(), lus.size() * sizeof(LuItem));
+    put(fast.data(), fast.size() * sizeof(GemmItem));
+    put(slow.data(), slow.size() * sizeof(GemmItem));
+    return off;
+  }
+};
+
+void describe_step(const Ctx& c, const Step& s, StepItems& out) {
+  for (const StepItem& it : s.items) {
+    switch (s.kind) {
+      case ST_LOAD: {
+        LoadItem li;
+        std::memset(&li, 0, sizeof(li));
+        li.src = resolve(c, it.x);
+        li.dst = dst_ptr(c, it.dst, li.ldd);
+        li.rows = c.b;
+        li.cols = c.b;
+        out.loads.push_back(li);
+        break;
+      }
+      case ST_GETRF:
+      case ST_TRTRI: {
+        LuItem lu;
+        std::memset(&lu, 0, sizeof(lu));
+        lu.a = slot_ptr(c, it.dst.a);
+        lu.perm = perm_ptr(c, it.dst.a);
+        lu.swaps = swap_ptr(c, it.dst.a);
+        lu.tmp = s.kind == ST_TRTRI ? slot_ptr(c, it.x.a) : nullptr;
+        lu.aux = aux_ptr(c, it.dst.a);
+        lu.info = c.info;
+        lu.node = it.node;
+        lu.b = c.b;
+        out.lus.push_back(lu);
+        break;
+      }
+      default: {
+        GemmItem g = gemm_base(c);
+        g.out = dst_ptr(c, it.dst, g.ldo);
+        if (s.kind == ST_TRMM_L) {
+          g.A = slot_view(c, it.x.a, 1);
+          g.B = resolve(c, it.y);
+          g.B.rowperm = perm_ptr(c, it.x.a);
+          g.alpha = 1.0;
+        } else if (s.kind == ST_TRMM_U) {
+          g.A = slot_view(c, it.x.a, 2);
+          g.B = resolve(c, it.y);
+          g.alpha = 1.0;
+        } else {
+          g.A = resolve(c, it.x);
+          g.B = resolve(c, it.y);
+          if (it.cin.kind != OPND_NONE) {
+            g.Cin = resolve(c, it.cin);
+            g.has_cin = 1;
+            g.beta = 1.0;
           }
-          (gemm_item_is_fast(g) ? fast : slow).push_back(g);
-          break;
+          if (it.sub.kind != OPND_NONE) {
+            g.Sub = resolve(c, it.sub);
+            g.has_sub = 1;
+          }
+          g.alpha = (s.kind == ST_GEMM_ACC) ? 1.0 : -1.0;
         }
+        (gemm_item_is_fast(g) ? out.fast : out.slow).push_back(g);
+        break;
       }
     }
-    if (!fast.empty() || !slow.empty()) {
-      // Fast items first; the generic instance takes the rest.
-      std::memcpy(base, fast.data(), fast.size() * sizeof(GemmItem));
-      std::memcpy(base + fast.size() * sizeof(GemmItem), slow.data(), slow.size() * sizeof(GemmItem));
-      nfast[si] = static_cast<int>(fast.size());
-    }
+  }
+}
+
+void build_descriptors(const Ctx& c, const Plan& p, char* host, std::vector<int>& nfast) {
+  nfast.assign(p.steps.size(), 0);
+  StepItems items;
+  for (size_t si = 0; si < p.steps.size(); ++si) {
+    items.clear();
+    describe_step(c, p.steps[si], items);
+    items.write(host + c.lay->step_off[si]);
+    nfast[si] = static_cast<int>(items.fast.size());
   }
 }
 
@@ -382,49 +407,60 @@ int64_t step_launches(const Step& s, int b) {
   }
 }
 
+// One step as launched: its kind, item count, fast product items, descriptor
+// address on the device and the step it stands for (for the profile record).
+struct ExecStep {
+  StepKind kind;
+  int count;
+  int nfast;
+  const void* desc;
+  const Step* step;
+  double flops;  // algorithmic flops of all items (profile record)
+};
+
+// Enqueues the kernels of the steps; bmax is the largest block order among
+// the items (merged batches mix orders; every kernel skips the parts of a
+// smaller matrix).
 template <typename T>
-int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
-  const char* dbase = c.ws + c.lay->desc_off;
+int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lp, hipStream_t st) {
   bool prof;
   {
     std::lock_guard<std::mutex> g(g_prof_mu);
     prof = g_prof_on;
   }
-  for (size_t si = 0; si < p.steps.size(); ++si) {
-    const Step& s = p.steps[si];
-    const void* d = dbase + c.lay->step_off[si];
-    const int count = static_cast<int>(s.items.size());
+  for (const ExecStep& s : steps) {
+    if (s.count <= 0) continue;
     hipError_t e = hipSuccess;
     ProfRecord rec{};
     if (prof) {
       std::lock_guard<std::mutex> g(g_prof_mu);
       rec.kind = s.kind;
-      rec.launches = step_launches(s, c.b);
-      rec.flops = step_flops(s, c.b);
+      rec.launches = step_launches(*s.step, bmax);
+      rec.flops = s.flops;
       rec.e0 = prof_event();
       rec.e1 = prof_event();
       if (!rec.e0 || !rec.e1 || hipEventRecord(rec.e0, st) != hipSuccess) return BRI_ERR_HIP;
     }
     switch (s.kind) {
       case ST_LOAD:
-        e = launch_load<T>(static_cast<const LoadItem*>(d), count, c.b, c.b, st);
+        e = launch_load<T>(static_cast<const LoadItem*>(s.desc), s.count, bmax, bmax, st);
         break;
       case ST_GETRF:
-        e = c.pivoting == BRI_PIVOT_PANEL ? launch_getrf<T>(static_cast<const LuItem*>(d), count, c.b, c.info, st)
-                                          : launch_getrf_tile<T>(static_cast<const LuItem*>(d), count, c.b, c.info, st);
+        e = pivoting == BRI_PIVOT_PANEL ? launch_getrf<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st)
+                                        : launch_getrf_tile<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
         break;
       case ST_TRTRI:
-        e = launch_trtri<T>(static_cast<const LuItem*>(d), count, c.b, st);
+        e = launch_trtri<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
         break;
       default: {
         GemmLaunch L{};
         L.mode = GEMM_EXPLICIT;
         L.elem = sizeof(T);
-        L.items = d;
-        L.count = count;
-        L.w = c.lay->nfast[si];
-        L.lp = c.lp;
-        e = launch_gemm<T>(L, c.b, c.b, st);
+        L.items = s.desc;
+        L.count = s.count;
+        L.w = s.nfast;
+        L.lp = lp;
+        e = launch_gemm<T>(L, bmax, bmax, st);
         break;
       }
     }
@@ -436,6 +472,19 @@ int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
     }
   }
   return BRI_OK;
+}
+
+template <typename T>
+int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
+  const char* dbase = c.ws + c.lay->desc_off;
+  std::vector<ExecStep> ex;
+  ex.reserve(p.steps.size());
+  for (size_t si = 0; si < p.steps.size(); ++si) {
+    const Step& s = p.steps[si];
+    ex.push_back(ExecStep{s.kind, static_cast<int>(s.items.size()), c.lay->nfast[si], dbase + c.lay->step_off[si], &s,
+                          step_flops(s, c.b)});
+  }
+  return run_exec<T>(ex, c.b, c.pivoting, c.lp, st);
 }
 
 // Uploads the descriptors of plan cp for context c and enqueues its kernels.
@@ -642,11 +691,13 @@ int invert_block_mixed(const void* M, int64_t n, int64_t ldm, int k, int i, int 
   if (launch_refine_update(X, D, cnt, scal, 1, st) != hipSuccess) return BRI_ERR_HIP;
 
   // Sweeps: R = E_j - Gamma X (FP64), D = (sigma Gamma)^{-1} (s R) by the float
-  // solve plan, X += (sigma / s) D, until ||dX||_F <= tol ||X||_F.
+  // solve plan, X += (sigma / s) D, until the error of X is below tol ||X||_F
+  // (see the convergence test below).
   bool converged = o->refine_max_iters <= 0;
   const double tol = o->refine_tol;
   t_last_sweeps = 0;
   t_last_update = 0.0;
+  double prev_upd = 0.0;
   for (int it = 0; it < o->refine_max_iters; ++it) {
     if (launch_scal_clear(scal, 1, 4, st) != hipSuccess) return BRI_ERR_HIP;
     GemmLaunch L{};
@@ -669,7 +720,17 @@ int invert_block_mixed(const void* M, int64_t n, int64_t ldm, int k, int i, int 
     t_last_sweeps = it + 1;
     t_last_update = xx > 0 ? std::sqrt(dd / xx) : dd;
     if (!std::isfinite(dd) || !std::isfinite(xx)) break;
-    if (dd <= tol * tol * xx) {
+    // Converged when the correction itself is below tol, or, from the second
+    // sweep on, when the observed contraction rho = ||dX_t|| / ||dX_{t-1}||
+    // bounds the remaining error, rho / (1 - rho) ||dX_t||, below tol.
+    const double upd = std::sqrt(dd), lim = tol * std::sqrt(xx);
+    bool done = upd <= lim;
+    if (!done && prev_upd > 0) {
+      const double rho = upd / prev_upd;
+      done = rho < 0.5 && rho / (1.0 - rho) * upd <= lim;
+    }
+    prev_upd = upd;
+    if (done) {
       converged = true;
       break;
     }
@@ -679,6 +740,144 @@ int invert_block_mixed(const void* M, int64_t n, int64_t ldm, int k, int i, int 
   if (!converged && launch_info_unconverged(info, st) != hipSuccess) return BRI_ERR_HIP;
   return BRI_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Merged batches: problems whose plans have the same step structure (same k,
+// same kind of target, same width) share every launch; each work item carries
+// its own block order, operands and status word.
+// ---------------------------------------------------------------------------
+bool same_structure(const Plan& a, const Plan& b) {
+  if (a.steps.size() != b.steps.size()) return false;
+  for (size_t s = 0; s < a.steps.size(); ++s)
+    if (a.steps[s].kind != b.steps[s].kind || a.steps[s].items.size() != b.steps[s].items.size()) return false;
+  return true;
+}
+
+int merged_width(int k) { return static_cast<int>(std::min<int64_t>(16, leaves_of(k))); }
+
+struct BatchPlan {
+  std::vector<std::shared_ptr<CachedPlan>> plans;  // per problem
+  std::vector<size_t> region;                      // per problem: offset of its slot region
+  std::vector<std::vector<int>> groups;            // problems of every merged group
+  std::vector<std::vector<size_t>> step_desc;      // per group and step: descriptor offset
+  size_t info_off = 0, desc_off = 0, desc_bytes = 0, total = 0;
+};
+
+BatchPlan make_batch_plan(int count, const int64_t* n, const int* k, const int* i, const int* j, int elem) {
+  BatchPlan bp;
+  bp.plans.resize(count);
+  bp.region.resize(count);
+  std::map<std::pair<int, int>, std::vector<int>> by_key;  // (k, diagonal target) -> groups
+  for (int t = 0; t < count; ++t) {
+    bp.plans[t] = get_plan(0, n[t], k[t], i[t], j[t], merged_width(k[t]), elem, 0);
+    std::vector<int>& cands = by_key[{k[t], i[t] == j[t] ? 1 : 0}];
+    int g = -1;
+    for (int c : cands)
+      if (same_structure(bp.plans[bp.groups[c][0]]->plan, bp.plans[t]->plan)) g = c;
+    if (g < 0) {
+      g = static_cast<int>(bp.groups.size());
+      bp.groups.emplace_back();
+      cands.push_back(g);
+    }
+    bp.groups[g].push_back(t);
+  }
+  size_t off = 0;
+  for (int t = 0; t < count; ++t) {
+    bp.region[t] = off;
+    off += align_up(bp.plans[t]->layout.desc_off);  // slots, permutations, tile scratch, status
+  }
+  bp.info_off = off;
+  off += kAlign;
+  bp.desc_off = off;
+  size_t d = 0;
+  for (const std::vector<int>& grp : bp.groups) {
+    const Plan& p0 = bp.plans[grp[0]]->plan;
+    bp.step_desc.emplace_back();
+    for (size_t si = 0; si < p0.steps.size(); ++si) {
+      bp.step_desc.back().push_back(d);
+      d += align_up(item_bytes(p0.steps[si].kind) * p0.steps[si].items.size() * grp.size());
+    }
+  }
+  bp.desc_bytes = d;
+  bp.total = off + d;
+  return bp;
+}
+
+template <typename T>
+int run_batch(const BatchPlan& bp, const void* const* M, const int64_t* n, const int64_t* ldm, void* const* out,
+              const int64_t* ldo, int count, const bri_opts* o) {
+  hipStream_t st = o->stream;
+  char* ws = static_cast<char*>(o->workspace);
+  int32_t* shared_info = reinterpret_cast<int32_t*>(ws + bp.info_off);
+  static std::mutex mu;
+  static void* host = nullptr;
+  static size_t host_bytes = 0;
+  static hipEvent_t ev = nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (ev && hipEventSynchronize(ev) != hipSuccess) return BRI_ERR_HIP;
+  if (host_bytes < bp.desc_bytes) {
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+    host_bytes = 0;
+    if (hipHostMalloc(&host, bp.desc_bytes) != hipSuccess) return BRI_ERR_HIP;
+    host_bytes = bp.desc_bytes;
+  }
+  if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return BRI_ERR_HIP;
+  std::vector<Ctx> ctx(count);
+  for (int t = 0; t < count; ++t) {
+    Ctx& c = ctx[t];
+    c.pivoting = BRI_PIVOT_TILE;
+    c.M = static_cast<const char*>(M[t]);
+    c.n = n[t];
+    c.ldm = ldm[t];
+    c.b = bp.plans[t]->plan.b;
+    c.elem = sizeof(T);
+    c.ws = ws + bp.region[t];
+    c.lay = &bp.plans[t]->layout;
+    c.out = static_cast<char*>(out[t]);
+    c.ldo = ldo[t];
+    c.info = o->d_info ? o->d_info + t : shared_info;
+  }
+  std::vector<std::vector<ExecStep>> exec(bp.groups.size());
+  std::vector<int> bmax(bp.groups.size(), 0);
+  StepItems items;
+  try {
+    for (size_t g = 0; g < bp.groups.size(); ++g) {
+      const std::vector<int>& grp = bp.groups[g];
+      const Plan& p0 = bp.plans[grp[0]]->plan;
+      for (int t : grp) bmax[g] = std::max(bmax[g], ctx[t].b);
+      for (size_t si = 0; si < p0.steps.size(); ++si) {
+        items.clear();
+        double flops = 0;
+        for (int t : grp) {
+          const Step& s = bp.plans[t]->plan.steps[si];
+          describe_step(ctx[t], s, items);
+          flops += step_flops(s, ctx[t].b);
+        }
+        items.write(static_cast<char*>(host) + bp.step_desc[g][si]);
+        exec[g].push_back(ExecStep{p0.steps[si].kind, static_cast<int>(items.count()),
+                                   static_cast<int>(items.fast.size()), ws + bp.desc_off + bp.step_desc[g][si],
+                                   &p0.steps[si], flops});
+      }
+    }
+  } catch (const std::exception&) {
+    return BRI_ERR_UNSUPPORTED;
+  }
+  if (hipMemcpyAsync(ws + bp.desc_off, host, bp.desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return BRI_ERR_HIP;
+  if (hipEventRecord(ev, st) != hipSuccess) return BRI_ERR_HIP;
+  if (launch_fill_int(o->d_info ? o->d_info : shared_info, o->d_info ? count : 1, 0, st) != hipSuccess)
+    return BRI_ERR_HIP;
+  for (size_t g = 0; g < bp.groups.size(); ++g) {
+    const int rc = run_exec<T>(exec[g], bmax[g], BRI_PIVOT_TILE, 0, st);
+    if (rc != BRI_OK) return rc;
+  }
+  return BRI_OK;
+}
+
+// Merged execution needs plain precision and tile pivoting (the panel
+// pivoting kernels assume one block order per launch; the mixed path
+// synchronises per refinement sweep).
+bool batch_mergeable(const bri_opts* o) { return plain_precision(o->precision) && o->pivoting == BRI_PIVOT_TILE; }
 
 }  // namespace
 }  // namespace bri
@@ -926,9 +1125,26 @@ int bri_block_column(const void* M, int64_t n, int64_t ldm, int k, int j, int tr
   return execute(*cp, c, o->stream, true);
 }
 
+static int check_batch_args(int count, const int64_t* n, const int* k, const int* i, const int* j) {
+  for (int t = 0; t < count; ++t) {
+    const int rc = check_block_args(n[t], n[t], k[t], i[t], j[t], (n[t] + k[t] - 1) / k[t]);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
 size_t bri_batched_workspace_size(int count, const int64_t* n, const int* k, const int* i, const int* j,
                                   const bri_opts* o) {
   if (count < 0 || !n || !k || !i || !j || !o) return 0;
+  if (check_batch_args(count, n, k, i, j) != 0) return 0;
+  if (count == 0) return kAlign;
+  if (batch_mergeable(o)) {
+    try {
+      return make_batch_plan(count, n, k, i, j, elem_size(o->precision)).total;
+    } catch (const std::exception&) {
+      return 0;
+    }
+  }
   size_t m = 0;
   for (int t = 0; t < count; ++t) {
     const size_t s = bri_workspace_size(n[t], k[t], i[t], j[t], o);
@@ -950,6 +1166,24 @@ int invert_block_batched(int count, const void* const* M, const int64_t* n, cons
   if (!out) return -8;
   if (!ldo) return -9;
   if (!o) return -10;
+  if (count == 0) return BRI_OK;
+  for (int t = 0; t < count; ++t) {
+    if (!M[t]) return -2;
+    if (!out[t]) return -8;
+    const int rc = check_block_args(n[t], ldm[t], k[t], i[t], j[t], ldo[t]);
+    if (rc) return rc == -2 ? -3 : rc == -3 ? -4 : rc == -4 ? -5 : rc == -5 ? -6 : rc == -6 ? -7 : rc == -8 ? -9 : rc;
+  }
+  if (batch_mergeable(o)) {
+    BatchPlan bp;
+    try {
+      bp = make_batch_plan(count, n, k, i, j, elem_size(o->precision));
+    } catch (const std::exception&) {
+      return BRI_ERR_UNSUPPORTED;
+    }
+    if (!o->workspace || o->workspace_bytes < bp.total) return BRI_ERR_WORKSPACE;
+    return o->precision == BRI_F64 ? run_batch<double>(bp, M, n, ldm, out, ldo, count, o)
+                                   : run_batch<float>(bp, M, n, ldm, out, ldo, count, o);
+  }
   for (int t = 0; t < count; ++t) {
     bri_opts ot = *o;
     ot.d_info = o->d_info ? o->d_info + t : nullptr;

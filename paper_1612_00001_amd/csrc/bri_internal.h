@@ -45,7 +45,8 @@ struct LuItem {
   int32_t* swaps;    // per-panel list of moved rows: [count, (dest, src) ...]
   void* tmp;         // b x b scratch for the triangular inversion
   void* aux;         // 2 kTile^2 elements: inverses of the current diagonal tile's L and U
-  int32_t node;      // Schur operation index reported through d_info
+  int32_t* info;     // device status word of the problem this matrix belongs to (or null)
+  int32_t node;      // Schur operation index reported through *info
   int32_t b;
 };
 

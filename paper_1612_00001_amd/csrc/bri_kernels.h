@@ -10,9 +10,9 @@ namespace bri {
 template <typename T>
 hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st);
 template <typename T>
-hipError_t launch_getrf(const LuItem* d_items, int count, int b, int32_t* info, hipStream_t st);
+hipError_t launch_getrf(const LuItem* d_items, int count, int b, hipStream_t st);
 template <typename T>
-hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, int32_t* info, hipStream_t st);
+hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, hipStream_t st);
 template <typename T>
 hipError_t launch_trtri(const LuItem* d_items, int count, int b, hipStream_t st);
 template <typename T>

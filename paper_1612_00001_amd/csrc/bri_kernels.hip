@@ -800,7 +800,7 @@ __device__ __forceinline__ void panel_step(T (&a)[R][NB], int (&orig)[R], PanelS
 }
 
 template <typename T, int NB, int R>
-__global__ __launch_bounds__(512) void k_getf2(const LuItem* items, int j, int32_t* info) {
+__global__ __launch_bounds__(512) void k_getf2(const LuItem* items, int j) {
   constexpr int NT = 512;
   const LuItem it = items[blockIdx.x];
   T* A = static_cast<T*>(it.a);
@@ -819,7 +819,7 @@ __global__ __launch_bounds__(512) void k_getf2(const LuItem* items, int j, int32
       a[q][c] = (lr < h && c < w) ? A[static_cast<int64_t>(j + lr) * b + j + c] : T(0);
   }
   if (tid == 0) sh.cnt = 0;
-  for (int C = 0; C < w; ++C) panel_step<T, NB, R, NT>(a, orig, sh, C, h, tid, info, it.node);
+  for (int C = 0; C < w; ++C) panel_step<T, NB, R, NT>(a, orig, sh, C, h, tid, it.info, it.node);
   __syncthreads();
 
   // Write the factored panel back and record the moved rows.
@@ -932,9 +932,10 @@ __device__ __forceinline__ int half_argmax(uint64_t k, int h) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0, int32_t* info) {
+__global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
   constexpr int LD = kTile + 2;
   const LuItem it = items[blockIdx.x];
+  if (t0 >= it.b) return;  // a smaller matrix of a merged batch
   T* A = static_cast<T*>(it.a);
   const int b = it.b, ts = min(kTile, b - t0);
   const int l = threadIdx.x, r = l & 31, half = l >> 5;
@@ -995,7 +996,7 @@ __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0, int
     yc = z;
     p = pn;
   }
-  if (bad && l == 0 && info) atomicCAS(info, 0, it.node + 1);
+  if (bad && l == 0 && it.info) atomicCAS(it.info, 0, it.node + 1);
   __syncthreads();
   // Factored row in pivot order: multipliers left of its pivot column, U
   // from there on (rows past the tile edge are identity rows).
@@ -1053,6 +1054,7 @@ __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0, int
 template <typename T>
 __global__ __launch_bounds__(256) void k_tile_strips(const LuItem* items, int t0) {
   const LuItem it = items[blockIdx.y];
+  if (t0 >= it.b) return;  // a smaller matrix of a merged batch
   T* A = static_cast<T*>(it.a);
   const int b = it.b, ts = min(kTile, b - t0), tid = threadIdx.x;
   const int rest = b - t0 - ts;
@@ -1295,10 +1297,10 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
 }
 
 template <typename T>
-hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, int32_t* info, hipStream_t st) {
+hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, hipStream_t st) {
   for (int t0 = 0; t0 < b; t0 += kTile) {
     const int ts = std::min(kTile, b - t0);
-    hipLaunchKernelGGL((k_tile_lu<T>), dim3(count), dim3(64), 0, st, d_items, t0, info);
+    hipLaunchKernelGGL((k_tile_lu<T>), dim3(count), dim3(64), 0, st, d_items, t0);
     const int rest = b - t0 - ts;
     const int nblk = 2 * cdiv(rest, 64) + cdiv(t0, 64);
     if (nblk > 0) hipLaunchKernelGGL((k_tile_strips<T>), dim3(nblk, count), dim3(256), 0, st, d_items, t0);
@@ -1318,19 +1320,19 @@ hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, int32_t* i
 }
 
 template <typename T>
-hipError_t launch_getrf(const LuItem* d_items, int count, int b, int32_t* info, hipStream_t st) {
+hipError_t launch_getrf(const LuItem* d_items, int count, int b, hipStream_t st) {
   for (int j = 0; j < b;) {
     const int h = b - j;
     const int nb = panel_width(h);
     const int w = nb < h ? nb : h;
     if (h <= 512) {
-      hipLaunchKernelGGL((k_getf2<T, 32, 1>), dim3(count), dim3(512), 0, st, d_items, j, info);
+      hipLaunchKernelGGL((k_getf2<T, 32, 1>), dim3(count), dim3(512), 0, st, d_items, j);
     } else if (h <= 1024) {
-      hipLaunchKernelGGL((k_getf2<T, 32, 2>), dim3(count), dim3(512), 0, st, d_items, j, info);
+      hipLaunchKernelGGL((k_getf2<T, 32, 2>), dim3(count), dim3(512), 0, st, d_items, j);
     } else if (h <= 2048) {
-      hipLaunchKernelGGL((k_getf2<T, 16, 4>), dim3(count), dim3(512), 0, st, d_items, j, info);
+      hipLaunchKernelGGL((k_getf2<T, 16, 4>), dim3(count), dim3(512), 0, st, d_items, j);
     } else {
-      hipLaunchKernelGGL((k_getf2<T, 8, 8>), dim3(count), dim3(512), 0, st, d_items, j, info);
+      hipLaunchKernelGGL((k_getf2<T, 8, 8>), dim3(count), dim3(512), 0, st, d_items, j);
     }
     if (j > 0 || j + w < b) {
       dim3 grid(cdiv(b, 128), count);
@@ -1394,10 +1396,10 @@ hipError_t launch_fill_int(int32_t* p, int n, int v, hipStream_t st) {
 
 template hipError_t launch_gemm<double>(const GemmLaunch&, int, int, hipStream_t);
 template hipError_t launch_gemm<float>(const GemmLaunch&, int, int, hipStream_t);
-template hipError_t launch_getrf<double>(const LuItem*, int, int, int32_t*, hipStream_t);
-template hipError_t launch_getrf_tile<double>(const LuItem*, int, int, int32_t*, hipStream_t);
-template hipError_t launch_getrf_tile<float>(const LuItem*, int, int, int32_t*, hipStream_t);
-template hipError_t launch_getrf<float>(const LuItem*, int, int, int32_t*, hipStream_t);
+template hipError_t launch_getrf<double>(const LuItem*, int, int, hipStream_t);
+template hipError_t launch_getrf_tile<double>(const LuItem*, int, int, hipStream_t);
+template hipError_t launch_getrf_tile<float>(const LuItem*, int, int, hipStream_t);
+template hipError_t launch_getrf<float>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_trtri<double>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_trtri<float>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_load<double>(const LoadItem*, int, int, int, hipStream_t);

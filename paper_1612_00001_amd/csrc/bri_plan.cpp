@@ -637,23 +637,27 @@ void build_column(Builder& B, const std::vector<int>& order, int j, std::vector<
   }
   for (int pos = k - 2; pos >= 0; --pos) {
     const int q = order[pos];
-    int acc = pool.alloc();
-    bool first = true;
     std::vector<int> later(order.begin() + pos + 1, order.end());
     later.insert(later.begin(), j);
-    for (int t : later) {
-      const int sv = B.value(q, t, pos);
+    // All values of this position have depth pos: one lock-step batch
+    // (pivot last); at depth 0 they are blocks of Gamma read in place.
+    std::vector<Node> nodes;
+    for (int t : later) nodes.push_back(Node{q, t, pos});
+    nodes.push_back(Node{q, q, pos});
+    std::vector<int> sv(nodes.size(), -1);
+    if (pos > 0) sv = B.eval_children(nodes);
+    int acc = pool.alloc();
+    for (size_t u = 0; u < later.size(); ++u) {
       Step& g = B.step(ST_GEMM);
       StepItem it;
       it.dst = Opnd::slot(acc);
-      it.x = Opnd::slot(sv);
-      it.y = Opnd::out_blk(t);
-      it.cin = first ? Opnd::none() : Opnd::slot(acc);
+      it.x = pos > 0 ? Opnd::slot(sv[u]) : Opnd::mblk(q, later[u]);
+      it.y = Opnd::out_blk(later[u]);
+      it.cin = u == 0 ? Opnd::none() : Opnd::slot(acc);
       g.items.push_back(it);
-      first = false;
-      pool.release(sv);
+      if (pos > 0) pool.release(sv[u]);
     }
-    const int sq = B.value(q, q, pos);
+    const int sq = pos > 0 ? sv.back() : B.value(q, q, 0);
     B.factor_only({sq});
     plan.schur_ops--;  // the back-substitution pivots are inversions, not Schur steps
     plan.final_inversions++;
@@ -706,17 +710,22 @@ RefinePlans make_refine_plans(int64_t n, int k, int j, int width) {
   order.push_back(j);
   for (int pos = k - 1; pos >= 0; --pos) {
     const int q = order[pos];
-    const int acc = S.value(q, k, pos);
+    // Every value of this position in one lock-step batch (the right-hand
+    // side first); at depth 0 they are read in place.
+    std::vector<Node> nodes{Node{q, k, pos}};
+    for (int t = pos + 1; t < k; ++t) nodes.push_back(Node{q, order[t], pos});
+    std::vector<int> sv(nodes.size(), -1);
+    if (pos > 0) sv = S.eval_children(nodes);
+    const int acc = pos > 0 ? sv[0] : S.value(q, k, 0);
     for (int t = pos + 1; t < k; ++t) {
-      const int sv = S.value(q, order[t], pos);
       Step& g = S.step(ST_GEMM);
       StepItem it;
       it.dst = Opnd::slot(acc);
-      it.x = Opnd::slot(sv);
+      it.x = pos > 0 ? Opnd::slot(sv[t - pos]) : Opnd::mblk(q, order[t]);
       it.y = Opnd::out_blk(order[t]);
       it.cin = Opnd::slot(acc);
       g.items.push_back(it);
-      pool.release(sv);
+      if (pos > 0) pool.release(sv[t - pos]);
     }
     S.solve_with({rp.kept[pos]}, {Opnd::slot(acc)}, {Opnd::out_blk(q)});
     pool.release(acc);

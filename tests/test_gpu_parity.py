@@ -196,3 +196,30 @@ def test_batched_mixed_problems():
     for p, o in zip(probs, outs):
         want = oracle.invert_block(workloads.batch_matrix(p), p.k, p.i, p.j)
         assert rel(o.cpu().numpy(), want) < 1e-12, (p.n, p.k, p.i, p.j)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batched_512_problems_merged(precision):
+    # The batched workload: 512 problems, n in [64, 1024], k in {2, 3, 4},
+    # random target, Gaussian + n I, merged launches.  Every block is checked
+    # against the dense inverse of its (augmented) matrix.
+    probs = workloads.batch_problems()
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    mats = [workloads.batch_matrix(p) for p in probs]
+    Ms = [gpu(m, dtype) for m in mats]
+    info = torch.zeros(len(probs), dtype=torch.int32, device=DEV)
+    print(f"batched 512 problems {precision}", flush=True)
+    outs = bri.invert_block_batched(Ms, [p.k for p in probs], [p.i for p in probs], [p.j for p in probs],
+                                    precision=precision, info=info)
+    torch.cuda.synchronize()
+    assert int(info.abs().sum().item()) == 0
+    worst = 0.0
+    for p, m, o in zip(probs, mats, outs):
+        b = -(-p.n // p.k)
+        g = np.eye(p.k * b)
+        g[:p.n, :p.n] = m
+        want = np.linalg.inv(g)[p.i * b:(p.i + 1) * b, p.j * b:(p.j + 1) * b]
+        err = rel(o.double().cpu().numpy(), want)
+        worst = max(worst, err)
+    print(f"  worst rel err {worst:.2e}", flush=True)
+    assert worst < (1e-12 if precision == "f64" else 64 * EPS32 * 2)

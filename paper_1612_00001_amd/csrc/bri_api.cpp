@@ -519,18 +519,209 @@ bool mixed_precision(int p) { return p == BRI_MIXED_F32 || p == BRI_MIXED_F16 ||
 int lp_of(int p) { return p == BRI_MIXED_F16 ? 1 : (p == BRI_MIXED_BF16 ? 2 : 0); }
 
 // ---------------------------------------------------------------------------
+// Pinned staging buffer for the descriptors of batched and mixed calls
+// (grown on demand; the event guards reuse while an upload is in flight).
+// ---------------------------------------------------------------------------
+struct Staging {
+  std::mutex mu;
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t ev = nullptr;
+  // Call with mu held.  Returns nullptr on a HIP failure.
+  char* get(size_t need) {
+    if (ev && hipEventSynchronize(ev) != hipSuccess) return nullptr;
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (bytes < need) {
+      if (host) (void)hipHostFree(host);
+      host = nullptr;
+      bytes = 0;
+      if (hipHostMalloc(&host, std::max<size_t>(need, 4096)) != hipSuccess) return nullptr;
+      bytes = std::max<size_t>(need, 4096);
+    }
+    return static_cast<char*>(host);
+  }
+};
+Staging& staging() {
+  static Staging s;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Merging plans: members whose plans have the same step structure form a
+// group; every step of a group is one launch over the items of all members,
+// each item carrying its own block order, operands and status word.
+// ---------------------------------------------------------------------------
+bool same_structure(const Plan& a, const Plan& b) {
+  if (a.steps.size() != b.steps.size()) return false;
+  for (size_t s = 0; s < a.steps.size(); ++s)
+    if (a.steps[s].kind != b.steps[s].kind || a.steps[s].items.size() != b.steps[s].items.size()) return false;
+  return true;
+}
+
+struct MergedLayout {
+  std::vector<std::vector<int>> groups;       // member indices of every group
+  std::vector<std::vector<size_t>> step_off;  // per group and step: descriptor offset
+  size_t bytes = 0;
+};
+
+MergedLayout merge_layout(const std::vector<const Plan*>& plans) {
+  MergedLayout m;
+  std::map<size_t, std::vector<int>> by_len;  // step count -> candidate groups
+  for (int t = 0; t < static_cast<int>(plans.size()); ++t) {
+    std::vector<int>& cands = by_len[plans[t]->steps.size()];
+    int g = -1;
+    for (int c : cands)
+      if (same_structure(*plans[m.groups[c][0]], *plans[t])) g = c;
+    if (g < 0) {
+      g = static_cast<int>(m.groups.size());
+      m.groups.emplace_back();
+      cands.push_back(g);
+    }
+    m.groups[g].push_back(t);
+  }
+  size_t d = 0;
+  for (const std::vector<int>& grp : m.groups) {
+    const Plan& p0 = *plans[grp[0]];
+    m.step_off.emplace_back();
+    for (const Step& st : p0.steps) {
+      m.step_off.back().push_back(d);
+      d += align_up(item_bytes(st.kind) * st.items.size() * grp.size());
+    }
+  }
+  m.bytes = d;
+  return m;
+}
+
+struct MergedExec {
+  std::vector<std::vector<ExecStep>> groups;
+  std::vector<int> bmax;
+};
+
+// Writes the merged descriptors to host (device copy at dev) and returns the
+// steps to launch.  Throws on operands that cannot be resolved.
+MergedExec merge_write(const std::vector<const Plan*>& plans, const std::vector<Ctx>& ctx, const MergedLayout& m,
+                       char* host, const char* dev) {
+  MergedExec ex;
+  StepItems items;
+  for (size_t g = 0; g < m.groups.size(); ++g) {
+    const std::vector<int>& grp = m.groups[g];
+    const Plan& p0 = *plans[grp[0]];
+    int bmax = 0;
+    for (int t : grp) bmax = std::max(bmax, ctx[t].b);
+    ex.bmax.push_back(bmax);
+    ex.groups.emplace_back();
+    for (size_t si = 0; si < p0.steps.size(); ++si) {
+      items.clear();
+      double flops = 0;
+      for (int t : grp) {
+        const Step& st = plans[t]->steps[si];
+        describe_step(ctx[t], st, items);
+        flops += step_flops(st, ctx[t].b);
+      }
+      items.write(host + m.step_off[g][si]);
+      ex.groups.back().push_back(ExecStep{p0.steps[si].kind, static_cast<int>(items.count()),
+                                          static_cast<int>(items.fast.size()), dev + m.step_off[g][si],
+                                          &p0.steps[si], flops});
+    }
+  }
+  return ex;
+}
+
+template <typename T>
+int run_merged(const MergedExec& ex, int pivoting, int lp, hipStream_t st) {
+  for (size_t g = 0; g < ex.groups.size(); ++g) {
+    const int rc = run_exec<T>(ex.groups[g], ex.bmax[g], pivoting, lp, st);
+    if (rc != BRI_OK) return rc;
+  }
+  return BRI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plain precisions, batched (tile pivoting): merged block plans.
+// ---------------------------------------------------------------------------
+int merged_width(int k) { return static_cast<int>(std::min<int64_t>(16, leaves_of(k))); }
+
+struct BatchPlan {
+  std::vector<std::shared_ptr<CachedPlan>> plans;  // per problem
+  std::vector<size_t> region;                      // per problem: offset of its slot region
+  MergedLayout merged;
+  size_t info_off = 0, desc_off = 0, total = 0;
+};
+
+BatchPlan make_batch_plan(int count, const int64_t* n, const int* k, const int* i, const int* j, int elem) {
+  BatchPlan bp;
+  bp.plans.resize(count);
+  bp.region.resize(count);
+  std::vector<const Plan*> pl(count);
+  size_t off = 0;
+  for (int t = 0; t < count; ++t) {
+    bp.plans[t] = get_plan(0, n[t], k[t], i[t], j[t], merged_width(k[t]), elem, 0);
+    pl[t] = &bp.plans[t]->plan;
+    bp.region[t] = off;
+    off += align_up(bp.plans[t]->layout.desc_off);  // slots, permutations, tile scratch, status
+  }
+  bp.merged = merge_layout(pl);
+  bp.info_off = off;
+  off += kAlign;
+  bp.desc_off = off;
+  bp.total = off + bp.merged.bytes;
+  return bp;
+}
+
+template <typename T>
+int run_batch(const BatchPlan& bp, const void* const* M, const int64_t* n, const int64_t* ldm, void* const* out,
+              const int64_t* ldo, int count, const bri_opts* o) {
+  hipStream_t st = o->stream;
+  char* ws = static_cast<char*>(o->workspace);
+  int32_t* shared_info = reinterpret_cast<int32_t*>(ws + bp.info_off);
+  std::vector<Ctx> ctx(count);
+  std::vector<const Plan*> pl(count);
+  for (int t = 0; t < count; ++t) {
+    Ctx& c = ctx[t];
+    c.pivoting = BRI_PIVOT_TILE;
+    c.M = static_cast<const char*>(M[t]);
+    c.n = n[t];
+    c.ldm = ldm[t];
+    c.b = bp.plans[t]->plan.b;
+    c.elem = sizeof(T);
+    c.ws = ws + bp.region[t];
+    c.lay = &bp.plans[t]->layout;
+    c.out = static_cast<char*>(out[t]);
+    c.ldo = ldo[t];
+    c.info = o->d_info ? o->d_info + t : shared_info;
+    pl[t] = &bp.plans[t]->plan;
+  }
+  Staging& sg = staging();
+  std::lock_guard<std::mutex> lk(sg.mu);
+  char* host = sg.get(bp.merged.bytes);
+  if (!host) return BRI_ERR_HIP;
+  MergedExec ex;
+  try {
+    ex = merge_write(pl, ctx, bp.merged, host, ws + bp.desc_off);
+  } catch (const std::exception&) {
+    return BRI_ERR_UNSUPPORTED;
+  }
+  if (hipMemcpyAsync(ws + bp.desc_off, host, bp.merged.bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    return BRI_ERR_HIP;
+  if (hipEventRecord(sg.ev, st) != hipSuccess) return BRI_ERR_HIP;
+  if (launch_fill_int(o->d_info ? o->d_info : shared_info, o->d_info ? count : 1, 0, st) != hipSuccess)
+    return BRI_ERR_HIP;
+  return run_merged<T>(ex, BRI_PIVOT_TILE, 0, st);
+}
+
+// Merged execution of plain precisions needs tile pivoting (the panel
+// pivoting kernels assume one block order per launch).
+bool batch_mergeable(const bri_opts* o) {
+  return o->pivoting == BRI_PIVOT_TILE && (plain_precision(o->precision) || mixed_precision(o->precision));
+}
+
+// ---------------------------------------------------------------------------
 // Mixed precision: block column by the float recursion, refined in FP64.
+// A single call is a batch of one.
 // ---------------------------------------------------------------------------
 struct RefineCache {
   std::shared_ptr<CachedPlan> col, sol;
   std::vector<int> kept;
-  std::mutex mu;            // serialises calls that share the staging buffer
-  void* host = nullptr;     // pinned: descriptors of the residual product and the output copy, norms
-  hipEvent_t uploaded = nullptr;
-  ~RefineCache() {
-    if (uploaded) (void)hipEventDestroy(uploaded);
-    if (host) (void)hipHostFree(host);
-  }
 };
 
 typedef std::tuple<int64_t, int, int, int> RefineKey;  // n, k, j, width
@@ -554,20 +745,18 @@ std::shared_ptr<RefineCache> get_refine(int64_t n, int k, int j, int width) {
   rc->col->layout = make_layout(rc->col->plan, 4);
   rc->sol->layout = make_layout(rc->sol->plan, 4);
   rc->kept = rp.kept;
-  if (c.size() > 64) c.clear();
+  if (c.size() > 1024) c.clear();
   c[key] = rc;
   return rc;
 }
 
-struct MixedLayout {
-  size_t g32 = 0, x64 = 0, r64 = 0, r32 = 0, d32 = 0, scal = 0, desc = 0, plans = 0, total = 0;
+// Per-problem buffers of the mixed path (offsets inside the problem's region).
+struct MixedRegion {
+  size_t g32 = 0, x64 = 0, r64 = 0, r32 = 0, d32 = 0, plans = 0, total = 0;
 };
 
-// Workspace of the mixed path: sigma Gamma in float, the FP64 iterate X and
-// residual R, their float images, device scalars, two descriptors and the
-// region of the float plans (shared by the column and the solve plan).
-MixedLayout mixed_layout(int64_t n, int k, const RefineCache& rc) {
-  MixedLayout L;
+MixedRegion mixed_region(int64_t n, int k, const RefineCache& rc) {
+  MixedRegion L;
   const size_t b = static_cast<size_t>((n + k - 1) / k);
   const size_t kb = static_cast<size_t>(k) * b;
   size_t off = 0;
@@ -581,303 +770,270 @@ MixedLayout mixed_layout(int64_t n, int k, const RefineCache& rc) {
   off += align_up(kb * b * 4);
   L.d32 = off;
   off += align_up(kb * b * 4);
-  L.scal = off;
-  off += align_up(kRefineScalars * sizeof(double));
-  L.desc = off;
-  off += align_up(sizeof(GemmItem)) + align_up(sizeof(LoadItem));
   L.plans = off;
-  off += std::max(rc.col->layout.total, rc.sol->layout.total);
+  off += align_up(std::max(rc.col->layout.desc_off, rc.sol->layout.desc_off));  // slots of both plans
   L.total = off;
   return L;
 }
 
-size_t mixed_workspace_size(int64_t n, int k, int j, int width) {
-  auto rc = get_refine(n, k, j, width);
-  return mixed_layout(n, k, *rc).total;
+// Workspace of a mixed call over count problems: the problems' regions, then
+// shared: status word, device scalars (kRefineScalars per problem),
+// refinement items, residual product items, output copy items, merged
+// descriptors of the block-column plans and of the correction solves.
+struct MixedBatch {
+  std::vector<std::shared_ptr<RefineCache>> rc;
+  std::vector<MixedRegion> reg;
+  std::vector<size_t> region;
+  MergedLayout col, sol;
+  size_t info_off = 0, scal_off = 0, items_off = 0, gemm_off = 0, load_off = 0, col_off = 0, sol_off = 0;
+  size_t desc_bytes = 0, total = 0;
+};
+
+MixedBatch make_mixed_batch(int count, const int64_t* n, const int* k, const int* j, const bri_opts* o,
+                            bool merged_width_rule) {
+  MixedBatch mb;
+  mb.rc.resize(count);
+  mb.reg.resize(count);
+  mb.region.resize(count);
+  std::vector<const Plan*> pc(count), ps(count);
+  size_t off = 0;
+  for (int t = 0; t < count; ++t) {
+    const int w = merged_width_rule ? merged_width(k[t]) : resolve_width(n[t], k[t], o);
+    mb.rc[t] = get_refine(n[t], k[t], j[t], w);
+    mb.reg[t] = mixed_region(n[t], k[t], *mb.rc[t]);
+    mb.region[t] = off;
+    off += mb.reg[t].total;
+    pc[t] = &mb.rc[t]->col->plan;
+    ps[t] = &mb.rc[t]->sol->plan;
+  }
+  mb.col = merge_layout(pc);
+  mb.sol = merge_layout(ps);
+  mb.info_off = off;
+  off += kAlign;
+  const size_t c = static_cast<size_t>(count);
+  mb.scal_off = off;
+  off += align_up(c * kRefineScalars * sizeof(double));
+  // descriptors, uploaded with one copy
+  const size_t d0 = off;
+  mb.items_off = off;
+  off += align_up(c * sizeof(RefItem));
+  mb.gemm_off = off;
+  off += align_up(c * sizeof(GemmItem));
+  mb.load_off = off;
+  off += align_up(c * sizeof(LoadItem));
+  mb.col_off = off;
+  off += mb.col.bytes;
+  mb.sol_off = off;
+  off += mb.sol.bytes;
+  mb.desc_bytes = off - d0;
+  mb.total = off;
+  return mb;
+}
+
+size_t mixed_workspace_size(int64_t n, int k, int j, const bri_opts* o) {
+  return make_mixed_batch(1, &n, &k, &j, o, false).total;
+}
+
+int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const int64_t* n, const int64_t* ldm,
+                    const int* i, const int* j, void* const* out, const int64_t* ldo, const bri_opts* o) {
+  hipStream_t st = o->stream;
+  char* ws = static_cast<char*>(o->workspace);
+  int32_t* shared_info = reinterpret_cast<int32_t*>(ws + mb.info_off);
+  double* scal_all = reinterpret_cast<double*>(ws + mb.scal_off);
+  const size_t d0 = mb.items_off;
+  std::vector<Ctx> cc(count), cs(count);
+  std::vector<const Plan*> pc(count), ps(count);
+  std::vector<RefItem> ri(count);
+  std::vector<GemmItem> gi(count);
+  std::vector<LoadItem> li(count);
+  int64_t max_nn = 0, max_kk = 0, max_kb_b = 0, max_fix = 0;
+  int max_n = 0, max_b = 0;
+  for (int t = 0; t < count; ++t) {
+    const RefineCache& rc = *mb.rc[t];
+    const MixedRegion& R = mb.reg[t];
+    char* base = ws + mb.region[t];
+    const int b = rc.col->plan.b;
+    const int64_t kb = static_cast<int64_t>(rc.col->plan.k) * b;
+    RefItem& r = ri[t];
+    std::memset(&r, 0, sizeof(r));
+    r.M = static_cast<const double*>(M[t]);
+    r.n = n[t];
+    r.ldm = ldm[t];
+    r.kb = kb;
+    r.b = b;
+    r.j = j[t];
+    r.G = reinterpret_cast<float*>(base + R.g32);
+    r.X = reinterpret_cast<double*>(base + R.x64);
+    r.R = reinterpret_cast<double*>(base + R.r64);
+    r.R32 = reinterpret_cast<float*>(base + R.r32);
+    r.D = reinterpret_cast<float*>(base + R.d32);
+    r.scal = scal_all + static_cast<size_t>(t) * kRefineScalars;
+    max_nn = std::max<int64_t>(max_nn, n[t] * n[t]);
+    max_kk = std::max<int64_t>(max_kk, kb * kb);
+    max_kb_b = std::max<int64_t>(max_kb_b, kb * b);
+    max_fix = std::max<int64_t>(max_fix, static_cast<int64_t>(b) * (1 + kb - n[t]));
+    max_n = std::max<int>(max_n, static_cast<int>(n[t]));
+    max_b = std::max(max_b, b);
+    // R[0:n) = -M X[0:n) in FP64
+    GemmItem& g = gi[t];
+    std::memset(&g, 0, sizeof(g));
+    g.A = g.B = g.Cin = g.Sub = zero_view();
+    g.A.p = M[t];
+    g.A.ld = ldm[t];
+    g.A.rows = static_cast<int32_t>(n[t]);
+    g.A.cols = static_cast<int32_t>(n[t]);
+    g.B.p = r.X;
+    g.B.ld = b;
+    g.B.rows = static_cast<int32_t>(kb);
+    g.B.cols = b;
+    g.out = r.R;
+    g.ldo = b;
+    g.M = static_cast<int32_t>(n[t]);
+    g.N = b;
+    g.K = static_cast<int32_t>(n[t]);
+    g.alpha = -1.0;
+    // block row i of X to out
+    LoadItem& l = li[t];
+    std::memset(&l, 0, sizeof(l));
+    l.src = zero_view();
+    l.src.p = r.X + static_cast<int64_t>(i[t]) * b * b;
+    l.src.ld = b;
+    l.src.rows = b;
+    l.src.cols = b;
+    l.dst = out[t];
+    l.ldd = ldo[t];
+    l.rows = b;
+    l.cols = b;
+    // float plans: sigma Gamma in place of M, D as the output, R32 as the right-hand side
+    Ctx& c = cc[t];
+    c.pivoting = o->pivoting;
+    c.M = reinterpret_cast<const char*>(r.G);
+    c.n = kb;
+    c.ldm = kb;
+    c.b = b;
+    c.elem = 4;
+    c.ws = base + R.plans;
+    c.lay = &rc.col->layout;
+    c.out = reinterpret_cast<char*>(r.D);
+    c.ldo = b;
+    c.info = o->d_info ? o->d_info + t : shared_info;
+    c.rhs = reinterpret_cast<char*>(r.R32);
+    c.ldr = b;
+    c.lp = lp_of(o->precision);
+    cs[t] = c;
+    cs[t].lay = &rc.sol->layout;
+    pc[t] = &rc.col->plan;
+    ps[t] = &rc.sol->plan;
+  }
+  // Panel pivoting kernels take one block order per launch: merged groups
+  // must then hold one order only (single calls always do).
+  Staging& sg = staging();
+  std::lock_guard<std::mutex> lk(sg.mu);
+  char* host = sg.get(mb.desc_bytes);
+  if (!host) return BRI_ERR_HIP;
+  std::memcpy(host + (mb.items_off - d0), ri.data(), count * sizeof(RefItem));
+  std::memcpy(host + (mb.gemm_off - d0), gi.data(), count * sizeof(GemmItem));
+  std::memcpy(host + (mb.load_off - d0), li.data(), count * sizeof(LoadItem));
+  MergedExec ecol, esol;
+  try {
+    ecol = merge_write(pc, cc, mb.col, host + (mb.col_off - d0), ws + mb.col_off);
+    esol = merge_write(ps, cs, mb.sol, host + (mb.sol_off - d0), ws + mb.sol_off);
+  } catch (const std::exception&) {
+    return BRI_ERR_UNSUPPORTED;
+  }
+  if (o->pivoting == BRI_PIVOT_PANEL) {
+    for (const MergedExec* e : {&ecol, &esol})
+      for (size_t g = 0; g < e->groups.size(); ++g)
+        for (int t : (e == &ecol ? mb.col : mb.sol).groups[g])
+          if (cc[t].b != e->bmax[g]) return BRI_ERR_UNSUPPORTED;
+  }
+  if (hipMemcpyAsync(ws + d0, host, mb.desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return BRI_ERR_HIP;
+  if (hipEventRecord(sg.ev, st) != hipSuccess) return BRI_ERR_HIP;
+  const RefItem* d_items = reinterpret_cast<const RefItem*>(ws + mb.items_off);
+  if (launch_fill_int(o->d_info ? o->d_info : shared_info, o->d_info ? count : 1, 0, st) != hipSuccess)
+    return BRI_ERR_HIP;
+
+  // sigma Gamma in float, then X0 = sigma (sigma Gamma)^{-1} E_j by the float
+  // block-column plans (which keep their pivots for the correction solves).
+  if (launch_scal_clear(d_items, count, 0, kRefineScalars, st) != hipSuccess) return BRI_ERR_HIP;
+  if (launch_absmax(d_items, count, 0, max_nn, st) != hipSuccess) return BRI_ERR_HIP;
+  if (launch_gamma_f32(d_items, count, max_kk, st) != hipSuccess) return BRI_ERR_HIP;
+  int rcode = run_merged<float>(ecol, o->pivoting, lp_of(o->precision), st);
+  if (rcode != BRI_OK) return rcode;
+  if (launch_refine_update(d_items, count, max_kb_b, 1, st) != hipSuccess) return BRI_ERR_HIP;
+
+  // Sweeps: R = E_j - Gamma X (FP64), D = (sigma Gamma)^{-1} (s R) by the float
+  // solves, X += (sigma / s) D.  A problem has converged when its correction
+  // is below tol ||X||_F, or, from the second sweep on, when the observed
+  // contraction rho = ||dX_t|| / ||dX_{t-1}|| < 1/2 bounds the remaining
+  // error rho / (1 - rho) ||dX_t|| below it.  All problems sweep together
+  // until every one has converged.
+  std::vector<char> conv(count, o->refine_max_iters <= 0 ? 1 : 0);
+  std::vector<double> prev(count, 0.0);
+  std::vector<double> hs(static_cast<size_t>(count) * kRefineScalars);
+  const double tol = o->refine_tol;
+  t_last_sweeps = 0;
+  t_last_update = 0.0;
+  for (int it = 0; it < o->refine_max_iters; ++it) {
+    if (launch_scal_clear(d_items, count, 1, 4, st) != hipSuccess) return BRI_ERR_HIP;
+    GemmLaunch L{};
+    L.mode = GEMM_EXPLICIT;
+    L.elem = 8;
+    L.items = ws + mb.gemm_off;
+    L.count = count;
+    L.w = count;  // stored dense operands
+    if (launch_gemm<double>(L, max_n, max_b, st) != hipSuccess) return BRI_ERR_HIP;
+    if (launch_resid_fix(d_items, count, max_fix, st) != hipSuccess) return BRI_ERR_HIP;
+    if (launch_absmax(d_items, count, 1, max_kb_b, st) != hipSuccess) return BRI_ERR_HIP;
+    if (launch_rhs_scale(d_items, count, max_kb_b, st) != hipSuccess) return BRI_ERR_HIP;
+    rcode = run_merged<float>(esol, o->pivoting, lp_of(o->precision), st);
+    if (rcode != BRI_OK) return rcode;
+    if (launch_refine_update(d_items, count, max_kb_b, 0, st) != hipSuccess) return BRI_ERR_HIP;
+    if (hipMemcpyAsync(hs.data(), scal_all, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+      return BRI_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return BRI_ERR_HIP;
+    t_last_sweeps = it + 1;
+    bool all = true;
+    double worst = 0.0;
+    for (int t = 0; t < count; ++t) {
+      const double dd = hs[static_cast<size_t>(t) * kRefineScalars + 2];
+      const double xx = hs[static_cast<size_t>(t) * kRefineScalars + 3];
+      const double upd = std::sqrt(dd), lim = tol * std::sqrt(xx);
+      worst = std::max(worst, xx > 0 ? upd / std::sqrt(xx) : upd);
+      if (!conv[t] && std::isfinite(dd) && std::isfinite(xx)) {
+        bool done = upd <= lim;
+        if (!done && prev[t] > 0) {
+          const double rho = upd / prev[t];
+          done = rho < 0.5 && rho / (1.0 - rho) * upd <= lim;
+        }
+        if (done) conv[t] = 1;
+      }
+      prev[t] = upd;
+      all = all && conv[t];
+    }
+    t_last_update = worst;
+    if (all) break;
+  }
+  if (launch_load<double>(reinterpret_cast<const LoadItem*>(ws + mb.load_off), count, max_b, max_b, st) !=
+      hipSuccess)
+    return BRI_ERR_HIP;
+  for (int t = 0; t < count; ++t)
+    if (!conv[t] && launch_info_unconverged(o->d_info ? o->d_info + t : shared_info, st) != hipSuccess)
+      return BRI_ERR_HIP;
+  return BRI_OK;
 }
 
 int invert_block_mixed(const void* M, int64_t n, int64_t ldm, int k, int i, int j, void* out, int64_t ldo,
                        const bri_opts* o) {
-  const int w = resolve_width(n, k, o);
-  std::shared_ptr<RefineCache> rc;
+  MixedBatch mb;
   try {
-    rc = get_refine(n, k, j, w);
+    mb = make_mixed_batch(1, &n, &k, &j, o, false);
   } catch (const std::exception&) {
     return BRI_ERR_UNSUPPORTED;
   }
-  const MixedLayout ml = mixed_layout(n, k, *rc);
-  if (!o->workspace || o->workspace_bytes < ml.total) return BRI_ERR_WORKSPACE;
-  std::lock_guard<std::mutex> lk(rc->mu);
-  hipStream_t st = o->stream;
-  char* ws = static_cast<char*>(o->workspace);
-  const int b = rc->col->plan.b;
-  const int64_t kb = static_cast<int64_t>(k) * b;
-  const int64_t cnt = kb * b;
-  float* G = reinterpret_cast<float*>(ws + ml.g32);
-  double* X = reinterpret_cast<double*>(ws + ml.x64);
-  double* R = reinterpret_cast<double*>(ws + ml.r64);
-  float* R32 = reinterpret_cast<float*>(ws + ml.r32);
-  float* D = reinterpret_cast<float*>(ws + ml.d32);
-  double* scal = reinterpret_cast<double*>(ws + ml.scal);
-  char* desc = ws + ml.desc;
-  int32_t* info = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(ws + ml.plans + rc->col->layout.info_off);
-
-  // Descriptors: R[0:n) = -M X[0:n) (FP64) and the copy of block row i of X to out.
-  GemmItem g;
-  std::memset(&g, 0, sizeof(g));
-  g.A = g.B = g.Cin = g.Sub = zero_view();
-  g.A.p = M;
-  g.A.ld = ldm;
-  g.A.rows = static_cast<int32_t>(n);
-  g.A.cols = static_cast<int32_t>(n);
-  g.B.p = X;
-  g.B.ld = b;
-  g.B.rows = static_cast<int32_t>(kb);
-  g.B.cols = b;
-  g.out = R;
-  g.ldo = b;
-  g.M = static_cast<int32_t>(n);
-  g.N = b;
-  g.K = static_cast<int32_t>(n);
-  g.alpha = -1.0;
-  LoadItem li;
-  std::memset(&li, 0, sizeof(li));
-  li.src = zero_view();
-  li.src.p = X + static_cast<int64_t>(i) * b * b;
-  li.src.ld = b;
-  li.src.rows = b;
-  li.src.cols = b;
-  li.dst = out;
-  li.ldd = ldo;
-  li.rows = b;
-  li.cols = b;
-  const size_t gbytes = align_up(sizeof(GemmItem));
-  const size_t hbytes = gbytes + align_up(sizeof(LoadItem)) + kRefineScalars * sizeof(double);
-  if (!rc->host) {
-    if (hipHostMalloc(&rc->host, hbytes) != hipSuccess) return BRI_ERR_HIP;
-    if (hipEventCreateWithFlags(&rc->uploaded, hipEventDisableTiming) != hipSuccess) return BRI_ERR_HIP;
-  } else if (hipEventSynchronize(rc->uploaded) != hipSuccess) {
-    return BRI_ERR_HIP;
-  }
-  char* host = static_cast<char*>(rc->host);
-  std::memcpy(host, &g, sizeof(g));
-  std::memcpy(host + gbytes, &li, sizeof(li));
-  double* hscal = reinterpret_cast<double*>(host + gbytes + align_up(sizeof(LoadItem)));
-  if (hipMemcpyAsync(desc, host, gbytes + sizeof(LoadItem), hipMemcpyHostToDevice, st) != hipSuccess)
-    return BRI_ERR_HIP;
-  if (hipEventRecord(rc->uploaded, st) != hipSuccess) return BRI_ERR_HIP;
-
-  // sigma Gamma in float, then X0 = sigma (sigma Gamma)^{-1} E_j by the float
-  // block column plan (which keeps its pivots for the correction solves).
-  if (launch_scal_clear(scal, 0, kRefineScalars, st) != hipSuccess) return BRI_ERR_HIP;
-  if (launch_absmax(M, 8, n, n, ldm, scal, st) != hipSuccess) return BRI_ERR_HIP;
-  if (launch_gamma_f32(static_cast<const double*>(M), n, ldm, kb, G, scal, st) != hipSuccess) return BRI_ERR_HIP;
-  Ctx c;
-  c.pivoting = o->pivoting;
-  c.M = reinterpret_cast<const char*>(G);
-  c.n = kb;
-  c.ldm = kb;
-  c.b = b;
-  c.elem = 4;
-  c.ws = ws + ml.plans;
-  c.out = reinterpret_cast<char*>(D);
-  c.ldo = b;
-  c.info = info;
-  c.rhs = reinterpret_cast<char*>(R32);
-  c.ldr = b;
-  c.lp = lp_of(o->precision);
-  int rcode = execute(*rc->col, c, st, true);
-  if (rcode != BRI_OK) return rcode;
-  if (launch_refine_update(X, D, cnt, scal, 1, st) != hipSuccess) return BRI_ERR_HIP;
-
-  // Sweeps: R = E_j - Gamma X (FP64), D = (sigma Gamma)^{-1} (s R) by the float
-  // solve plan, X += (sigma / s) D, until the error of X is below tol ||X||_F
-  // (see the convergence test below).
-  bool converged = o->refine_max_iters <= 0;
-  const double tol = o->refine_tol;
-  t_last_sweeps = 0;
-  t_last_update = 0.0;
-  double prev_upd = 0.0;
-  for (int it = 0; it < o->refine_max_iters; ++it) {
-    if (launch_scal_clear(scal, 1, 4, st) != hipSuccess) return BRI_ERR_HIP;
-    GemmLaunch L{};
-    L.mode = GEMM_EXPLICIT;
-    L.elem = 8;
-    L.items = desc;
-    L.count = 1;
-    L.w = 1;  // stored dense operands
-    if (launch_gemm<double>(L, static_cast<int>(n), b, st) != hipSuccess) return BRI_ERR_HIP;
-    if (launch_resid_fix(R, X, n, kb, b, j, st) != hipSuccess) return BRI_ERR_HIP;
-    if (launch_absmax(R, 8, kb, b, b, scal + 1, st) != hipSuccess) return BRI_ERR_HIP;
-    if (launch_rhs_scale(R, R32, cnt, scal, st) != hipSuccess) return BRI_ERR_HIP;
-    rcode = execute(*rc->sol, c, st, false);
-    if (rcode != BRI_OK) return rcode;
-    if (launch_refine_update(X, D, cnt, scal, 0, st) != hipSuccess) return BRI_ERR_HIP;
-    if (hipMemcpyAsync(hscal, scal, kRefineScalars * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
-      return BRI_ERR_HIP;
-    if (hipStreamSynchronize(st) != hipSuccess) return BRI_ERR_HIP;
-    const double dd = hscal[2], xx = hscal[3];
-    t_last_sweeps = it + 1;
-    t_last_update = xx > 0 ? std::sqrt(dd / xx) : dd;
-    if (!std::isfinite(dd) || !std::isfinite(xx)) break;
-    // Converged when the correction itself is below tol, or, from the second
-    // sweep on, when the observed contraction rho = ||dX_t|| / ||dX_{t-1}||
-    // bounds the remaining error, rho / (1 - rho) ||dX_t||, below tol.
-    const double upd = std::sqrt(dd), lim = tol * std::sqrt(xx);
-    bool done = upd <= lim;
-    if (!done && prev_upd > 0) {
-      const double rho = upd / prev_upd;
-      done = rho < 0.5 && rho / (1.0 - rho) * upd <= lim;
-    }
-    prev_upd = upd;
-    if (done) {
-      converged = true;
-      break;
-    }
-  }
-  if (launch_load<double>(reinterpret_cast<const LoadItem*>(desc + gbytes), 1, b, b, st) != hipSuccess)
-    return BRI_ERR_HIP;
-  if (!converged && launch_info_unconverged(info, st) != hipSuccess) return BRI_ERR_HIP;
-  return BRI_OK;
+  if (!o->workspace || o->workspace_bytes < mb.total) return BRI_ERR_WORKSPACE;
+  return run_mixed_batch(mb, 1, &M, &n, &ldm, &i, &j, &out, &ldo, o);
 }
-
-// ---------------------------------------------------------------------------
-// Merged batches: problems whose plans have the same step structure (same k,
-// same kind of target, same width) share every launch; each work item carries
-// its own block order, operands and status word.
-// ---------------------------------------------------------------------------
-bool same_structure(const Plan& a, const Plan& b) {
-  if (a.steps.size() != b.steps.size()) return false;
-  for (size_t s = 0; s < a.steps.size(); ++s)
-    if (a.steps[s].kind != b.steps[s].kind || a.steps[s].items.size() != b.steps[s].items.size()) return false;
-  return true;
-}
-
-int merged_width(int k) { return static_cast<int>(std::min<int64_t>(16, leaves_of(k))); }
-
-struct BatchPlan {
-  std::vector<std::shared_ptr<CachedPlan>> plans;  // per problem
-  std::vector<size_t> region;                      // per problem: offset of its slot region
-  std::vector<std::vector<int>> groups;            // problems of every merged group
-  std::vector<std::vector<size_t>> step_desc;      // per group and step: descriptor offset
-  size_t info_off = 0, desc_off = 0, desc_bytes = 0, total = 0;
-};
-
-BatchPlan make_batch_plan(int count, const int64_t* n, const int* k, const int* i, const int* j, int elem) {
-  BatchPlan bp;
-  bp.plans.resize(count);
-  bp.region.resize(count);
-  std::map<std::pair<int, int>, std::vector<int>> by_key;  // (k, diagonal target) -> groups
-  for (int t = 0; t < count; ++t) {
-    bp.plans[t] = get_plan(0, n[t], k[t], i[t], j[t], merged_width(k[t]), elem, 0);
-    std::vector<int>& cands = by_key[{k[t], i[t] == j[t] ? 1 : 0}];
-    int g = -1;
-    for (int c : cands)
-      if (same_structure(bp.plans[bp.groups[c][0]]->plan, bp.plans[t]->plan)) g = c;
-    if (g < 0) {
-      g = static_cast<int>(bp.groups.size());
-      bp.groups.emplace_back();
-      cands.push_back(g);
-    }
-    bp.groups[g].push_back(t);
-  }
-  size_t off = 0;
-  for (int t = 0; t < count; ++t) {
-    bp.region[t] = off;
-    off += align_up(bp.plans[t]->layout.desc_off);  // slots, permutations, tile scratch, status
-  }
-  bp.info_off = off;
-  off += kAlign;
-  bp.desc_off = off;
-  size_t d = 0;
-  for (const std::vector<int>& grp : bp.groups) {
-    const Plan& p0 = bp.plans[grp[0]]->plan;
-    bp.step_desc.emplace_back();
-    for (size_t si = 0; si < p0.steps.size(); ++si) {
-      bp.step_desc.back().push_back(d);
-      d += align_up(item_bytes(p0.steps[si].kind) * p0.steps[si].items.size() * grp.size());
-    }
-  }
-  bp.desc_bytes = d;
-  bp.total = off + d;
-  return bp;
-}
-
-template <typename T>
-int run_batch(const BatchPlan& bp, const void* const* M, const int64_t* n, const int64_t* ldm, void* const* out,
-              const int64_t* ldo, int count, const bri_opts* o) {
-  hipStream_t st = o->stream;
-  char* ws = static_cast<char*>(o->workspace);
-  int32_t* shared_info = reinterpret_cast<int32_t*>(ws + bp.info_off);
-  static std::mutex mu;
-  static void* host = nullptr;
-  static size_t host_bytes = 0;
-  static hipEvent_t ev = nullptr;
-  std::lock_guard<std::mutex> lk(mu);
-  if (ev && hipEventSynchronize(ev) != hipSuccess) return BRI_ERR_HIP;
-  if (host_bytes < bp.desc_bytes) {
-    if (host) (void)hipHostFree(host);
-    host = nullptr;
-    host_bytes = 0;
-    if (hipHostMalloc(&host, bp.desc_bytes) != hipSuccess) return BRI_ERR_HIP;
-    host_bytes = bp.desc_bytes;
-  }
-  if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return BRI_ERR_HIP;
-  std::vector<Ctx> ctx(count);
-  for (int t = 0; t < count; ++t) {
-    Ctx& c = ctx[t];
-    c.pivoting = BRI_PIVOT_TILE;
-    c.M = static_cast<const char*>(M[t]);
-    c.n = n[t];
-    c.ldm = ldm[t];
-    c.b = bp.plans[t]->plan.b;
-    c.elem = sizeof(T);
-    c.ws = ws + bp.region[t];
-    c.lay = &bp.plans[t]->layout;
-    c.out = static_cast<char*>(out[t]);
-    c.ldo = ldo[t];
-    c.info = o->d_info ? o->d_info + t : shared_info;
-  }
-  std::vector<std::vector<ExecStep>> exec(bp.groups.size());
-  std::vector<int> bmax(bp.groups.size(), 0);
-  StepItems items;
-  try {
-    for (size_t g = 0; g < bp.groups.size(); ++g) {
-      const std::vector<int>& grp = bp.groups[g];
-      const Plan& p0 = bp.plans[grp[0]]->plan;
-      for (int t : grp) bmax[g] = std::max(bmax[g], ctx[t].b);
-      for (size_t si = 0; si < p0.steps.size(); ++si) {
-        items.clear();
-        double flops = 0;
-        for (int t : grp) {
-          const Step& s = bp.plans[t]->plan.steps[si];
-          describe_step(ctx[t], s, items);
-          flops += step_flops(s, ctx[t].b);
-        }
-        items.write(static_cast<char*>(host) + bp.step_desc[g][si]);
-        exec[g].push_back(ExecStep{p0.steps[si].kind, static_cast<int>(items.count()),
-                                   static_cast<int>(items.fast.size()), ws + bp.desc_off + bp.step_desc[g][si],
-                                   &p0.steps[si], flops});
-      }
-    }
-  } catch (const std::exception&) {
-    return BRI_ERR_UNSUPPORTED;
-  }
-  if (hipMemcpyAsync(ws + bp.desc_off, host, bp.desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return BRI_ERR_HIP;
-  if (hipEventRecord(ev, st) != hipSuccess) return BRI_ERR_HIP;
-  if (launch_fill_int(o->d_info ? o->d_info : shared_info, o->d_info ? count : 1, 0, st) != hipSuccess)
-    return BRI_ERR_HIP;
-  for (size_t g = 0; g < bp.groups.size(); ++g) {
-    const int rc = run_exec<T>(exec[g], bmax[g], BRI_PIVOT_TILE, 0, st);
-    if (rc != BRI_OK) return rc;
-  }
-  return BRI_OK;
-}
-
-// Merged execution needs plain precision and tile pivoting (the panel
-// pivoting kernels assume one block order per launch; the mixed path
-// synchronises per refinement sweep).
-bool batch_mergeable(const bri_opts* o) { return plain_precision(o->precision) && o->pivoting == BRI_PIVOT_TILE; }
 
 }  // namespace
 }  // namespace bri
@@ -958,7 +1114,7 @@ size_t bri_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
   const int w = resolve_width(n, k, o);
   if (mixed_precision(o->precision)) {
     try {
-      return mixed_workspace_size(n, k, j, w);
+      return mixed_workspace_size(n, k, j, o);
     } catch (const std::exception&) {
       return 0;
     }
@@ -989,7 +1145,7 @@ int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_pla
   s->block = p.b;
   s->algorithmic_flops = p.algorithmic_flops;
   s->executed_flops = p.executed_flops;
-  s->workspace_bytes = mixed_precision(o->precision) ? mixed_workspace_size(n, k, j, w) : cp->layout.total;
+  s->workspace_bytes = mixed_precision(o->precision) ? mixed_workspace_size(n, k, j, o) : cp->layout.total;
   return 0;
 }
 
@@ -1140,7 +1296,8 @@ size_t bri_batched_workspace_size(int count, const int64_t* n, const int* k, con
   if (count == 0) return kAlign;
   if (batch_mergeable(o)) {
     try {
-      return make_batch_plan(count, n, k, i, j, elem_size(o->precision)).total;
+      return mixed_precision(o->precision) ? make_mixed_batch(count, n, k, j, o, true).total
+                                           : make_batch_plan(count, n, k, i, j, elem_size(o->precision)).total;
     } catch (const std::exception&) {
       return 0;
     }
@@ -1172,6 +1329,16 @@ int invert_block_batched(int count, const void* const* M, const int64_t* n, cons
     if (!out[t]) return -8;
     const int rc = check_block_args(n[t], ldm[t], k[t], i[t], j[t], ldo[t]);
     if (rc) return rc == -2 ? -3 : rc == -3 ? -4 : rc == -4 ? -5 : rc == -5 ? -6 : rc == -6 ? -7 : rc == -8 ? -9 : rc;
+  }
+  if (batch_mergeable(o) && mixed_precision(o->precision)) {
+    MixedBatch mb;
+    try {
+      mb = make_mixed_batch(count, n, k, j, o, true);
+    } catch (const std::exception&) {
+      return BRI_ERR_UNSUPPORTED;
+    }
+    if (!o->workspace || o->workspace_bytes < mb.total) return BRI_ERR_WORKSPACE;
+    return run_mixed_batch(mb, count, M, n, ldm, i, j, out, ldo, o);
   }
   if (batch_mergeable(o)) {
     BatchPlan bp;

@@ -121,3 +121,26 @@ def test_mixed_batched_problems():
     for p, o in zip(probs, outs):
         want = oracle.invert_block(workloads.batch_matrix(p), p.k, p.i, p.j)
         assert rel(o.cpu().numpy(), want) < 1e-10, (p.n, p.k, p.i, p.j)
+
+
+def test_mixed_f32_batched_512_problems_merged():
+    # The batched workload in its stated precision (FP32 recursion with FP64
+    # refinement): every block against the dense inverse of its matrix.
+    probs = workloads.batch_problems()
+    mats = [workloads.batch_matrix(p) for p in probs]
+    Ms = [gpu(m) for m in mats]
+    info = torch.zeros(len(probs), dtype=torch.int32, device=DEV)
+    print("mixed_f32 batched 512 problems", flush=True)
+    outs = bri.invert_block_batched(Ms, [p.k for p in probs], [p.i for p in probs], [p.j for p in probs],
+                                    precision="mixed_f32", info=info)
+    torch.cuda.synchronize()
+    assert int(info.abs().sum().item()) == 0
+    worst = 0.0
+    for p, m, o in zip(probs, mats, outs):
+        b = -(-p.n // p.k)
+        g = np.eye(p.k * b)
+        g[:p.n, :p.n] = m
+        want = np.linalg.inv(g)[p.i * b:(p.i + 1) * b, p.j * b:(p.j + 1) * b]
+        worst = max(worst, rel(o.cpu().numpy(), want))
+    print(f"  worst rel err {worst:.2e}, sweeps {bri.refine_last()[0]}", flush=True)
+    assert worst < 1e-10

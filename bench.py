@@ -47,6 +47,30 @@ def profile_read(lib):
     return {t: (arr[t].steps, arr[t].launches, arr[t].ms, arr[t].flops) for t in range(1, n)}
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_gemm_explicit_hbm_traffic_spd_n4096_k4_f64.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1612_00001_amd", "csrc", "bri_kernels.hip")
+
+
+def counted_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size),
+    or None when the summary is missing or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+        digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("traffic_bytes", "source_sha256")))
+    if fields.get("source_sha256", "").strip() != digest:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def rel_err(a, b):
     import numpy as np
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
@@ -75,6 +99,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the block recursive inverse runs on a single MI355X "
@@ -83,6 +111,17 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        # A plain copy of known size: the HBM counters of its kernel give the
+        # scale between counted and actual bytes.
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": src.numel() * 8, "launches": 5}), flush=True)
+        return 0
 
     import paper_1612_00001_amd as bri
     import workloads
@@ -114,9 +153,12 @@ def main() -> int:
     for _ in range(args.warmup):
         call()
     torch.cuda.synchronize()
+    # Timed steps without instrumentation, then the same steps again with HIP
+    # events around every plan step for the per-kernel breakdown.
+    ms, wall_ms = time_calls(call, args.steps, 0, torch)
     lib.bri_profile_enable(1)
     profile_read(lib)  # clear
-    ms, wall_ms = time_calls(call, args.steps, 0, torch)
+    prof_ms, _ = time_calls(call, args.steps, 0, torch)
     prof = profile_read(lib)
     lib.bri_profile_enable(0)
     assert int(info.item()) == 0, "device status"
@@ -138,7 +180,7 @@ def main() -> int:
     roofline = {
         "kernel": "k_gemm<double, GEMM_EXPLICIT, 128x128> (Schur and triangular products)",
         "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
-        "frac": achieved / PEAK_TFLOPS["f64"], "traffic": None,
+        "frac": achieved / PEAK_TFLOPS["f64"], "traffic": counted_traffic(),
         "launches_per_step": p_la / args.steps, "avg_launch_ms": (p_ms / p_la) if p_la else None,
         "flops_per_launch": (p_fl / p_la) if p_la else None,
     }
@@ -151,7 +193,7 @@ def main() -> int:
                    "n": n, "k": k, "b": stats["block"], "block": [i, j], "precision": "f64",
                    "concurrency": stats["batch_width"]},
         "pct_fp64_mfma_peak": 100.0 * value / PEAK_TFLOPS["f64"],
-        "wall_ms_per_step": wall_ms,
+        "wall_ms_per_step": wall_ms, "profiled_ms_per_step": prof_ms,
         "schur_ops": stats["schur_ops"], "algorithmic_flops": flops, "executed_flops": stats["executed_flops"],
         "workspace_bytes": stats["workspace_bytes"], "workspace_blocks": stats["slots"],
         "kernel_launches_per_step": stats["kernel_launches"],
@@ -194,6 +236,20 @@ def main() -> int:
                     refs[(vi, vj)] = oracle.invert_block(m_host, k, vi, vj)
                 entry["rel_error"] = rel_err(o2.double().cpu().numpy(), refs[(vi, vj)])
             variants.append(entry)
+        # mixed precision on the same workload: float recursion (FP32, split
+        # FP16 or split BF16 MFMA products) with FP64 refinement of the block
+        # column; value = F / time including refinement (extra work not credited)
+        f64_ms = ms
+        for prec in ("mixed_f32", "mixed_f16", "mixed_bf16"):
+            c2, o2, inf2 = setup(M64, i, j, prec)
+            vms, _ = time_calls(c2, max(1, args.steps // 3), 1, torch)
+            sweeps, last = bri.refine_last()
+            entry = {"block": [i, j], "precision": prec, "ms_per_step": vms,
+                     "tflops": flops / (vms * 1e-3) / 1e12, "speed_vs_f64": f64_ms / vms,
+                     "refine_sweeps": sweeps, "last_rel_correction": last, "info": int(inf2.item())}
+            if not args.no_cpu_baseline:
+                entry["rel_error"] = rel_err(o2.cpu().numpy(), refs[(i, j)])
+            variants.append(entry)
         # latency case n = 256, k = 2 (FP64)
         m1 = workloads.workload_matrix("dd_n256_k2")
         M1 = torch.from_numpy(m1).to(dev)
@@ -208,6 +264,60 @@ def main() -> int:
             e1["rel_error"] = rel_err(o1.cpu().numpy(), oracle.invert_block(m1, 2, 0, 0))
         variants.append(e1)
         line["variants"] = variants
+
+    # ---- batched workload: 512 problems, n in [64, 1024], k in {2,3,4} ---------
+    if not args.no_batched:
+        probs = workloads.batch_problems()
+        mats = [workloads.batch_matrix(p) for p in probs]
+        bflops = sum(bri.plan_describe(p.n, p.k, p.i, p.j, "f64")["algorithmic_flops"] for p in probs)
+        ks, ii, jj = [p.k for p in probs], [p.i for p in probs], [p.j for p in probs]
+        sample = list(range(0, len(probs), 32))
+        dense = {}
+        for t in sample:
+            p = probs[t]
+            b = bri.block_size(p.n, p.k)
+            g = np.eye(p.k * b)
+            g[:p.n, :p.n] = mats[t]
+            dense[t] = np.linalg.inv(g)[p.i * b:(p.i + 1) * b, p.j * b:(p.j + 1) * b]
+        batched = []
+        for prec in ("mixed_f32", "f64", "f32"):
+            dt = torch.float32 if prec == "f32" else torch.float64
+            Ms = [torch.from_numpy(m).to(dev, dt) for m in mats]
+            binfo = torch.zeros(len(probs), dtype=torch.int32, device=dev)
+            outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo)
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo)
+            torch.cuda.synchronize()
+            bms = (time.perf_counter() - t0) * 1e3 / reps
+            err = max(rel_err(outs[t].double().cpu().numpy(), dense[t]) for t in sample)
+            batched.append({"precision": prec, "ms_per_batch": bms, "tflops": bflops / (bms * 1e-3) / 1e12,
+                            "problems_per_s": len(probs) / (bms * 1e-3), "max_rel_error_sampled": err,
+                            "info_nonzero": int((binfo != 0).sum().item()),
+                            "refine_sweeps": bri.refine_last()[0] if prec.startswith("mixed") else 0})
+            del Ms, outs
+        line["batched"] = {"workload": "512 problems, n ~ U[64,1024], k ~ U{2,3,4}, random block, Gaussian + n I, "
+                                       "seeds SeedSequence(5).spawn(512); error vs dense inverse on every 32nd problem",
+                           "algorithmic_flops": bflops, "runs": batched}
+
+    # ---- adjoint: n = 8192, k = 4, FP32, dL/dM for L = sum(W * N_00) --------
+    if not args.no_backward:
+        wlg = workloads.WORKLOADS["dd_n8192_k4_grad"]
+        mg = torch.from_numpy(workloads.workload_matrix(wlg.name)).to(dev, torch.float32)
+        bg = bri.block_size(wlg.n, wlg.k)
+        W = torch.from_numpy(workloads.cotangent(bg, seed=4)).to(dev, torch.float32)
+        gi, gj = wlg.targets[0]
+        grad = bri.invert_block_backward(mg, wlg.k, gi, gj, W, precision="f32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        grad = bri.invert_block_backward(mg, wlg.k, gi, gj, W, precision="f32")
+        torch.cuda.synchronize()
+        gms = (time.perf_counter() - t0) * 1e3
+        line["backward"] = {"workload": "dd_n8192_k4_grad: n=8192 k=4 b=2048, Gaussian + n I, block (0,0), FP32",
+                            "ms": gms, "finite": bool(torch.isfinite(grad).all().item())}
+        del grad, mg
 
     print(json.dumps(line), flush=True)
     return 0

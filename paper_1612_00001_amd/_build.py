@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import concurrent.futures
 import os
+import re
 import subprocess
 import sys
 
@@ -20,15 +21,40 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
           "-I" + os.path.join(HERE, "..", "include"), "-I" + CSRC]
 
 
+RESOURCE_REPORT = os.path.join(BUILD, "kernel_resources.txt")
+
+
+def _resources(text: str) -> list:
+    """(kernel, VGPRs, AGPRs, scratch bytes per lane) from hipcc's resource remarks."""
+    rows, cur = [], None
+    for line in text.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            cur = {"name": m.group(1)}
+            rows.append(cur)
+            continue
+        m = re.search(r"remark:\s+(VGPRs|AGPRs|ScratchSize) ?(?:\[bytes/lane\])?: (\d+)", line)
+        if m and cur is not None:
+            cur[m.group(1)] = int(m.group(2))
+    return rows
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".hip"):
-        cmd[1:1] = ["-x", "hip", *DEVICE_FLAGS]
+        cmd[1:1] = ["-x", "hip", *DEVICE_FLAGS, "-Rpass-analysis=kernel-resource-usage"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError(f"hipcc failed on {src}")
+    if src.endswith(".hip"):
+        # Per-kernel register and scratch use, kept for inspection and tests.
+        rows = _resources(r.stderr)
+        with open(os.path.join(BUILD, os.path.splitext(src)[0] + ".resources.txt"), "w") as f:
+            for row in rows:
+                f.write(f"{row['name']} vgprs={row.get('VGPRs', 0)} agprs={row.get('AGPRs', 0)} "
+                        f"scratch={row.get('ScratchSize', 0)}\n")
     return obj
 
 

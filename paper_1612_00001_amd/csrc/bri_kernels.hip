@@ -1032,6 +1032,7 @@ __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
     xs[q] = xq;
 #pragma unroll
     for (int i = q + 1; i < kTile; ++i) xs[i] = fma(-Mq[q * LD + i], xq, xs[i]);
+    wave_lds_order();  // keeps each step's LDS reads next to their use (no hoisting, no spills)
   }
   T* aux = static_cast<T*>(it.aux);
   if (half == 0) {
@@ -1261,14 +1262,20 @@ hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n
   if constexpr (sizeof(T) == 4) {
     if (L.lp) return launch_gemm_lp<MODE, GEN>(L, count, max_m, max_n, st);
   }
-  const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * count;
-  if (big_tiles >= 256) {
-    dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), count);
-    hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 128, 16, 64, 64>), grid, dim3(256), 0, st, L);
-  } else {
-    dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), count);
-    hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 64, 64, 16, 32, 32>), grid, dim3(256), 0, st, L);
+  // Large products: 128 x 256 output tiles, 16 wavefronts of 64 x 32 (four
+  // per SIMD, so MFMA issue continues while other wavefronts wait on LDS or
+  // memory); small ones: 64 x 64 tiles for more workgroups.
+  // The generic (element-wise view) instance always takes the small tiles.
+  if constexpr (!GEN) {
+    const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 256) * count;
+    if (big_tiles >= 192) {
+      dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 256), count);
+      hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 256, 16, 64, 32>), grid, dim3(1024), 0, st, L);
+      return hipGetLastError();
+    }
   }
+  dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), count);
+  hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 64, 64, 16, 32, 32>), grid, dim3(256), 0, st, L);
   return hipGetLastError();
 }
 

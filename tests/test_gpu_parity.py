@@ -223,3 +223,41 @@ def test_batched_512_problems_merged(precision):
         worst = max(worst, err)
     print(f"  worst rel err {worst:.2e}", flush=True)
     assert worst < (1e-12 if precision == "f64" else 64 * EPS32 * 2)
+
+
+def test_backward_directional_finite_differences_n64():
+    # Central differences of the GPU forward pass along random directions
+    # against <dL/dM, D> from the GPU adjoint (FP64, n = 64, k = 4).
+    n, k, i, j = 64, 4, 0, 0
+    m = workloads.gaussian_dd(n, 4)
+    w = workloads.cotangent(16, seed=4)
+    g = bri.invert_block_backward(gpu(m), k, i, j, gpu(w)).cpu().numpy()
+    rng = np.random.default_rng(7)
+    for _ in range(4):
+        d = rng.standard_normal((n, n))
+        h = 1e-4
+        lp = float((w * bri.invert_block(gpu(m + h * d), k, i, j).cpu().numpy()).sum())
+        lm = float((w * bri.invert_block(gpu(m - h * d), k, i, j).cpu().numpy()).sum())
+        fd = (lp - lm) / (2 * h)
+        an = float((g * d).sum())
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (fd, an)
+
+
+def test_backward_fp32_n8192_k4_against_dense_inverse():
+    # The adjoint workload at its full size (n = 8192, k = 4, FP32): the
+    # gradient -(N_{0,:})^T W (N_{:,0})^T against the same formula built from a
+    # dense FP64 inverse (rocSOLVER through torch, not this library).
+    wl = workloads.WORKLOADS["dd_n8192_k4_grad"]
+    m = workloads.workload_matrix(wl.name)
+    b = bri.block_size(wl.n, wl.k)
+    w = workloads.cotangent(b, seed=4)
+    print("backward n=8192 k=4 fp32", flush=True)
+    g = bri.invert_block_backward(gpu(m, torch.float32), wl.k, 0, 0, gpu(w, torch.float32), precision="f32")
+    torch.cuda.synchronize()
+    inv = torch.linalg.inv(gpu(m))
+    row = inv[0:b, :]          # N_{0,:}
+    col = inv[:, 0:b]          # N_{:,0}
+    want = -(row.T.contiguous() @ gpu(w)) @ col.T.contiguous()
+    err = float(torch.linalg.norm(g.double() - want) / torch.linalg.norm(want))
+    print(f"  rel err {err:.2e}", flush=True)
+    assert err < 1e-4

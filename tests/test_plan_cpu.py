@@ -264,3 +264,21 @@ def test_refine_solve_uses_three_way_recursion():
         # x_last: value of depth k-1 (+1 solve); x_q at position p: (k - p) values of depth p (+1 solve)
         want = c3[k - 1] + 1 + sum((k - p) * c3[p] + 1 for p in range(k - 1))
         assert trmm_l == want, (k, trmm_l, want)
+
+
+def test_no_kernel_spills_to_scratch():
+    # The build records every kernel's register and scratch use (hipcc
+    # resource remarks); a spill to scratch memory turns register traffic
+    # into memory traffic in the hot loops.
+    build_dir = os.path.join(ROOT, "paper_1612_00001_amd", "_build")
+    reports = [os.path.join(build_dir, f) for f in ("bri_kernels.resources.txt", "bri_refine.resources.txt")]
+    if not all(os.path.exists(r) for r in reports):
+        pytest.skip("kernel resource report not built (run __graft_entry__.build())")
+    spills = []
+    for r in reports:
+        for line in open(r):
+            name, *fields = line.split()
+            kv = dict(f.split("=") for f in fields)
+            if int(kv["scratch"]) > 0:
+                spills.append(name)
+    assert not spills, spills

@@ -899,36 +899,36 @@ __device__ __forceinline__ float tile_rcp(float d) {
   return fmaf(r, e, r);
 }
 
-// Pivot search key of a row for a column: the bits of |y| (a NaN orders
-// above +inf) with the low five bits replaced by 31 - r, so that one unsigned
-// 64-bit maximum picks the largest magnitude and, among magnitudes equal to
-// within the dropped bits, the lowest row; 0 when the row is not a candidate.
-__device__ __forceinline__ uint64_t pivot_key(double y, bool cand, int r) {
-  const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(fabs(y)));
-  return cand ? ((bits & ~static_cast<uint64_t>(31)) | static_cast<uint64_t>(31 - r)) : 0;
+// Pivot search key of a row for a column, 32 bits: the leading bits of |y|
+// (sign cleared, so the unsigned order is the order of magnitudes and a NaN
+// orders above +inf) with the low five bits replaced by 31 - r; one unsigned
+// maximum then picks the largest magnitude and, among magnitudes equal in
+// their leading 27 bits (15 mantissa bits for double, 18 for float), the
+// lowest row.  0 when the row is not a candidate.
+__device__ __forceinline__ uint32_t pivot_key(double y, bool cand, int r) {
+  const uint32_t hi = static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(fabs(y))) >> 32);
+  return cand ? ((hi & ~31u) | static_cast<uint32_t>(31 - r)) : 0u;
 }
-__device__ __forceinline__ uint64_t pivot_key(float y, bool cand, int r) {
-  const uint64_t bits = static_cast<uint32_t>(__float_as_int(fabsf(y)));
-  return cand ? ((bits << 5) | static_cast<uint64_t>(31 - r)) : 0;
+__device__ __forceinline__ uint32_t pivot_key(float y, bool cand, int r) {
+  const uint32_t bits = static_cast<uint32_t>(__float_as_int(fabsf(y)));
+  return cand ? ((bits & ~31u) | static_cast<uint32_t>(31 - r)) : 0u;
 }
 
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ void dpp_max_step(uint64_t& k) {
-  const int lo = static_cast<int>(k & 0xffffffff), hi = static_cast<int>(k >> 32);
-  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
-  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
-  const uint64_t o = (static_cast<uint64_t>(static_cast<uint32_t>(ohi)) << 32) | static_cast<uint32_t>(olo);
-  k = o > k ? o : k;
+__device__ __forceinline__ uint32_t dpp_umax(uint32_t k) {
+  const uint32_t o = static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(static_cast<int>(k), static_cast<int>(k), CTRL, ROW_MASK, 0xf, false));
+  return o > k ? o : k;
 }
 // Row of the largest key among the 32 lanes of half h (a wave-uniform value).
-__device__ __forceinline__ int half_argmax(uint64_t k, int h) {
-  dpp_max_step<0xB1, 0xf>(k);   // quad_perm [1,0,3,2]
-  dpp_max_step<0x4E, 0xf>(k);   // quad_perm [2,3,0,1]
-  dpp_max_step<0x141, 0xf>(k);  // row_half_mirror
-  dpp_max_step<0x140, 0xf>(k);  // row_mirror
-  dpp_max_step<0x142, 0xa>(k);  // row_bcast:15: lanes 31 and 63 hold their half's maximum
-  const int lo = __builtin_amdgcn_readlane(static_cast<int>(k & 0xffffffff), h ? 63 : 31);
-  return 31 - (lo & 31);
+__device__ __forceinline__ int half_argmax(uint32_t k, int h) {
+  k = dpp_umax<0xB1, 0xf>(k);   // quad_perm [1,0,3,2]
+  k = dpp_umax<0x4E, 0xf>(k);   // quad_perm [2,3,0,1]
+  k = dpp_umax<0x141, 0xf>(k);  // row_half_mirror
+  k = dpp_umax<0x140, 0xf>(k);  // row_mirror
+  k = dpp_umax<0x142, 0xa>(k);  // row_bcast:15: lanes 31 and 63 hold their half's maximum
+  const int top = __builtin_amdgcn_readlane(static_cast<int>(k), h ? 63 : 31);
+  return 31 - (top & 31);
 }
 
 template <typename T>
@@ -977,14 +977,15 @@ __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
     const T rinv = piv != T(0) ? tile_rcp(piv) : T(0);
     const bool act = !done && r < ts && r != p;
     const T lm = act ? xc * rinv : T(0);
-    if (half == 0 && act) sL[r][C] = lm;
+    sL[r][C] = lm;  // every lane (both halves store the same value); read only for rows chosen later
     if (r == p) {
       done = true;
       pos = C;
     }
     const T yn = fma(-lm, u1, yc);  // column C + 1 after this step
-    int pn = 0;
-    if (C + 1 < ts) pn = half_argmax(pivot_key(yn, half == 0 && !done && r < ts, r), 0);
+    // Pivot of column C + 1 (computed unconditionally so the step is one
+    // basic block; unused after the last column).
+    const int pn = half_argmax(pivot_key(yn, half == 0 && !done && r < ts, r), 0);
     const T z = fma(-lm, u2, y2);   // column C + 2 after this step
 #pragma unroll
     for (int t = 0; t < 16; ++t) a[t] = fma(-lm, sR[p][16 * half + t], a[t]);  // same operations as yn and z

@@ -51,16 +51,28 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_gemm_explicit_hbm_traffic_sp
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1612_00001_amd", "csrc", "bri_kernels.hip")
 
 
+def gemm_source_digest():
+    """sha256 over the source of the product kernel: its operand loaders and
+    kernel body (from the "Operand tiles." section to the low-precision
+    kernel) and its tile-shape selection (launch_gemm_mode)."""
+    import hashlib
+    text = open(KERNEL_SOURCE).read()
+    a = text.index("// Operand tiles.")
+    e = text.index("// Low-precision products")
+    c = text.index("hipError_t launch_gemm_mode(")
+    d = text.index("\n}\n", c)
+    return hashlib.sha256((text[a:e] + text[c:d]).encode()).hexdigest()
+
+
 def counted_traffic():
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size),
     or None when the summary is missing or the kernel source has changed
     since the counters were taken."""
-    import hashlib
     try:
         text = open(TRAFFIC_SUMMARY).read()
-        digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    except OSError:
+        digest = gemm_source_digest()
+    except (OSError, ValueError):
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("traffic_bytes", "source_sha256")))
     if fields.get("source_sha256", "").strip() != digest:

@@ -272,6 +272,9 @@ struct TileOp {
 // own kernel instance so that profiles separate the Schur products from the
 // LU and triangular-inversion updates.
 // ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void tile_lu_wave(const LuItem& it, int t0, int wprev);
+
 template <typename T, int MODE, bool GEN, int BM, int BN, int BK, int WM, int WN>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch L) {
   constexpr int NWN = BN / WN;
@@ -282,6 +285,15 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
   constexpr int AE = OpA::E, BE = OpB::E;
   static_assert(AE * NT == BM * BK && BE * NT == BK * BN, "tile/thread mismatch");
   constexpr bool USE_PERM = (MODE == GEMM_EXPLICIT) && !GEN;
+
+  if constexpr (MODE == GEMM_LU_TRAILING) {
+    // Look-ahead (L.npairs != 0): the last workgroup of every matrix updates
+    // and factors the next diagonal tile while the others update the rest.
+    if (L.npairs && blockIdx.x == gridDim.x - 1) {
+      if (threadIdx.x < 64) tile_lu_wave<T>(static_cast<const LuItem*>(L.items)[blockIdx.y], L.j + L.w, L.w);
+      return;
+    }
+  }
 
   GemmItem it;
   if (!gemm_item<T, MODE>(L, blockIdx.y + (GEN ? L.j : 0), it)) return;
@@ -390,7 +402,9 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
       for (int v = 0; v < 4; ++v) {
         const int r = m0 + wm * WM + i * 16 + MF<T>::row(lane, v);
         const int c = n0 + wn * WN + j * 16 + (lane & 15);
-        if (r < it.M && c < it.N) {
+        // look-ahead: the next diagonal tile belongs to the factorising workgroup
+        const bool skip = MODE == GEMM_LU_TRAILING && L.npairs && r < kTile && c < kTile;
+        if (r < it.M && c < it.N && !skip) {
           T val = alpha * acc[i][j][v];
           // The fast instance only receives plain Cin / Sub (gemm_item_is_fast).
           if (it.has_cin)
@@ -931,10 +945,13 @@ __device__ __forceinline__ int half_argmax(uint32_t k, int h) {
   return 31 - (top & 31);
 }
 
+// One wavefront (threads 0..63 of its workgroup; the function synchronises
+// only within the wavefront).  With wprev > 0 the tile first receives the
+// rank-wprev update of the previous panel, A_tt -= L(t, prev) U(prev, t)
+// (the look-ahead form used inside the trailing-update launch).
 template <typename T>
-__global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
+__device__ __forceinline__ void tile_lu_wave(const LuItem& it, int t0, int wprev) {
   constexpr int LD = kTile + 2;
-  const LuItem it = items[blockIdx.x];
   if (t0 >= it.b) return;  // a smaller matrix of a merged batch
   T* A = static_cast<T*>(it.a);
   const int b = it.b, ts = min(kTile, b - t0);
@@ -949,6 +966,24 @@ __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
   for (int t = 0; t < 16; ++t) {
     const int c = 16 * half + t;
     a[t] = (r < ts && c < ts) ? A[static_cast<int64_t>(t0 + r) * b + t0 + c] : (r == c ? T(1) : T(0));
+  }
+  if (wprev > 0) {
+    // Previous panel's multipliers (rows of this tile) and U rows (columns of
+    // this tile), staged in LDS; the update runs in ascending q.
+    const int p0 = t0 - wprev;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int q = 16 * half + t;
+      sL[r][q] = (r < ts && q < wprev) ? A[static_cast<int64_t>(t0 + r) * b + p0 + q] : T(0);
+      sF[r][q] = (r < wprev && q < ts) ? A[static_cast<int64_t>(p0 + r) * b + t0 + q] : T(0);
+    }
+    wave_lds_order();
+    for (int q = 0; q < wprev; ++q) {
+      const T lq = sL[r][q];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) a[t] = fma(-lq, sF[q][16 * half + t], a[t]);
+    }
+    wave_lds_order();
   }
   bool done = false;
   int pos = r;  // position of this row in the factored tile (rows >= ts keep theirs)
@@ -998,7 +1033,7 @@ __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
     p = pn;
   }
   if (bad && l == 0 && it.info) atomicCAS(it.info, 0, it.node + 1);
-  __syncthreads();
+  wave_lds_order();
   // Factored row in pivot order: multipliers left of its pivot column, U
   // from there on (rows past the tile edge are identity rows).
 #pragma unroll
@@ -1011,13 +1046,13 @@ __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
   }
   // Row movement of the tile: position pos holds original tile row r.  Rows
   // never leave their band, so the band's permutation entries are t0 + r.
-  __syncthreads();
+  wave_lds_order();
   if (half == 0 && r < ts) {
     it.swaps[1 + pos] = r;
     it.perm[t0 + pos] = t0 + r;
   }
   if (l < kTile) sD[l] = T(1) / sF[l][l];
-  __syncthreads();
+  wave_lds_order();
   // Inverses of the tile's triangular factors by forward substitution in
   // column (axpy) form, every update of a step independent:
   //   lanes 0..31 : column r of L^{-1}        (L unit lower: L[i][q] = sFT[q][i]);
@@ -1043,6 +1078,11 @@ __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
 #pragma unroll
     for (int i = 0; i < kTile; ++i) aux[kTile * kTile + r * kTile + i] = xs[i];  // U^{-1}[r][i]
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
+  tile_lu_wave<T>(items[blockIdx.x], t0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1267,15 +1307,19 @@ hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n
   // per SIMD, so MFMA issue continues while other wavefronts wait on LDS or
   // memory); small ones: 64 x 64 tiles for more workgroups.
   // The generic (element-wise view) instance always takes the small tiles.
-  if constexpr (!GEN) {
+  // Look-ahead trailing updates carry one more workgroup per matrix.  Those
+  // rank-32 updates are bound by memory, not MFMA, and take the 64 x 64 tiles
+  // (256 threads: the factorising wavefront keeps its full register budget).
+  const int extra = (MODE == GEMM_LU_TRAILING && L.npairs) ? 1 : 0;
+  if constexpr (!GEN && MODE != GEMM_LU_TRAILING) {
     const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 256) * count;
     if (big_tiles >= 192) {
-      dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 256), count);
+      dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 256) + extra, count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 256, 16, 64, 32>), grid, dim3(1024), 0, st, L);
       return hipGetLastError();
     }
   }
-  dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), count);
+  dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64) + extra, count);
   hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 64, 64, 16, 32, 32>), grid, dim3(256), 0, st, L);
   return hipGetLastError();
 }
@@ -1306,9 +1350,12 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
 
 template <typename T>
 hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, hipStream_t st) {
+  // Tile t + 1 is updated and factored inside the trailing-update launch of
+  // tile t (look-ahead), so per tile step the critical path is the strip
+  // solves followed by the longer of the trailing update and the next tile.
+  hipLaunchKernelGGL((k_tile_lu<T>), dim3(count), dim3(64), 0, st, d_items, 0);
   for (int t0 = 0; t0 < b; t0 += kTile) {
     const int ts = std::min(kTile, b - t0);
-    hipLaunchKernelGGL((k_tile_lu<T>), dim3(count), dim3(64), 0, st, d_items, t0);
     const int rest = b - t0 - ts;
     const int nblk = 2 * cdiv(rest, 64) + cdiv(t0, 64);
     if (nblk > 0) hipLaunchKernelGGL((k_tile_strips<T>), dim3(nblk, count), dim3(256), 0, st, d_items, t0);
@@ -1320,6 +1367,7 @@ hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, hipStream_
       L.count = count;
       L.j = t0;
       L.w = ts;
+      L.npairs = 1;  // look-ahead
       hipError_t e = launch_gemm<T>(L, rest, rest, st);
       if (e != hipSuccess) return e;
     }

@@ -104,6 +104,48 @@ def time_calls(fn, steps, warmup, torch):
     return ev0.elapsed_time(ev1) / steps, wall
 
 
+def precision_workload(bri, workloads, torch, np) -> int:
+    """n = 16384, k = 8 (b = 2048), Q Lam Q^T with cond 1e4 (generated on the
+    device, same recipe as the host generator), block (0,0): the plain FP64
+    path and the mixed paths, each timed once, against a dense FP64 solve of
+    M X = E_0 on the device (torch.linalg.solve, not this library)."""
+    wl = workloads.WORKLOADS["spd_n16384_k8"]
+    n, k = wl.n, wl.k
+    i, j = wl.targets[0]
+    b = bri.block_size(n, k)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    M = workloads.haar_spd_device(n, wl.seed, 0.0, 4.0, pin_endpoints=True, device=dev)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    e = torch.zeros(n, b, dtype=torch.float64, device=dev)
+    e[j * b:(j + 1) * b] = torch.eye(b, dtype=torch.float64, device=dev)
+    ref = torch.linalg.solve(M, e)[i * b:(i + 1) * b].contiguous()
+    del e
+    torch.cuda.synchronize()
+    flops = bri.plan_describe(n, k, i, j, "f64")["algorithmic_flops"]
+    runs = []
+    for prec in ("f64", "mixed_f16", "mixed_bf16", "mixed_f32"):
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        ws = torch.empty(bri.workspace_size(n, k, i, j, prec), dtype=torch.uint8, device=dev)
+        print(f"precision workload: {prec}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = bri.invert_block(M, k, i, j, precision=prec, info=info, workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = float(torch.linalg.norm(out - ref) / torch.linalg.norm(ref))
+        sweeps = bri.refine_last()[0] if prec.startswith("mixed") else 0
+        runs.append({"precision": prec, "s": dt, "tflops": flops / dt / 1e12, "rel_error_vs_dense_solve": err,
+                     "refine_sweeps": sweeps, "info": int(info.item()), "workspace_bytes": ws.numel()})
+        print(json.dumps(runs[-1]), file=sys.stderr, flush=True)
+        del ws, out
+    print(json.dumps({"workload": "spd_n16384_k8: n=16384 k=8 b=2048, Q Lam Q^T, cond 1e4 (Lam pinned at 1 and 1e4), "
+                                  "block (0,0), matrix generated on the device",
+                      "algorithmic_flops": flops, "generation_s": gen_s, "runs": runs}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +155,8 @@ def main() -> int:
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--precision-workload", action="store_true",
+                    help="run only the n=16384, k=8 (cond 1e4) precision workload once per precision and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -137,6 +181,9 @@ def main() -> int:
 
     import paper_1612_00001_amd as bri
     import workloads
+
+    if args.precision_workload:
+        return precision_workload(bri, workloads, torch, np)
 
     dev = torch.device("cuda:0")
     lib = bri.lib()

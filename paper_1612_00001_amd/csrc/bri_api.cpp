@@ -104,15 +104,19 @@ int64_t leaves_of(int k) { return static_cast<int64_t>(std::pow(4.0, std::max(0,
 int auto_width(int64_t n, int k, int precision) {
   const int64_t b = (n + k - 1) / k;
   const int64_t tiles = ((b + 127) / 128) * ((b + 127) / 128);
-  // Enough independent Schur operations for ~2048 output tiles of 128 x 128,
-  // rounded up to a power of 4 (the lock-step batch sizes).
+  // At least enough independent Schur operations for ~2048 output tiles of
+  // 128 x 128, rounded up to a power of 4 (the lock-step batch sizes); deeper
+  // recursions (more leaves) go wider, up to 256 nodes side by side, because
+  // every lock-step batch pays one factorisation latency.
   int64_t w = 1;
   while (w * tiles < 2048) w *= 4;
-  // Keep the live workspace of the batch within 16 GiB.
+  while (w < 256 && w * 4 <= leaves_of(k) && w * 16 <= leaves_of(k)) w *= 4;
+  // Keep the live workspace of the batch within 32 GiB.
   const double per = static_cast<double>(k + 4) * b * b * elem_size(precision);
-  const int64_t wmem = std::max<int64_t>(1, static_cast<int64_t>((16.0 * (1ull << 30)) / per));
+  int64_t wmem = 1;
+  while (wmem * 4 * per <= 32.0 * (1ull << 30)) wmem *= 4;
   w = std::min(w, wmem);
-  return static_cast<int>(std::min<int64_t>(w, leaves_of(k)));
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(w, leaves_of(k))));
 }
 
 int resolve_width(int64_t n, int k, const bri_opts* o) {

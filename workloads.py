@@ -75,6 +75,31 @@ def haar_spd(n: int, seed, lo_exp: float = 0.0, hi_exp: float = 2.0,
     return SpdMatrix(m=m, q=q, lam=lam)
 
 
+def haar_spd_device(n: int, seed, lo_exp: float = 0.0, hi_exp: float = 2.0, pin_endpoints: bool = False,
+                    device="cuda:0"):
+    """The ``haar_spd`` recipe with the O(n^3) steps (QR, Q Lam Q^T) done by
+    torch on ``device`` in float64, for sizes where the host would take
+    minutes.  Same draws as ``haar_spd`` (the Gaussian and the eigenvalues
+    come from the same seeded generator, in the same order); Q differs from
+    the host one only by rounding (the QR is unique once the sign of
+    diag(R) is fixed).  Returns a float64 device tensor."""
+    import torch
+
+    rng = rng_for(seed)
+    z = torch.from_numpy(rng.standard_normal((n, n))).to(device)
+    lam = 10.0 ** rng.uniform(lo_exp, hi_exp, size=n)
+    if pin_endpoints and n >= 2:
+        lam[0] = 10.0 ** lo_exp
+        lam[-1] = 10.0 ** hi_exp
+    q, r = torch.linalg.qr(z)
+    del z
+    q *= torch.sign(torch.diagonal(r))[None, :]
+    del r
+    m = (q * torch.from_numpy(lam).to(device)[None, :]) @ q.T.contiguous()
+    del q
+    return 0.5 * (m + m.T)
+
+
 def tridiag_toeplitz(n: int, diag: float = 4.0, off: float = -1.0) -> np.ndarray:
     """Constant tridiagonal matrix with ``diag`` on the diagonal and ``off`` beside it."""
     t = np.zeros((n, n))

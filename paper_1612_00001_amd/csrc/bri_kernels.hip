@@ -461,13 +461,14 @@ struct LPT<2> {  // BF16, three parts
   __device__ static f4_t mma(V a, V b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
 
-template <int LP, int MODE, bool GEN>
-__global__ __launch_bounds__(256) void k_gemm_lp(GemmLaunch L) {
+template <int LP, int MODE, bool GEN, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lp(GemmLaunch L) {
   typedef LPT<LP> P;
   typedef typename P::E E;
   typedef typename P::V V;
   constexpr int NP = P::PARTS;
-  constexpr int BM = 64, BN = 64, BK = 32, NT = 256, WM = 32, WN = 32, KP = BK + 8;
+  constexpr int NWN = BN / WN, FM = WM / 16, FN = WN / 16;
+  constexpr int BK = 32, NT = (BM / WM) * NWN * 64, KP = BK + 8;
   typedef TileOp<float, BM, BK, NT> OpA;
   typedef TileOp<float, BK, BN, NT> OpB;
   constexpr int AE = OpA::E, BE = OpB::E;
@@ -490,7 +491,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(GemmLaunch L) {
   __shared__ __attribute__((aligned(16))) E Bs[2][NP][BN][KP];
   __shared__ int32_t s_perm[(MODE == GEMM_EXPLICIT && !GEN) ? kMaxBlock : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / NWN, wn = wave % NWN;
 
   OpA opa;
   OpB opb;
@@ -511,11 +512,11 @@ __global__ __launch_bounds__(256) void k_gemm_lp(GemmLaunch L) {
   opa.init(it.A, permA, it.M, it.K, tid);
   opb.init(it.B, permB, it.K, it.N, tid);
 
-  f4_t acc[2][2], accx[2][2];
+  f4_t acc[FM][FN], accx[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         acc[i][j][v] = 0.f;
@@ -556,18 +557,21 @@ __global__ __launch_bounds__(256) void k_gemm_lp(GemmLaunch L) {
     for (int k0 = kb; k0 < ke; k0 += BK) {
       const bool more = k0 + BK < ke;
       if (more) issue(k0 + BK);
-      V a[2][NP], bv[2][NP];
+      V a[FM][NP], bv[FN][NP];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
+        for (int q = 0; q < NP; ++q)
           a[i][q] = *reinterpret_cast<const V*>(&As[buf][q][wm * WM + i * 16 + (lane & 15)][8 * (lane >> 4)]);
-          bv[i][q] = *reinterpret_cast<const V*>(&Bs[buf][q][wn * WN + i * 16 + (lane & 15)][8 * (lane >> 4)]);
-        }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < FN; ++j)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int q = 0; q < NP; ++q)
+          bv[j][q] = *reinterpret_cast<const V*>(&Bs[buf][q][wn * WN + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
           if (LP == 1) {
             acc[i][j] = P::mma(a[i][0], bv[j][0], acc[i][j]);
             accx[i][j] = P::mma(a[i][0], bv[j][1], accx[i][j]);
@@ -593,9 +597,9 @@ __global__ __launch_bounds__(256) void k_gemm_lp(GemmLaunch L) {
   const float* subp = static_cast<const float*>(it.Sub.p);
   const float xs = (LP == 1) ? (1.0f / 2048.0f) : 1.0f;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + v;
@@ -1287,13 +1291,31 @@ namespace {
 inline int cdiv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 }  // namespace
 
+template <int LP, int MODE, bool GEN, int BM, int BN, int WM, int WN>
+void launch_lp_shape(const GemmLaunch& L, int count, int max_m, int max_n, hipStream_t st) {
+  dim3 grid(cdiv(max_m, BM) * cdiv(max_n, BN), count);
+  hipLaunchKernelGGL((k_gemm_lp<LP, MODE, GEN, BM, BN, WM, WN>), grid, dim3((BM / WM) * (BN / WN) * 64), 0, st, L);
+}
+
 template <int MODE, bool GEN>
 hipError_t launch_gemm_lp(const GemmLaunch& L, int count, int max_m, int max_n, hipStream_t st) {
-  dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), count);
+  // Large products: 128 x 128 tiles, 16 wavefronts of 32 x 32 (four per
+  // SIMD hide the splitting, LDS and memory latency between MFMA issues);
+  // small ones: 64 x 64.
+  if constexpr (!GEN) {
+    const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * count;
+    if (big_tiles >= 256) {
+      if (L.lp == 1)
+        launch_lp_shape<1, MODE, GEN, 128, 128, 32, 32>(L, count, max_m, max_n, st);
+      else
+        launch_lp_shape<2, MODE, GEN, 128, 128, 32, 32>(L, count, max_m, max_n, st);
+      return hipGetLastError();
+    }
+  }
   if (L.lp == 1)
-    hipLaunchKernelGGL((k_gemm_lp<1, MODE, GEN>), grid, dim3(256), 0, st, L);
+    launch_lp_shape<1, MODE, GEN, 64, 64, 32, 32>(L, count, max_m, max_n, st);
   else
-    hipLaunchKernelGGL((k_gemm_lp<2, MODE, GEN>), grid, dim3(256), 0, st, L);
+    launch_lp_shape<2, MODE, GEN, 64, 64, 32, 32>(L, count, max_m, max_n, st);
   return hipGetLastError();
 }
 

@@ -125,18 +125,20 @@ def precision_workload(bri, workloads, torch, np) -> int:
     torch.cuda.synchronize()
     flops = bri.plan_describe(n, k, i, j, "f64")["algorithmic_flops"]
     runs = []
-    for prec in ("f64", "mixed_f16", "mixed_bf16", "mixed_f32"):
+    for prec, reuse in (("f64", False), ("mixed_f16", False), ("mixed_bf16", False), ("mixed_f32", False),
+                        ("f64", True), ("mixed_f16", True), ("mixed_bf16", True)):
         info = torch.zeros(1, dtype=torch.int32, device=dev)
-        ws = torch.empty(bri.workspace_size(n, k, i, j, prec), dtype=torch.uint8, device=dev)
-        print(f"precision workload: {prec}", file=sys.stderr, flush=True)
+        ws = torch.empty(bri.workspace_size(n, k, i, j, prec, reuse=reuse), dtype=torch.uint8, device=dev)
+        print(f"precision workload: {prec} reuse={reuse}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = bri.invert_block(M, k, i, j, precision=prec, info=info, workspace=ws)
+        out = bri.invert_block(M, k, i, j, precision=prec, info=info, workspace=ws, reuse=reuse)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         err = float(torch.linalg.norm(out - ref) / torch.linalg.norm(ref))
         sweeps = bri.refine_last()[0] if prec.startswith("mixed") else 0
-        runs.append({"precision": prec, "s": dt, "tflops": flops / dt / 1e12, "rel_error_vs_dense_solve": err,
+        runs.append({"precision": prec, "reuse_pivots": reuse, "s": dt, "paper_equivalent_tflops": flops / dt / 1e12,
+                     "rel_error_vs_dense_solve": err,
                      "refine_sweeps": sweeps, "info": int(info.item()), "workspace_bytes": ws.numel()})
         print(json.dumps(runs[-1]), file=sys.stderr, flush=True)
         del ws, out
@@ -193,15 +195,15 @@ def main() -> int:
     M64 = torch.from_numpy(m_host).to(dev)
     M32 = M64.float()
 
-    def setup(M, i, j, precision):
-        need = bri.workspace_size(n, k, i, j, precision)
+    def setup(M, i, j, precision, reuse=False):
+        need = bri.workspace_size(n, k, i, j, precision, reuse=reuse)
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
         b = bri.block_size(n, k)
         out = torch.empty(b, b, dtype=M.dtype, device=dev)
         info = torch.zeros(1, dtype=torch.int32, device=dev)
 
         def call():
-            bri.invert_block(M, k, i, j, precision=precision, out=out, info=info, workspace=ws)
+            bri.invert_block(M, k, i, j, precision=precision, out=out, info=info, workspace=ws, reuse=reuse)
         return call, out, info
 
     # ---- headline: FP64, block (0, 0) ------------------------------------
@@ -306,6 +308,20 @@ def main() -> int:
             entry = {"block": [i, j], "precision": prec, "ms_per_step": vms,
                      "tflops": flops / (vms * 1e-3) / 1e12, "speed_vs_f64": f64_ms / vms,
                      "refine_sweeps": sweeps, "last_rel_correction": last, "info": int(inf2.item())}
+            if not args.no_cpu_baseline:
+                entry["rel_error"] = rel_err(o2.cpu().numpy(), refs[(i, j)])
+            variants.append(entry)
+        # the paper's suggested reuse across branches (elimination pivots kept
+        # and factored once); value still counts the paper's operations F
+        for prec in ("f64", "mixed_f16"):
+            c2, o2, inf2 = setup(M64, i, j, prec, reuse=True)
+            vms, _ = time_calls(c2, max(1, args.steps // 3), 1, torch)
+            entry = {"block": [i, j], "precision": prec, "reuse_pivots": True, "ms_per_step": vms,
+                     "paper_equivalent_tflops": flops / (vms * 1e-3) / 1e12, "speed_vs_f64": f64_ms / vms,
+                     "executed_flops": bri.plan_describe(n, k, i, j, prec, reuse=True)["executed_flops"],
+                     "info": int(inf2.item())}
+            if prec.startswith("mixed"):
+                entry["refine_sweeps"] = bri.refine_last()[0]
             if not args.no_cpu_baseline:
                 entry["rel_error"] = rel_err(o2.cpu().numpy(), refs[(i, j)])
             variants.append(entry)

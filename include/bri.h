@@ -80,6 +80,11 @@ typedef struct {
   int precision;           /* a bri_precision value                                   */
   int concurrency;         /* W: Schur operations evaluated side by side; <= 0: auto  */
   int pivoting;            /* a bri_pivoting value                                    */
+  int reuse;               /* 0: recompute every Schur complement (the paper's
+                              procedure); 1: keep the k - 1 factored elimination
+                              pivots and reuse them (the paper's suggested reuse
+                              across branches: 3 children per Schur node instead of
+                              4, k - 1 more b x b blocks of workspace)            */
   int refine_max_iters;    /* mixed paths: refinement sweeps (0 = none)               */
   double refine_tol;       /* mixed paths: stop when the correction dX_t, or from the
                               second sweep the bound rho/(1-rho) ||dX_t||_F with
@@ -90,9 +95,9 @@ typedef struct {
   hipStream_t stream;      /* stream the work is enqueued on (NULL = default stream)  */
 } bri_opts;
 
-/* Fills *o with defaults: BRI_F64, automatic concurrency, tile pivoting,
- * 10 refinement sweeps, tolerance 1e-12, no workspace, no d_info, default
- * stream. */
+/* Fills *o with defaults: BRI_F64, automatic concurrency, tile pivoting, no
+ * reuse, 10 refinement sweeps, tolerance 1e-12, no workspace, no d_info,
+ * default stream. */
 void bri_default_opts(bri_opts* o);
 
 /* Bytes of device workspace invert_block() needs for (n, k, i, j) with the

@@ -35,6 +35,7 @@ class BriOpts(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("concurrency", ctypes.c_int),
         ("pivoting", ctypes.c_int),
+        ("reuse", ctypes.c_int),
         ("refine_max_iters", ctypes.c_int),
         ("refine_tol", ctypes.c_double),
         ("workspace", ctypes.c_void_p),
@@ -139,7 +140,7 @@ def _check(status: int) -> None:
 
 
 def make_opts(precision: str = "f64", concurrency: int = 0, refine_max_iters: int = 10,
-              refine_tol: float = 1e-12, pivoting: str = "tile") -> BriOpts:
+              refine_tol: float = 1e-12, pivoting: str = "tile", reuse: bool = False) -> BriOpts:
     o = BriOpts()
     lib().bri_default_opts(ctypes.byref(o))
     if precision not in PRECISIONS:
@@ -149,6 +150,7 @@ def make_opts(precision: str = "f64", concurrency: int = 0, refine_max_iters: in
     o.precision = PRECISIONS[precision]
     o.pivoting = PIVOTING[pivoting]
     o.concurrency = int(concurrency)
+    o.reuse = int(bool(reuse))
     o.refine_max_iters = int(refine_max_iters)
     o.refine_tol = float(refine_tol)
     return o
@@ -171,9 +173,10 @@ def block_size(n: int, k: int) -> int:
     return -(-n // k)
 
 
-def plan_describe(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0) -> dict:
+def plan_describe(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
+                  reuse: bool = False) -> dict:
     """Host-only structure of the plan (no GPU needed)."""
-    o = make_opts(precision, concurrency)
+    o = make_opts(precision, concurrency, reuse=reuse)
     s = BriPlanStats()
     _check(lib().bri_plan_describe(n, k, i, j, ctypes.byref(o), ctypes.byref(s)))
     return {f: getattr(s, f) for f, _ in BriPlanStats._fields_}
@@ -193,9 +196,10 @@ def _decode_steps(words: List[int]) -> List[tuple]:
     return steps
 
 
-def plan_dump(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0) -> List[tuple]:
+def plan_dump(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
+              reuse: bool = False) -> List[tuple]:
     """Host-only list of plan steps: [(kind, [items...])], item = (dst, x, y, cin, sub, node)."""
-    o = make_opts(precision, concurrency)
+    o = make_opts(precision, concurrency, reuse=reuse)
     need = lib().bri_plan_dump(n, k, i, j, ctypes.byref(o), None, 0)
     if need < 0:
         raise BriError(int(need), status_string(int(need)))
@@ -204,12 +208,12 @@ def plan_dump(n: int, k: int, i: int, j: int, precision: str = "f64", concurrenc
     return _decode_steps(list(buf))
 
 
-def refine_plan_dump(n: int, k: int, j: int, which: str, concurrency: int = 0):
+def refine_plan_dump(n: int, k: int, j: int, which: str, concurrency: int = 0, reuse: bool = False):
     """Host-only plans of the mixed-precision refinement: which = "column"
     (float block column, keeps its pivots), "solve" (correction solve with the
     right-hand side as operand kind 5) or "kept" (pivot slot per position)."""
     w = {"column": 0, "solve": 1, "kept": 2}[which]
-    o = make_opts("mixed_f32", concurrency)
+    o = make_opts("mixed_f32", concurrency, reuse=reuse)
     need = lib().bri_refine_plan_dump(n, k, j, w, ctypes.byref(o), None, 0)
     if need < 0:
         raise BriError(int(need), status_string(int(need)))
@@ -218,15 +222,16 @@ def refine_plan_dump(n: int, k: int, j: int, which: str, concurrency: int = 0):
     return list(buf)[:need] if which == "kept" else _decode_steps(list(buf)[:need])
 
 
-def workspace_size(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0) -> int:
-    o = make_opts(precision, concurrency)
+def workspace_size(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
+                   reuse: bool = False) -> int:
+    o = make_opts(precision, concurrency, reuse=reuse)
     return int(lib().bri_workspace_size(n, k, i, j, ctypes.byref(o)))
 
 
 def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
                  out: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
                  workspace: Optional[torch.Tensor] = None, refine_max_iters: int = 10,
-                 refine_tol: float = 1e-12, pivoting: str = "tile") -> torch.Tensor:
+                 refine_tol: float = 1e-12, pivoting: str = "tile", reuse: bool = False) -> torch.Tensor:
     """Block N_ij (b x b, b = ceil(n/k)) of M^{-1} (of Gamma^{-1} when k does not divide n).
 
     ``info`` (optional int32 GPU tensor of one element) receives the device
@@ -238,7 +243,7 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
     if M.shape[1] != n:
         raise ValueError("M must be square")
     b = block_size(n, k)
-    o = make_opts(precision, concurrency, refine_max_iters, refine_tol, pivoting)
+    o = make_opts(precision, concurrency, refine_max_iters, refine_tol, pivoting, reuse)
     need = lib().bri_workspace_size(n, k, i, j, ctypes.byref(o))
     if need == 0:
         # Invalid arguments: let the library name the offending one (it
@@ -305,7 +310,7 @@ def invert_block_backward(M: torch.Tensor, k: int, i: int, j: int, G: torch.Tens
 
 def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Sequence[int],
                          jjs: Sequence[int], precision: str = "f64", concurrency: int = 0,
-                         info: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
+                         info: Optional[torch.Tensor] = None, reuse: bool = False) -> List[torch.Tensor]:
     """One block per problem; all problems share one workspace and one call."""
     count = len(Ms)
     dtype = _DTYPE_OF[precision]
@@ -322,7 +327,7 @@ def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Seq
     ldo = (ctypes.c_int64 * count)(*[o_.stride(0) for o_ in outs])
     mp = (ctypes.c_void_p * count)(*[m.data_ptr() for m in Ms])
     op = (ctypes.c_void_p * count)(*[o_.data_ptr() for o_ in outs])
-    o = make_opts(precision, concurrency)
+    o = make_opts(precision, concurrency, reuse=reuse)
     need = lib().bri_batched_workspace_size(count, n, kk, ii, jj, ctypes.byref(o))
     if need == 0 and count > 0:
         raise BriError(BRI_ERR_UNSUPPORTED, "invalid arguments")

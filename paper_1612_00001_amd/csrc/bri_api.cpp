@@ -90,6 +90,7 @@ struct CachedPlan {
 };
 
 typedef std::tuple<int, int64_t, int, int, int, int, int, int> PlanKey;  // kind,n,k,i,j,width,elem,transpose
+// kind: 0 block plan, 1 block column plan, 2 block plan with kept pivots
 
 std::mutex g_cache_mu;
 std::map<PlanKey, std::shared_ptr<CachedPlan>>& cache() {
@@ -131,7 +132,9 @@ std::shared_ptr<CachedPlan> get_plan(int kind, int64_t n, int k, int i, int j, i
   auto itp = c.find(key);
   if (itp != c.end()) return itp->second;
   auto cp = std::make_shared<CachedPlan>();
-  cp->plan = kind == 0 ? make_block_plan(n, k, i, j, width) : make_column_plan(n, k, j, width);
+  cp->plan = kind == 0   ? make_block_plan(n, k, i, j, width)
+             : kind == 2 ? make_block_plan_reuse(n, k, i, j, width)
+                         : make_column_plan(n, k, j, width);
   cp->plan.transpose = transpose;
   cp->layout = make_layout(cp->plan, elem);
   if (c.size() > 64) c.clear();
@@ -652,14 +655,15 @@ struct BatchPlan {
   size_t info_off = 0, desc_off = 0, total = 0;
 };
 
-BatchPlan make_batch_plan(int count, const int64_t* n, const int* k, const int* i, const int* j, int elem) {
+BatchPlan make_batch_plan(int count, const int64_t* n, const int* k, const int* i, const int* j, int elem,
+                          int reuse) {
   BatchPlan bp;
   bp.plans.resize(count);
   bp.region.resize(count);
   std::vector<const Plan*> pl(count);
   size_t off = 0;
   for (int t = 0; t < count; ++t) {
-    bp.plans[t] = get_plan(0, n[t], k[t], i[t], j[t], merged_width(k[t]), elem, 0);
+    bp.plans[t] = get_plan(reuse ? 2 : 0, n[t], k[t], i[t], j[t], merged_width(k[t]), elem, 0);
     pl[t] = &bp.plans[t]->plan;
     bp.region[t] = off;
     off += align_up(bp.plans[t]->layout.desc_off);  // slots, permutations, tile scratch, status
@@ -726,21 +730,22 @@ bool batch_mergeable(const bri_opts* o) {
 struct RefineCache {
   std::shared_ptr<CachedPlan> col, sol;
   std::vector<int> kept;
+  bool column_gives_x0 = true;
 };
 
-typedef std::tuple<int64_t, int, int, int> RefineKey;  // n, k, j, width
+typedef std::tuple<int64_t, int, int, int, int> RefineKey;  // n, k, j, width, reuse
 
 // Outcome of the calling thread's last mixed-precision call.
 thread_local int t_last_sweeps = 0;
 thread_local double t_last_update = 0.0;
 
-std::shared_ptr<RefineCache> get_refine(int64_t n, int k, int j, int width) {
+std::shared_ptr<RefineCache> get_refine(int64_t n, int k, int j, int width, int reuse) {
   static std::map<RefineKey, std::shared_ptr<RefineCache>> c;
-  RefineKey key(n, k, j, width);
+  RefineKey key(n, k, j, width, reuse);
   std::lock_guard<std::mutex> g(g_cache_mu);
   auto itp = c.find(key);
   if (itp != c.end()) return itp->second;
-  RefinePlans rp = make_refine_plans(n, k, j, width);
+  RefinePlans rp = make_refine_plans(n, k, j, width, reuse != 0);
   auto rc = std::make_shared<RefineCache>();
   rc->col = std::make_shared<CachedPlan>();
   rc->sol = std::make_shared<CachedPlan>();
@@ -749,6 +754,7 @@ std::shared_ptr<RefineCache> get_refine(int64_t n, int k, int j, int width) {
   rc->col->layout = make_layout(rc->col->plan, 4);
   rc->sol->layout = make_layout(rc->sol->plan, 4);
   rc->kept = rp.kept;
+  rc->column_gives_x0 = rp.column_gives_x0;
   if (c.size() > 1024) c.clear();
   c[key] = rc;
   return rc;
@@ -803,7 +809,7 @@ MixedBatch make_mixed_batch(int count, const int64_t* n, const int* k, const int
   size_t off = 0;
   for (int t = 0; t < count; ++t) {
     const int w = merged_width_rule ? merged_width(k[t]) : resolve_width(n[t], k[t], o);
-    mb.rc[t] = get_refine(n[t], k[t], j[t], w);
+    mb.rc[t] = get_refine(n[t], k[t], j[t], w, o->reuse);
     mb.reg[t] = mixed_region(n[t], k[t], *mb.rc[t]);
     mb.region[t] = off;
     off += mb.reg[t].total;
@@ -964,6 +970,12 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
   if (launch_gamma_f32(d_items, count, max_kk, st) != hipSuccess) return BRI_ERR_HIP;
   int rcode = run_merged<float>(ecol, o->pivoting, lp_of(o->precision), st);
   if (rcode != BRI_OK) return rcode;
+  if (!mb.rc[0]->column_gives_x0) {
+    // Pivots only (reuse): X0 = (sigma Gamma)^{-1} E_j by the solve plan.
+    if (launch_set_ej(d_items, count, max_kb_b, st) != hipSuccess) return BRI_ERR_HIP;
+    rcode = run_merged<float>(esol, o->pivoting, lp_of(o->precision), st);
+    if (rcode != BRI_OK) return rcode;
+  }
   if (launch_refine_update(d_items, count, max_kb_b, 1, st) != hipSuccess) return BRI_ERR_HIP;
 
   // Sweeps: R = E_j - Gamma X (FP64), D = (sigma Gamma)^{-1} (s R) by the float
@@ -1125,7 +1137,7 @@ size_t bri_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
   }
   if (!plain_precision(o->precision)) return 0;
   try {
-    auto cp = get_plan(0, n, k, i, j, w, elem_size(o->precision), 0);
+    auto cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, w, elem_size(o->precision), 0);
     return cp->layout.total;
   } catch (const std::exception&) {
     return 0;
@@ -1138,7 +1150,7 @@ int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_pla
   const int rc = check_block_args(n, n, k, i, j, (n + k - 1) / k);
   if (rc) return rc;
   const int w = resolve_width(n, k, o);
-  auto cp = get_plan(0, n, k, i, j, w, elem_size(o->precision), 0);
+  auto cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, w, elem_size(o->precision), 0);
   const Plan& p = cp->plan;
   s->schur_ops = p.schur_ops;
   s->final_inversions = p.final_inversions;
@@ -1190,7 +1202,7 @@ int64_t bri_plan_dump(int64_t n, int k, int i, int j, const bri_opts* o, int64_t
   const int rc = check_block_args(n, n, k, i, j, (n + k - 1) / k);
   if (rc) return rc;
   const int w = resolve_width(n, k, o);
-  auto cp = get_plan(0, n, k, i, j, w, elem_size(o->precision), 0);
+  auto cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, w, elem_size(o->precision), 0);
   return dump_steps(cp->plan, words, cap);
 }
 
@@ -1200,7 +1212,7 @@ int64_t bri_refine_plan_dump(int64_t n, int k, int j, int which, const bri_opts*
   if (rc) return rc == -6 ? -3 : rc;
   if (which < 0 || which > 2) return -4;
   const int w = resolve_width(n, k, o);
-  auto r = get_refine(n, k, j, w);
+  auto r = get_refine(n, k, j, w, o->reuse);
   if (which == 2) {
     for (int t = 0; t < k; ++t)
       if (words && t < cap) words[t] = r->kept[t];
@@ -1222,7 +1234,7 @@ int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, voi
   const int w = resolve_width(n, k, o);
   std::shared_ptr<CachedPlan> cp;
   try {
-    cp = get_plan(0, n, k, i, j, w, elem, 0);
+    cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, w, elem, 0);
   } catch (const std::exception&) {
     return BRI_ERR_UNSUPPORTED;
   }
@@ -1301,7 +1313,7 @@ size_t bri_batched_workspace_size(int count, const int64_t* n, const int* k, con
   if (batch_mergeable(o)) {
     try {
       return mixed_precision(o->precision) ? make_mixed_batch(count, n, k, j, o, true).total
-                                           : make_batch_plan(count, n, k, i, j, elem_size(o->precision)).total;
+                                           : make_batch_plan(count, n, k, i, j, elem_size(o->precision), o->reuse).total;
     } catch (const std::exception&) {
       return 0;
     }
@@ -1347,7 +1359,7 @@ int invert_block_batched(int count, const void* const* M, const int64_t* n, cons
   if (batch_mergeable(o)) {
     BatchPlan bp;
     try {
-      bp = make_batch_plan(count, n, k, i, j, elem_size(o->precision));
+      bp = make_batch_plan(count, n, k, i, j, elem_size(o->precision), o->reuse);
     } catch (const std::exception&) {
       return BRI_ERR_UNSUPPORTED;
     }

@@ -177,9 +177,15 @@ Plan make_column_plan(int64_t n, int k, int j, int width);
 //           complements are recomputed, reusing the kept pivots.
 struct RefinePlans {
   Plan column, solve;
-  std::vector<int> kept;  // kept[pos]: slot of the pivot of elimination position pos
+  std::vector<int> kept;         // kept[pos]: slot of the pivot of elimination position pos
+  bool column_gives_x0 = true;   // false: the column plan only factors the pivots (reuse)
 };
-RefinePlans make_refine_plans(int64_t n, int k, int j, int width);
+RefinePlans make_refine_plans(int64_t n, int k, int j, int width, bool reuse);
+
+// The plan of invert_block with the k - 1 elimination pivots kept and reused
+// (each Schur node then has three children; the paper's suggested reuse
+// across branches).  Same result, fewer operations, k - 1 kept b x b blocks.
+Plan make_block_plan_reuse(int64_t n, int k, int i, int j, int width);
 
 // Launch/flop accounting of the kernels that realise a step.
 int64_t getrf_launches(int b);

@@ -597,6 +597,96 @@ Plan make_block_plan(int64_t n, int k, int i, int j, int width) {
 
 namespace {
 
+// Factored elimination pivots P_pos = v(order[pos], order[pos], {order[0..pos-1]})
+// for pos < npos, in increasing position: each is evaluated with the pivots
+// before it kept (three children per Schur node instead of four) and stays in
+// its slot (kept[pos]).  This is the reuse across branches the paper
+// suggests as future work (Section "Conclusion").
+void build_pivots(Builder& B, const std::vector<int>& order, int npos, std::vector<int>& kept) {
+  kept.clear();
+  for (int pos = 0; pos < npos; ++pos) {
+    B.set_memo(kept);
+    const int sq = B.value(order[pos], order[pos], pos);
+    B.factor_only({sq});
+    B.plan_.schur_ops--;  // a kept pivot's factorisation, counted with the inversions
+    B.plan_.final_inversions++;
+    kept.push_back(sq);
+  }
+  B.set_memo(kept);
+}
+
+}  // namespace
+
+Plan make_block_plan_reuse(int64_t n, int k, int i, int j, int width) {
+  if (k < 2 || n < k || i < 0 || i >= k || j < 0 || j >= k) throw std::invalid_argument("bad target");
+  if (k == 2) return make_block_plan(n, k, i, j, width);  // nothing to reuse
+  Plan plan;
+  plan.n = n;
+  plan.k = k;
+  plan.i = i;
+  plan.j = j;
+  plan.b = static_cast<int>((n + k - 1) / k);
+  const int64_t leaves = static_cast<int64_t>(std::pow(3.0, std::max(0, k - 2)));
+  plan.width = std::max<int64_t>(1, std::min<int64_t>(width, leaves));
+  int a, c;
+  if (i == j) {
+    a = i;
+    c = (i == k - 1) ? k - 2 : k - 1;
+  } else {
+    a = j;
+    c = i;
+  }
+  std::vector<int> elim;
+  for (int t = 0; t < k; ++t)
+    if (t != a && t != c) elim.push_back(t);
+  elim.push_back(c);
+  Builder B(plan, elim, plan.width);
+  SlotPool& pool = B.pool();
+  std::vector<int> kept;
+  build_pivots(B, elim, k - 2, kept);
+  // Root frame values at depth k - 2 (every pivot below them kept), then the
+  // root pivot v(c, c) and the final 2 x 2 step as in the recomputing plan.
+  const std::vector<int> r4 = B.eval_children({Node{a, a, k - 2}, Node{a, c, k - 2}, Node{c, c, k - 2},
+                                               Node{c, a, k - 2}});
+  const int sz = r4[0], sc_ = r4[1], sp = r4[2], sx = r4[3];
+  B.factor_and_solve({sp}, {Opnd::slot(sx)}, {Opnd::slot(sx)}, true);
+  pool.release(sp);
+  {
+    Step& g = B.step(ST_GEMM);
+    StepItem gi;
+    gi.dst = Opnd::slot(sz);
+    gi.x = Opnd::slot(sc_);
+    gi.y = Opnd::slot(sx);
+    gi.cin = Opnd::slot(sz);
+    g.items.push_back(gi);
+  }
+  pool.release(sc_);
+  if (i == j) {
+    B.final_inverse(sz, Opnd::outp(), true);
+  } else {
+    int sn = pool.alloc();
+    B.final_inverse(sz, Opnd::slot(sn), true);
+    Step& g = B.step(ST_GEMM_NEG);
+    StepItem gi;
+    gi.dst = Opnd::outp();
+    gi.x = Opnd::slot(sx);
+    gi.y = Opnd::slot(sn);
+    g.items.push_back(gi);
+    pool.release(sn);
+  }
+  pool.release(sx);
+  pool.release(sz);
+  for (int kp : kept) pool.release(kp);
+  plan.nslots = pool.peak;
+  const double b3 = cube(plan.b);
+  const double T = static_cast<double>((static_cast<int64_t>(std::pow(4.0, k - 1)) - 1) / 3);
+  plan.algorithmic_flops = T * (14.0 / 3.0) * b3 + 2.0 * b3 + (i != j ? 2.0 * b3 : 0.0);
+  account(plan);
+  return plan;
+}
+
+namespace {
+
 // Elimination order of the block column plans: every index but j ascending,
 // j last (x_j is the first unknown of the back substitution).
 std::vector<int> column_order(int k, int j) {
@@ -689,13 +779,23 @@ Plan make_column_plan(int64_t n, int k, int j, int width) {
   return plan;
 }
 
-RefinePlans make_refine_plans(int64_t n, int k, int j, int width) {
+RefinePlans make_refine_plans(int64_t n, int k, int j, int width, bool reuse) {
   RefinePlans rp;
   init_column_plan(rp.column, n, k, j, width);
   init_column_plan(rp.solve, n, k, j, width);
   std::vector<int> order = column_order(k, j);
   Builder B(rp.column, order, rp.column.width);
-  build_column(B, order, j, &rp.kept);
+  if (reuse) {
+    // Only the pivots: every position's pivot with the earlier ones kept;
+    // the block column itself then comes from the solve plan with R = E_j.
+    std::vector<int> full(order);
+    full.push_back(j);
+    build_pivots(B, full, k, rp.kept);
+    rp.column_gives_x0 = false;
+  } else {
+    build_column(B, order, j, &rp.kept);
+    rp.column_gives_x0 = true;
+  }
   // The solve plan starts from the column plan's pool: the kept pivots stay
   // allocated, everything else is free again.
   Builder S(rp.solve, order, rp.solve.width);

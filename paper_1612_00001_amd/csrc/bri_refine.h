@@ -35,6 +35,8 @@ hipError_t launch_resid_fix(const RefItem* items, int count, int64_t max_elems, 
 hipError_t launch_rhs_scale(const RefItem* items, int count, int64_t max_elems, hipStream_t st);
 // X (+)= (sigma / s) D and the squared norms of the update and of X.
 hipError_t launch_refine_update(const RefItem* items, int count, int64_t max_elems, int first, hipStream_t st);
+// R32 = E_j.
+hipError_t launch_set_ej(const RefItem* items, int count, int64_t max_elems, hipStream_t st);
 // Clears scal[from, to) of every item.
 hipError_t launch_scal_clear(const RefItem* items, int count, int from, int to, hipStream_t st);
 // *info = -1 where *info == 0 (refinement did not converge).

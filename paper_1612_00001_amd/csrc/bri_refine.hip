@@ -115,6 +115,16 @@ __global__ __launch_bounds__(256) void k_refine_update(const RefItem* items, int
   }
 }
 
+// R32 = E_j (the unit block column j of Gamma's order).
+__global__ __launch_bounds__(256) void k_set_ej(const RefItem* items) {
+  const RefItem it = items[blockIdx.y];
+  const int64_t jb = static_cast<int64_t>(it.j) * it.b;
+  for (int64_t e = first_elem(); e < it.kb * it.b; e += elem_stride()) {
+    const int64_t r = e / it.b, c = e - r * it.b;
+    it.R32[e] = (r == jb + c) ? 1.0f : 0.0f;
+  }
+}
+
 __global__ void k_scal_clear(const RefItem* items, int from, int to) {
   const int e = from + static_cast<int>(threadIdx.x);
   if (e < to) items[blockIdx.y].scal[e] = 0.0;
@@ -164,6 +174,12 @@ hipError_t launch_rhs_scale(const RefItem* items, int count, int64_t max_elems, 
 hipError_t launch_refine_update(const RefItem* items, int count, int64_t max_elems, int first, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_refine_update, grid_for(max_elems, count), dim3(256), 0, st, items, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_ej(const RefItem* items, int count, int64_t max_elems, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_ej, grid_for(max_elems, count), dim3(256), 0, st, items);
   return hipGetLastError();
 }
 

@@ -144,3 +144,15 @@ def test_mixed_f32_batched_512_problems_merged():
         worst = max(worst, rel(o.cpu().numpy(), want))
     print(f"  worst rel err {worst:.2e}, sweeps {bri.refine_last()[0]}", flush=True)
     assert worst < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["mixed_f32", "mixed_f16"])
+def test_mixed_with_reused_pivots(precision):
+    n, k = 300, 5
+    m = workloads.haar_spd(n, 12, 0.0, 2.0).m
+    for (i, j) in [(0, 0), (3, 2)]:
+        info = torch.zeros(1, dtype=torch.int32, device=DEV)
+        got = bri.invert_block(gpu(m), k, i, j, precision=precision, info=info, reuse=True)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        assert rel(got.cpu().numpy(), oracle.invert_block(m, k, i, j)) < 1e-10

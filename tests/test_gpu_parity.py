@@ -261,3 +261,20 @@ def test_backward_fp32_n8192_k4_against_dense_inverse():
     err = float(torch.linalg.norm(g.double() - want) / torch.linalg.norm(want))
     print(f"  rel err {err:.2e}", flush=True)
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("n,k", [(130, 4), (300, 5), (64, 8), (257, 2)])
+def test_reuse_of_pivots_matches_oracle(n, k):
+    m = workloads.gaussian_dd(n, 50 + n)
+    for (i, j) in [(0, 0), (k - 1, 1)]:
+        info = torch.zeros(1, dtype=torch.int32, device=DEV)
+        got = bri.invert_block(gpu(m), k, i, j, info=info, reuse=True)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        assert rel(got.cpu().numpy(), oracle.invert_block(m, k, i, j)) < 1e-12
+
+
+def test_reuse_config_n4096_k4_fp64():
+    m = workloads.workload_matrix("spd_n4096_k4")
+    got = bri.invert_block(gpu(m), 4, 0, 0, reuse=True).cpu().numpy()
+    assert rel(got, oracle.invert_block(m, 4, 0, 0)) < 1e-12

@@ -282,3 +282,59 @@ def test_no_kernel_spills_to_scratch():
             if int(kv["scratch"]) > 0:
                 spills.append(name)
     assert not spills, spills
+
+
+# ---------------------------------------------------------------------------
+# Reuse of the elimination pivots (kept, factored once)
+# ---------------------------------------------------------------------------
+REUSE_CASES = [(16, 2, 0, 0, 1), (18, 3, 0, 0, 1), (18, 3, 2, 1, 4), (24, 4, 0, 0, 1), (24, 4, 1, 2, 4),
+               (23, 4, 3, 3, 16), (25, 5, 0, 0, 4), (26, 5, 4, 1, 16), (18, 6, 5, 2, 64), (14, 7, 3, 3, 16)]
+
+
+@pytest.mark.parametrize("n,k,i,j,W", REUSE_CASES)
+def test_reuse_plan_interpreter_reproduces_inverse_blocks(n, k, i, j, W):
+    m = workloads.gaussian_dd(n, 3000 + 7 * n + k)
+    steps = bri.plan_dump(n, k, i, j, "f64", W, reuse=True)
+    out = run_plan(m, k, steps)
+    b = -(-n // k)
+    full = np.eye(k * b)
+    full[:n, :n] = m
+    want = np.linalg.inv(full)[i * b:(i + 1) * b, j * b:(j + 1) * b]
+    assert np.abs(out[0] - want).max() < 1e-12
+
+
+def test_reuse_factorises_only_the_elimination_pivots():
+    for k in (3, 4, 5, 6, 8):
+        n = 16 * k
+        d = bri.plan_describe(n, k, 0, 0, "f64", 1, reuse=True)
+        steps = bri.plan_dump(n, k, 0, 0, "f64", 1, reuse=True)
+        getrf = sum(len(items) for kind, items in steps if kind == ST_GETRF)
+        # k - 2 kept pivots, the root pivot and the final inverse
+        assert getrf == k, (k, getrf)
+        assert d["final_inversions"] == k - 1
+        # three children per node: the four root values of depth k - 2, the
+        # kept pivots of depths 0 .. k - 3, and the root pivot's solve
+        c3 = [(3 ** t - 1) // 2 for t in range(k)]
+        assert d["schur_ops"] == 4 * c3[k - 2] + sum(c3[:k - 2]) + 1, (k, d["schur_ops"])
+        assert d["schur_ops"] <= (4 ** (k - 1) - 1) // 3
+
+
+@pytest.mark.parametrize("n,k,j,W", [(16, 2, 1, 1), (18, 3, 1, 4), (24, 4, 0, 1), (25, 5, 4, 16), (18, 6, 2, 16)])
+def test_reuse_refine_plans(n, k, j, W):
+    m = workloads.gaussian_dd(n, 4000 + 5 * n + k)
+    b = -(-n // k)
+    full = np.eye(k * b)
+    full[:n, :n] = m
+    inv = np.linalg.inv(full)
+    state = {}
+    run_plan(m, k, bri.refine_plan_dump(n, k, j, "column", W, reuse=True), state=state)
+    kept = bri.refine_plan_dump(n, k, j, "kept", W, reuse=True)
+    assert len(set(kept)) == k and all(s in state["factors"] for s in kept)
+    ej = np.zeros((k * b, b))
+    ej[j * b:(j + 1) * b] = np.eye(b)
+    solve = bri.refine_plan_dump(n, k, j, "solve", W, reuse=True)
+    x = run_plan(m, k, solve, rhs=ej, state=state)
+    assert np.abs(np.vstack([x[t] for t in range(k)]) - inv[:, j * b:(j + 1) * b]).max() < 1e-12
+    r = np.random.default_rng(n).standard_normal((k * b, b))
+    y = run_plan(m, k, solve, rhs=r, state=state)
+    assert np.abs(np.vstack([y[t] for t in range(k)]) - inv @ r).max() < 1e-10

@@ -61,7 +61,7 @@ Layout make_layout(const Plan& p, int elem) {
   L.swap_off = off;
   off += align_up(sizeof(int32_t) * kSwapWords * p.nslots);
   L.aux_off = off;
-  L.aux_bytes = align_up(static_cast<size_t>(2) * kTile * kTile * elem);
+  L.aux_bytes = align_up(static_cast<size_t>(kAuxElems) * elem);
   off += L.aux_bytes * p.nslots;
   L.info_off = off;
   off += kAlign;

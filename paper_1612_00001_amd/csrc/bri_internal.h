@@ -42,9 +42,10 @@ struct GemmItem {
 struct LuItem {
   void* a;           // dense b x b, leading dimension b
   int32_t* perm;     // b entries: row x of P A is row perm[x] of A
-  int32_t* swaps;    // per-panel list of moved rows: [count, (dest, src) ...]
+  int32_t* swaps;    // partial pivoting: per-panel list of moved rows [count, (dest, src) ...];
+                     // tile pivoting: kStepBufs tile permutations of kTile entries after word 0
   void* tmp;         // b x b scratch for the triangular inversion
-  void* aux;         // 2 kTile^2 elements: inverses of the current diagonal tile's L and U
+  void* aux;         // kAuxElems elements: inverses of the L and U factors of recent diagonal tiles
   int32_t* info;     // device status word of the problem this matrix belongs to (or null)
   int32_t node;      // Schur operation index reported through *info
   int32_t b;
@@ -53,6 +54,11 @@ struct LuItem {
 // Tile of the tile-local pivoting LU: the pivot search of column c runs over
 // the rows of the kTile x kTile diagonal tile that holds c.
 constexpr int kTile = 32;
+// The tile-step launch of tile s reads the factors of tiles s - 1 and s while
+// it factors tile s + 1, so the tile inverses and permutations rotate through
+// three buffers.
+constexpr int kStepBufs = 3;
+constexpr int kAuxElems = kStepBufs * 2 * kTile * kTile;
 
 struct LoadItem {
   DView src;
@@ -102,6 +108,7 @@ inline bool gemm_item_is_fast(const GemmItem& g) {
 }
 
 constexpr int kSwapWords = 1 + 2 * 2 * 64;  // count + up to 128 (dest, src) pairs
+static_assert(1 + kStepBufs * kTile <= kSwapWords, "tile permutations exceed the swap words");
 constexpr int kTrtriTile = 32;                // diagonal tile of the triangular inversion
 
 // Width of the LU panel held in registers for a panel of h rows (512 threads

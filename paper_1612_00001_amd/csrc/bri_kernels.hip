@@ -192,6 +192,10 @@ template <typename T>
 __device__ __forceinline__ T gload(const T* p) {
   return *(const __attribute__((address_space(1))) T*)(p);
 }
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)(p) = v;
+}
 
 template <typename T, int R, int C, int NT>
 struct TileOp {
@@ -272,9 +276,6 @@ struct TileOp {
 // own kernel instance so that profiles separate the Schur products from the
 // LU and triangular-inversion updates.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void tile_lu_wave(const LuItem& it, int t0, int wprev);
-
 template <typename T, int MODE, bool GEN, int BM, int BN, int BK, int WM, int WN>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch L) {
   constexpr int NWN = BN / WN;
@@ -285,15 +286,6 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
   constexpr int AE = OpA::E, BE = OpB::E;
   static_assert(AE * NT == BM * BK && BE * NT == BK * BN, "tile/thread mismatch");
   constexpr bool USE_PERM = (MODE == GEMM_EXPLICIT) && !GEN;
-
-  if constexpr (MODE == GEMM_LU_TRAILING) {
-    // Look-ahead (L.npairs != 0): the last workgroup of every matrix updates
-    // and factors the next diagonal tile while the others update the rest.
-    if (L.npairs && blockIdx.x == gridDim.x - 1) {
-      if (threadIdx.x < 64) tile_lu_wave<T>(static_cast<const LuItem*>(L.items)[blockIdx.y], L.j + L.w, L.w);
-      return;
-    }
-  }
 
   GemmItem it;
   if (!gemm_item<T, MODE>(L, blockIdx.y + (GEN ? L.j : 0), it)) return;
@@ -402,9 +394,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
       for (int v = 0; v < 4; ++v) {
         const int r = m0 + wm * WM + i * 16 + MF<T>::row(lane, v);
         const int c = n0 + wn * WN + j * 16 + (lane & 15);
-        // look-ahead: the next diagonal tile belongs to the factorising workgroup
-        const bool skip = MODE == GEMM_LU_TRAILING && L.npairs && r < kTile && c < kTile;
-        if (r < it.M && c < it.N && !skip) {
+        if (r < it.M && c < it.N) {
           T val = alpha * acc[i][j][v];
           // The fast instance only receives plain Cin / Sub (gemm_item_is_fast).
           if (it.has_cin)
@@ -934,8 +924,12 @@ __device__ __forceinline__ uint32_t pivot_key(float y, bool cand, int r) {
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ uint32_t dpp_umax(uint32_t k) {
-  const uint32_t o = static_cast<uint32_t>(
-      __builtin_amdgcn_update_dpp(static_cast<int>(k), static_cast<int>(k), CTRL, ROW_MASK, 0xf, false));
+  // Every source lane is valid for the full-mask patterns, so the plain DPP
+  // move (undefined old value) is used there and can fold into the maximum.
+  const uint32_t o = ROW_MASK == 0xf
+                         ? static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(k), CTRL, 0xf, 0xf, false))
+                         : static_cast<uint32_t>(__builtin_amdgcn_update_dpp(static_cast<int>(k), static_cast<int>(k),
+                                                                             CTRL, ROW_MASK, 0xf, false));
   return o > k ? o : k;
 }
 // Row of the largest key among the 32 lanes of half h (a wave-uniform value).
@@ -949,45 +943,43 @@ __device__ __forceinline__ int half_argmax(uint32_t k, int h) {
   return 31 - (top & 31);
 }
 
-// One wavefront (threads 0..63 of its workgroup; the function synchronises
-// only within the wavefront).  With wprev > 0 the tile first receives the
-// rank-wprev update of the previous panel, A_tt -= L(t, prev) U(prev, t)
-// (the look-ahead form used inside the trailing-update launch).
+// Buffers of tile s of the tile-pivoting LU: inverses of its L and U
+// factors (kTile x kTile each, row-major, L^{-1} first) and its permutation
+// (position q of the factored tile holds original tile row perm[q]).
 template <typename T>
-__device__ __forceinline__ void tile_lu_wave(const LuItem& it, int t0, int wprev) {
-  constexpr int LD = kTile + 2;
+__device__ __forceinline__ T* step_inv(const LuItem& it, int s) {
+  return static_cast<T*>(it.aux) + static_cast<int64_t>(s % kStepBufs) * 2 * kTile * kTile;
+}
+__device__ __forceinline__ int32_t* step_perm(const LuItem& it, int s) { return it.swaps + 1 + (s % kStepBufs) * kTile; }
+
+// LDS of one tile factorisation: four kTile x (kTile + 2) arrays and kTile
+// reciprocals.
+constexpr int kLuLd = kTile + 2;
+constexpr int kLuLdsElems = 4 * kTile * kLuLd + kTile;
+
+// One wavefront (threads 0..63 of its workgroup; the function synchronises
+// only within the wavefront) factors diagonal tile t0 / kTile.  The tile is
+// read from the matrix, or from LDS (sT, leading dimension ldt) when the
+// caller has just formed it there; lds is kLuLdsElems elements of scratch.
+template <typename T>
+__device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T* sT, int ldt, T* lds) {
+  constexpr int LD = kLuLd;
+  const LuItem it = item;  // every field read up front, ahead of the stores
   if (t0 >= it.b) return;  // a smaller matrix of a merged batch
   T* A = static_cast<T*>(it.a);
-  const int b = it.b, ts = min(kTile, b - t0);
-  const int l = threadIdx.x, r = l & 31, half = l >> 5;
-  __shared__ __attribute__((aligned(16))) T sR[kTile][LD];   // current rows, by original tile row (2 spare columns)
-  __shared__ __attribute__((aligned(16))) T sL[kTile][LD];   // multipliers: sL[r][C]
-  __shared__ __attribute__((aligned(16))) T sF[kTile][LD];   // factored tile in pivot order
-  __shared__ __attribute__((aligned(16))) T sFT[kTile][LD];  // its transpose
-  __shared__ T sD[kTile];                                    // reciprocals of U's diagonal
+  const int b = it.b, ts = min(kTile, b - t0), s = t0 / kTile;
+  const int l = threadIdx.x & 63, r = l & 31, half = l >> 5;
+  T (*sR)[LD] = reinterpret_cast<T (*)[LD]>(lds);                       // current rows, by original tile row
+  T (*sL)[LD] = reinterpret_cast<T (*)[LD]>(lds + kTile * LD);          // multipliers: sL[r][C]
+  T (*sF)[LD] = reinterpret_cast<T (*)[LD]>(lds + 2 * kTile * LD);      // factored tile in pivot order
+  T (*sFT)[LD] = reinterpret_cast<T (*)[LD]>(lds + 3 * kTile * LD);     // its transpose
+  T* sD = lds + 4 * kTile * LD;                                         // reciprocals of U's diagonal
   T a[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int c = 16 * half + t;
-    a[t] = (r < ts && c < ts) ? A[static_cast<int64_t>(t0 + r) * b + t0 + c] : (r == c ? T(1) : T(0));
-  }
-  if (wprev > 0) {
-    // Previous panel's multipliers (rows of this tile) and U rows (columns of
-    // this tile), staged in LDS; the update runs in ascending q.
-    const int p0 = t0 - wprev;
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int q = 16 * half + t;
-      sL[r][q] = (r < ts && q < wprev) ? A[static_cast<int64_t>(t0 + r) * b + p0 + q] : T(0);
-      sF[r][q] = (r < wprev && q < ts) ? A[static_cast<int64_t>(p0 + r) * b + t0 + q] : T(0);
-    }
-    wave_lds_order();
-    for (int q = 0; q < wprev; ++q) {
-      const T lq = sL[r][q];
-#pragma unroll
-      for (int t = 0; t < 16; ++t) a[t] = fma(-lq, sF[q][16 * half + t], a[t]);
-    }
-    wave_lds_order();
+    a[t] = (r < ts && c < ts) ? (sT ? sT[r * ldt + c] : gload(A + static_cast<int64_t>(t0 + r) * b + t0 + c))
+                              : (r == c ? T(1) : T(0));
   }
   bool done = false;
   int pos = r;  // position of this row in the factored tile (rows >= ts keep theirs)
@@ -1003,31 +995,41 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& it, int t0, int wprev
   // published in LDS after the previous step, column C + 2 is prepared the
   // same way, and the multipliers go to sL (so the row update needs no
   // column mask: columns left of C of unchosen rows are dead).  All those
-  // LDS accesses are off the critical path.
+  // LDS accesses are off the critical path.  The pivot search of column
+  // C + 1 ranks the rows by |piv yc - xc u1| = |piv| |yn| (the same order as
+  // |yn|), so it does not wait for the reciprocal of the pivot.
   T xc = sR[r][0], yc = sR[r][1];
   int p = half_argmax(pivot_key(xc, half == 0 && r < ts, r), 0);
   bool bad = false;
   for (int C = 0; C < ts; ++C) {
+    // Reads of the pivot row first: their latency overlaps the search.
     const int c2 = min(C + 2, kTile + 1);
     const T y2 = sR[r][c2], u2 = sR[p][c2];
+    T prow[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) prow[t] = sR[p][16 * half + t];
     const T piv = read_lane(xc, p);
     const T u1 = read_lane(yc, p);
-    bad = bad || !(piv != T(0) && isfinite(piv));
-    const T rinv = piv != T(0) ? tile_rcp(piv) : T(0);
     const bool act = !done && r < ts && r != p;
-    const T lm = act ? xc * rinv : T(0);
-    sL[r][C] = lm;  // every lane (both halves store the same value); read only for rows chosen later
     if (r == p) {
       done = true;
       pos = C;
     }
-    const T yn = fma(-lm, u1, yc);  // column C + 1 after this step
     // Pivot of column C + 1 (computed unconditionally so the step is one
-    // basic block; unused after the last column).
-    const int pn = half_argmax(pivot_key(yn, half == 0 && !done && r < ts, r), 0);
+    // basic block; unused after the last column), then the multiplier and
+    // columns C + 1 and C + 2 of every row; the scheduling barriers keep
+    // this chain ahead of the bulk row update.
+    const T ys = fma(piv, yc, -(xc * u1));
+    const int pn = half_argmax(pivot_key(ys, half == 0 && !done && r < ts, r), 0);
+    bad = bad || !(piv != T(0) && isfinite(piv));
+    const T rinv = piv != T(0) ? tile_rcp(piv) : T(0);
+    const T lm = act ? xc * rinv : T(0);
+    const T yn = fma(-lm, u1, yc);  // column C + 1 after this step
     const T z = fma(-lm, u2, y2);   // column C + 2 after this step
+    __builtin_amdgcn_sched_barrier(0);
+    sL[r][C] = lm;  // every lane (both halves store the same value); read only for rows chosen later
 #pragma unroll
-    for (int t = 0; t < 16; ++t) a[t] = fma(-lm, sR[p][16 * half + t], a[t]);  // same operations as yn and z
+    for (int t = 0; t < 16; ++t) a[t] = fma(-lm, prow[t], a[t]);  // same operations as yn and z
     wave_lds_order();
 #pragma unroll
     for (int t = 0; t < 16; ++t) sR[r][16 * half + t] = a[t];
@@ -1035,26 +1037,40 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& it, int t0, int wprev
     xc = yn;
     yc = z;
     p = pn;
+    __builtin_amdgcn_sched_barrier(0);
   }
   if (bad && l == 0 && it.info) atomicCAS(it.info, 0, it.node + 1);
   wave_lds_order();
   // Factored row in pivot order: multipliers left of its pivot column, U
   // from there on (rows past the tile edge are identity rows).
+  T fv[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) fv[t] = sL[r][16 * half + t];  // read in full, used left of pos
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int c = 16 * half + t;
-    const T v = (r < ts && c < pos) ? sL[r][c] : a[t];
-    sF[pos][c] = v;
-    sFT[c][pos] = v;
-    if (r < ts && c < ts) A[static_cast<int64_t>(t0 + pos) * b + t0 + c] = v;
+    fv[t] = (r < ts && c < pos) ? fv[t] : a[t];
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int c = 16 * half + t;
+    sF[pos][c] = fv[t];
+    sFT[c][pos] = fv[t];
+  }
+  if (r < ts) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int c = 16 * half + t;
+      if (c < ts) gstore(A + static_cast<int64_t>(t0 + pos) * b + t0 + c, fv[t]);
+    }
   }
   // Row movement of the tile: position pos holds original tile row r.  Rows
   // never leave their band, so the band's permutation entries are t0 + r.
-  wave_lds_order();
   if (half == 0 && r < ts) {
-    it.swaps[1 + pos] = r;
-    it.perm[t0 + pos] = t0 + r;
+    gstore(step_perm(it, s) + pos, r);
+    gstore(it.perm + t0 + pos, t0 + r);
   }
+  wave_lds_order();
   if (l < kTile) sD[l] = T(1) / sF[l][l];
   wave_lds_order();
   // Inverses of the tile's triangular factors by forward substitution in
@@ -1062,112 +1078,359 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& it, int t0, int wprev
   //   lanes 0..31 : column r of L^{-1}        (L unit lower: L[i][q] = sFT[q][i]);
   //   lanes 32..63: column r of (U^T)^{-1} = row r of U^{-1}
   //                 ((U^T)[i][q] = U[q][i] = sF[q][i], diagonal 1 / sD).
+  // Row q + 1 of the operand is read from LDS while step q computes
+  // (scheduling barriers keep every step's reads next to it).
   const T* Mq = half ? &sF[0][0] : &sFT[0][0];
   T xs[kTile];
 #pragma unroll
   for (int q = 0; q < kTile; ++q) xs[q] = (q == r) ? T(1) : T(0);
+  T mrow[2][kTile];
+  T dq[2];
+#pragma unroll
+  for (int i = 1; i < kTile; ++i) mrow[0][i] = Mq[i];
+  dq[0] = sD[0];
 #pragma unroll
   for (int q = 0; q < kTile; ++q) {
-    const T xq = half ? xs[q] * sD[q] : xs[q];
+    const int cur = q & 1, nxt = cur ^ 1;
+    if (q + 1 < kTile) {
+#pragma unroll
+      for (int i = q + 2; i < kTile; ++i) mrow[nxt][i] = Mq[(q + 1) * LD + i];
+      dq[nxt] = sD[q + 1];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const T xq = half ? xs[q] * dq[cur] : xs[q];
     xs[q] = xq;
 #pragma unroll
-    for (int i = q + 1; i < kTile; ++i) xs[i] = fma(-Mq[q * LD + i], xq, xs[i]);
-    wave_lds_order();  // keeps each step's LDS reads next to their use (no hoisting, no spills)
+    for (int i = q + 1; i < kTile; ++i) xs[i] = fma(-mrow[cur][i], xq, xs[i]);
+    __builtin_amdgcn_sched_barrier(0);
   }
-  T* aux = static_cast<T*>(it.aux);
+  T* aux = step_inv<T>(it, s);
   if (half == 0) {
 #pragma unroll
-    for (int i = 0; i < kTile; ++i) aux[i * kTile + r] = xs[i];  // L^{-1}[i][r]
+    for (int i = 0; i < kTile; ++i) gstore(aux + i * kTile + r, xs[i]);  // L^{-1}[i][r]
   } else {
 #pragma unroll
-    for (int i = 0; i < kTile; ++i) aux[kTile * kTile + r * kTile + i] = xs[i];  // U^{-1}[r][i]
+    for (int i = 0; i < kTile; ++i) gstore(aux + kTile * kTile + r * kTile + i, xs[i]);  // U^{-1}[r][i]
   }
 }
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
-  tile_lu_wave<T>(items[blockIdx.x], t0, 0);
+  __shared__ __attribute__((aligned(16))) T lds[kLuLdsElems];
+  tile_lu_wave<T>(items[blockIdx.x], t0, nullptr, 0, lds);
 }
 
 // ---------------------------------------------------------------------------
-// Strip update of tile step t0 (after k_tile_lu), 256 threads per block:
-//   right blocks : rows of the tile band, 64 columns right of the tile:
-//                  U12 = L_tt^{-1} (P_tt A12);
-//   left blocks  : rows of the band, 64 columns left of the tile: P_tt A;
-//   lower blocks : 64 rows below the tile, the tile's columns:
-//                  L21 = A21 U_tt^{-1}.
+// Tile step of the tile-pivoting LU.  The launch for diagonal tile s (rows
+// and columns [t0, t0 + kTile)) runs after tile s has been factored, and its
+// workgroups share the work that needs only tiles s - 1 and s:
+//   look-ahead (first workgroup): tile s + 1 receives the update of panel s,
+//       A_tt -= (A_t,s U_s^{-1}) (L_s^{-1} P_s A_s,t), and is factored, so the
+//       next launch can start at once (the factorisation's critical path);
+//   trailing blocks: 64 x 64 blocks of the matrix right of and below tile s
+//       (tile s + 1 excepted) receive the same update; every block forms the
+//       pieces of L21 = A21 U_s^{-1} and U12 = L_s^{-1} P_s A12 it needs in
+//       LDS, since other blocks still read the unreduced strips;
+//   strip blocks: the strips of tile s - 1, which no block reads any more,
+//       are reduced in place (L21 rows with the rows of tile s's band in
+//       their new order, U12 columns);
+//   band blocks: the rows of tile s's band are permuted in the columns left
+//       of tile s - 1 (the L part; the U part is formed in pivot order).
+// All products run on MFMA from LDS operands; 256 threads per workgroup.
 // ---------------------------------------------------------------------------
+constexpr int kStepLd = kTile + 1;      // LDS leading dimension of 32-wide operands
+constexpr int kStepLdw = 64 + 1;        // of 64-wide operands
+constexpr int kStepLdsElems = 64 * kStepLd + kTile * kStepLdw + 2 * kTile * kStepLd;
+static_assert(kStepLdsElems >= kTile * kStepLd + kLuLdsElems, "step LDS too small for the look-ahead");
+
+// acc (+/-)= A[16 x kTile] B[kTile x 16] from LDS (row-major, leading dimensions lda, ldb).
+template <typename T, bool NEG>
+__device__ __forceinline__ void frag_mma(const T* A, int lda, const T* B, int ldb, typename MF<T>::acc& acc) {
+  const int lane = threadIdx.x & 63, i = lane & 15, k = lane >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < kTile; k0 += 4) {
+    const T av = A[i * lda + k0 + k];
+    acc = MF<T>::mma(NEG ? -av : av, B[(k0 + k) * ldb + i], acc);
+  }
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_tile_strips(const LuItem* items, int t0) {
-  const LuItem it = items[blockIdx.y];
-  if (t0 >= it.b) return;  // a smaller matrix of a merged batch
+__device__ __forceinline__ void zero_acc(typename MF<T>::acc& acc) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = T(0);
+}
+
+// Stages the two tile inverses of step s (kTile x kTile each) into LDS.
+template <typename T>
+__device__ __forceinline__ void stage_inverses(const LuItem& it, int s, T* sLi, T* sUi) {
+  const T* inv = step_inv<T>(it, s);
+  for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+    const int q = e >> 5, c = e & 31;
+    if (sLi) sLi[q * kStepLd + c] = gload(inv + e);
+    if (sUi) sUi[q * kStepLd + c] = gload(inv + kTile * kTile + e);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem) {
   T* A = static_cast<T*>(it.a);
-  const int b = it.b, ts = min(kTile, b - t0), tid = threadIdx.x;
-  const int rest = b - t0 - ts;
-  const int nR = (rest + 63) / 64, nL = (t0 + 63) / 64, nC = nR;
-  const int blk = blockIdx.x;
-  if (blk >= nR + nL + nC) return;
-  __shared__ T sInv[kTile][kTile + 1];
-  __shared__ T sX[64][kTile + 1];  // band: sX[c][q] = band row q, column c; below: sX[r][q]
-  __shared__ int sOrig[kTile];
-  if (tid < kTile) sOrig[tid] = tid < ts ? it.swaps[1 + tid] : tid;
-  const bool band = blk < nR + nL;
-  const bool right = blk < nR;
-  if (right || !band) {
-    const T* inv = static_cast<const T*>(it.aux) + (band ? 0 : kTile * kTile);
-    for (int e = tid; e < kTile * kTile; e += 256) sInv[e / kTile][e % kTile] = inv[e];
+  const int b = it.b, s = t0 / kTile, t1 = t0 + kTile, ts1 = min(kTile, b - t1);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  T* sT = smem;                    // updated tile s + 1
+  T* sA = sT + kTile * kStepLd;    // its rows of strip s, then L21
+  T* sB = sA + kTile * kStepLd;    // its columns of band s (P_s order), then U12
+  T* sLi = sB + kTile * kStepLd;
+  T* sUi = sLi + kTile * kStepLd;
+  const int32_t* pm = step_perm(it, s);
+  for (int e = tid; e < kTile * kTile; e += 256) {
+    const int x = e >> 5, y = e & 31;
+    sA[x * kStepLd + y] = x < ts1 ? gload(A + static_cast<int64_t>(t1 + x) * b + t0 + y) : T(0);
+    sB[x * kStepLd + y] = y < ts1 ? gload(A + static_cast<int64_t>(t0 + gload(pm + x)) * b + t1 + y) : T(0);
+  }
+  stage_inverses<T>(it, s, sLi, sUi);
+  __syncthreads();
+  // L21 fragment (wave >> 1, wave & 1) and U12 fragment (wave >> 1, wave & 1)
+  const int fi = wave >> 1, fj = wave & 1;
+  typename MF<T>::acc l21, u12;
+  zero_acc<T>(l21);
+  zero_acc<T>(u12);
+  frag_mma<T, false>(sA + 16 * fi * kStepLd, kStepLd, sUi + 16 * fj, kStepLd, l21);
+  frag_mma<T, false>(sLi + 16 * fi * kStepLd, kStepLd, sB + 16 * fj, kStepLd, u12);
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int x = 16 * fi + MF<T>::row(lane, v), y = 16 * fj + (lane & 15);
+    sA[x * kStepLd + y] = l21[v];
+    sB[x * kStepLd + y] = u12[v];
   }
   __syncthreads();
-  if (band) {
-    const int c0 = right ? t0 + ts + 64 * blk : 64 * (blk - nR);
-    const int cw = right ? min(64, b - c0) : min(64, t0 - c0);
-    // band rows in their new order (row q of the band is old row sOrig[q])
-    for (int e = tid; e < kTile * 64; e += 256) {
-      const int q = e >> 6, c = e & 63;
-      sX[c][q] = (c < cw && q < ts) ? A[static_cast<int64_t>(t0 + sOrig[q]) * b + c0 + c] : T(0);
-    }
-    __syncthreads();
-    const int c = tid & 63, rg = tid >> 6;  // column c, band rows 8 rg .. 8 rg + 7
-    T y[8];
+  typename MF<T>::acc acc;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) y[i] = right ? T(0) : sX[c][8 * rg + i];
-    if (right) {
-      // U12 = L_tt^{-1} (P_tt A12): runtime loop over the 32-term products
-      for (int q = 0; q < ts; ++q) {
-        const T xq = sX[c][q];
+  for (int v = 0; v < 4; ++v) {
+    const int x = 16 * fi + MF<T>::row(lane, v), y = 16 * fj + (lane & 15);
+    acc[v] = (x < ts1 && y < ts1) ? gload(A + static_cast<int64_t>(t1 + x) * b + t1 + y) : T(0);
+  }
+  frag_mma<T, true>(sA + 16 * fi * kStepLd, kStepLd, sB + 16 * fj, kStepLd, acc);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) y[i] += sInv[8 * rg + i][q] * xq;
-      }
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int x = 16 * fi + MF<T>::row(lane, v), y = 16 * fj + (lane & 15);
+    sT[x * kStepLd + y] = acc[v];
+  }
+  __syncthreads();
+  if (wave == 0) tile_lu_wave<T>(it, t1, sT, kStepLd, sA);
+}
+
+template <typename T>
+__device__ __forceinline__ void step_trailing(const LuItem& it, int t0, int ti, int tj, T* smem) {
+  T* A = static_cast<T*>(it.a);
+  const int b = it.b, s = t0 / kTile, t1 = t0 + kTile;
+  const int r0 = t1 + 64 * ti, c0 = t1 + 64 * tj;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  T* sA = smem;                     // [64][kStepLd]: rows r0.. of strip s, then L21
+  T* sB = sA + 64 * kStepLd;        // [kTile][kStepLdw]: band s (P_s order), columns c0.., then U12
+  T* sLi = sB + kTile * kStepLdw;
+  T* sUi = sLi + kTile * kStepLd;
+  const int32_t* pm = step_perm(it, s);
+  for (int e = tid; e < 64 * kTile; e += 256) {
+    const int x = e >> 5, q = e & 31;
+    sA[x * kStepLd + q] = r0 + x < b ? gload(A + static_cast<int64_t>(r0 + x) * b + t0 + q) : T(0);
+  }
+  for (int e = tid; e < kTile * 64; e += 256) {
+    const int q = e >> 6, y = e & 63;
+    sB[q * kStepLdw + y] = c0 + y < b ? gload(A + static_cast<int64_t>(t0 + gload(pm + q)) * b + c0 + y) : T(0);
+  }
+  stage_inverses<T>(it, s, sLi, sUi);
+  __syncthreads();
+  // Strip pieces: L21 (64 x 32, fragments 0..7) and U12 (32 x 64, fragments
+  // 8..15); wavefront w forms fragments w, w + 4, w + 8, w + 12.
+  typename MF<T>::acc pc[4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int row = 8 * rg + i;
-      if (c < cw && row < ts) A[static_cast<int64_t>(t0 + row) * b + c0 + c] = y[i];
-    }
-  } else {
-    const int r0 = t0 + ts + 64 * (blk - nR - nL);
-    const int rw = min(64, b - r0);
-    for (int e = tid; e < 64 * kTile; e += 256) {
-      const int r = e >> 5, q = e & 31;
-      sX[r][q] = (r < rw && q < ts) ? A[static_cast<int64_t>(r0 + r) * b + t0 + q] : T(0);
-    }
-    __syncthreads();
-    const int r = tid >> 2, cg = tid & 3;  // row r, tile columns 8 cg .. 8 cg + 7
-    T y[8];
+  for (int j = 0; j < 4; ++j) {
+    const int f = wave + 4 * j;
+    zero_acc<T>(pc[j]);
+    if (f < 8)
+      frag_mma<T, false>(sA + 16 * (f >> 1) * kStepLd, kStepLd, sUi + 16 * (f & 1), kStepLd, pc[j]);
+    else
+      frag_mma<T, false>(sLi + 16 * ((f - 8) >> 2) * kStepLd, kStepLd, sB + 16 * ((f - 8) & 3), kStepLdw, pc[j]);
+  }
+  __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 8; ++i) y[i] = T(0);
-    // L21 = A21 U_tt^{-1}
-    for (int q = 0; q < ts; ++q) {
-      const T xq = sX[r][q];
+  for (int j = 0; j < 4; ++j) {
+    const int f = wave + 4 * j;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) y[i] += xq * sInv[q][8 * cg + i];
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int col = 8 * cg + i;
-      if (r < rw && col < ts) A[static_cast<int64_t>(r0 + r) * b + t0 + col] = y[i];
+    for (int v = 0; v < 4; ++v) {
+      const int x = MF<T>::row(lane, v), y = lane & 15;
+      if (f < 8)
+        sA[(16 * (f >> 1) + x) * kStepLd + 16 * (f & 1) + y] = pc[j][v];
+      else
+        sB[(16 * ((f - 8) >> 2) + x) * kStepLdw + 16 * ((f - 8) & 3) + y] = pc[j][v];
     }
   }
+  __syncthreads();
+  // C -= L21 U12 on the 32 x 32 quarter of wavefront w.
+  const int wr = wave >> 1, wc = wave & 1;
+  typename MF<T>::acc acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gr = r0 + 32 * wr + 16 * i + MF<T>::row(lane, v), gc = c0 + 32 * wc + 16 * j + (lane & 15);
+        acc[i][j][v] = (gr < b && gc < b) ? gload(A + static_cast<int64_t>(gr) * b + gc) : T(0);
+      }
+#pragma unroll
+  for (int k0 = 0; k0 < kTile; k0 += 4) {
+    const int k = k0 + (lane >> 4);
+    T av[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) av[i] = -sA[(32 * wr + 16 * i + (lane & 15)) * kStepLd + k];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bv[j] = sB[k * kStepLdw + 32 * wc + 16 * j + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = MF<T>::mma(av[i], bv[j], acc[i][j]);
+  }
+  const int look = t1 + kTile;  // tile s + 1 belongs to the look-ahead workgroup
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gr = r0 + 32 * wr + 16 * i + MF<T>::row(lane, v), gc = c0 + 32 * wc + 16 * j + (lane & 15);
+        if (gr < b && gc < b && !(gr < look && gc < look)) gstore(A + static_cast<int64_t>(gr) * b + gc, acc[i][j][v]);
+      }
+}
+
+// L21 of tile s - 1 for rows [R0, R0 + 64): A21 U^{-1}, in place; rows of
+// tile s's band are taken in their new order.
+template <typename T>
+__device__ __forceinline__ void step_strip_rows(const LuItem& it, int t0, int i, T* smem) {
+  T* A = static_cast<T*>(it.a);
+  const int b = it.b, s = t0 / kTile, tp = t0 - kTile, ts = min(kTile, b - t0), R0 = t0 + 64 * i;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  T* sX = smem;                   // [64][kStepLd]
+  T* sUi = sX + 64 * kStepLd;
+  const int32_t* pm = step_perm(it, s);
+  for (int e = tid; e < 64 * kTile; e += 256) {
+    const int x = e >> 5, q = e & 31;
+    const int g = R0 + x;
+    T v = T(0);
+    if (g < b) {
+      const int src = g < t0 + ts ? t0 + gload(pm + (g - t0)) : g;
+      v = gload(A + static_cast<int64_t>(src) * b + tp + q);
+    }
+    sX[x * kStepLd + q] = v;
+  }
+  stage_inverses<T>(it, s - 1, static_cast<T*>(nullptr), sUi);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int f = wave + 4 * j, fi = f >> 1, fj = f & 1;
+    typename MF<T>::acc acc;
+    zero_acc<T>(acc);
+    frag_mma<T, false>(sX + 16 * fi * kStepLd, kStepLd, sUi + 16 * fj, kStepLd, acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int g = R0 + 16 * fi + MF<T>::row(lane, v);
+      if (g < b) gstore(A + static_cast<int64_t>(g) * b + tp + 16 * fj + (lane & 15), acc[v]);
+    }
+  }
+}
+
+// U12 of tile s - 1 for columns [C0, C0 + 64): L^{-1} P A12, in place.
+template <typename T>
+__device__ __forceinline__ void step_strip_cols(const LuItem& it, int t0, int j, T* smem) {
+  T* A = static_cast<T*>(it.a);
+  const int b = it.b, s = t0 / kTile, tp = t0 - kTile, C0 = t0 + 64 * j;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  T* sB = smem;                   // [kTile][kStepLdw]
+  T* sLi = sB + kTile * kStepLdw;
+  const int32_t* pm = step_perm(it, s - 1);
+  for (int e = tid; e < kTile * 64; e += 256) {
+    const int q = e >> 6, y = e & 63;
+    sB[q * kStepLdw + y] = C0 + y < b ? gload(A + static_cast<int64_t>(tp + gload(pm + q)) * b + C0 + y) : T(0);
+  }
+  stage_inverses<T>(it, s - 1, sLi, static_cast<T*>(nullptr));
+  __syncthreads();
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj) {
+    const int f = wave + 4 * jj, gi = f >> 2, gj = f & 3;
+    typename MF<T>::acc acc;
+    zero_acc<T>(acc);
+    frag_mma<T, false>(sLi + 16 * gi * kStepLd, kStepLd, sB + 16 * gj, kStepLdw, acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int y = C0 + 16 * gj + (lane & 15);
+      if (y < b) gstore(A + static_cast<int64_t>(tp + 16 * gi + MF<T>::row(lane, v)) * b + y, acc[v]);
+    }
+  }
+}
+
+// Rows of tile s's band in their new order, columns [64 j, 64 j + 64) left
+// of tile s - 1.
+template <typename T>
+__device__ __forceinline__ void step_band(const LuItem& it, int t0, int j) {
+  T* A = static_cast<T*>(it.a);
+  const int b = it.b, s = t0 / kTile, ts = min(kTile, b - t0), cend = t0 - kTile;
+  const int32_t* pm = step_perm(it, s);
+  T v[kTile * 64 / 256];
+#pragma unroll
+  for (int t = 0; t < kTile * 64 / 256; ++t) {
+    const int e = threadIdx.x + 256 * t, q = e >> 6, y = 64 * j + (e & 63);
+    v[t] = (q < ts && y < cend) ? gload(A + static_cast<int64_t>(t0 + gload(pm + q)) * b + y) : T(0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < kTile * 64 / 256; ++t) {
+    const int e = threadIdx.x + 256 * t, q = e >> 6, y = 64 * j + (e & 63);
+    if (q < ts && y < cend) gstore(A + static_cast<int64_t>(t0 + q) * b + y, v[t]);
+  }
+}
+
+// Workgroup counts of the tile step at t0 for a matrix of order b.
+struct StepShape {
+  int look, trail_n, strip, band;
+  __host__ __device__ StepShape(int b, int t0) {
+    const int s = t0 / kTile, rest = b - t0 - kTile;
+    look = rest > 0 ? 1 : 0;
+    trail_n = rest > 0 ? (rest + 63) / 64 : 0;
+    strip = s > 0 ? (b - t0 + 63) / 64 : 0;
+    band = s > 1 ? (t0 - kTile + 63) / 64 : 0;
+  }
+  __host__ __device__ int total() const { return look + trail_n * trail_n + 2 * strip + band; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_step(const LuItem* items, int t0) {
+  __shared__ __attribute__((aligned(16))) T smem[kStepLdsElems];
+  const LuItem it = items[blockIdx.y];
+  if (t0 >= it.b) return;  // a smaller matrix of a merged batch
+  const StepShape sh(it.b, t0);
+  int bx = blockIdx.x;
+  if (bx < sh.look) {
+    step_lookahead<T>(it, t0, smem);
+    return;
+  }
+  bx -= sh.look;
+  if (bx < sh.trail_n * sh.trail_n) {
+    step_trailing<T>(it, t0, bx / sh.trail_n, bx % sh.trail_n, smem);
+    return;
+  }
+  bx -= sh.trail_n * sh.trail_n;
+  if (bx < sh.strip) {
+    step_strip_rows<T>(it, t0, bx, smem);
+    return;
+  }
+  bx -= sh.strip;
+  if (bx < sh.strip) {
+    step_strip_cols<T>(it, t0, bx, smem);
+    return;
+  }
+  bx -= sh.strip;
+  if (bx < sh.band) step_band<T>(it, t0, bx);
 }
 
 // ---------------------------------------------------------------------------
@@ -1325,23 +1588,30 @@ hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n
   if constexpr (sizeof(T) == 4) {
     if (L.lp) return launch_gemm_lp<MODE, GEN>(L, count, max_m, max_n, st);
   }
-  // Large products: 128 x 256 output tiles, 16 wavefronts of 64 x 32 (four
-  // per SIMD, so MFMA issue continues while other wavefronts wait on LDS or
-  // memory); small ones: 64 x 64 tiles for more workgroups.
-  // The generic (element-wise view) instance always takes the small tiles.
-  // Look-ahead trailing updates carry one more workgroup per matrix.  Those
-  // rank-32 updates are bound by memory, not MFMA, and take the 64 x 64 tiles
-  // (256 threads: the factorising wavefront keeps its full register budget).
-  const int extra = (MODE == GEMM_LU_TRAILING && L.npairs) ? 1 : 0;
+  // Tile shapes by the number of output tiles the launch has (four
+  // wavefronts per SIMD where possible, so MFMA issue continues while other
+  // wavefronts wait on LDS or memory):
+  //   large: 128 x 256 tiles, 16 wavefronts of 64 x 32;
+  //   medium: 128 x 128 tiles, 16 wavefronts of 32 x 32;
+  //   small: 64 x 64 tiles, 16 wavefronts of 16 x 16.
+  // The generic (element-wise view) instance and the trailing updates of the
+  // partial-pivoting LU take 64 x 64 tiles of four 32 x 32 wavefronts.
   if constexpr (!GEN && MODE != GEMM_LU_TRAILING) {
     const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 256) * count;
+    const int64_t mid_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * count;
     if (big_tiles >= 192) {
-      dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 256) + extra, count);
+      dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 256), count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 256, 16, 64, 32>), grid, dim3(1024), 0, st, L);
-      return hipGetLastError();
+    } else if (mid_tiles >= 128) {
+      dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), count);
+      hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 128, 16, 32, 32>), grid, dim3(1024), 0, st, L);
+    } else {
+      dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), count);
+      hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 64, 64, 16, 16, 16>), grid, dim3(1024), 0, st, L);
     }
+    return hipGetLastError();
   }
-  dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64) + extra, count);
+  dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), count);
   hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 64, 64, 16, 32, 32>), grid, dim3(256), 0, st, L);
   return hipGetLastError();
 }
@@ -1372,27 +1642,12 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
 
 template <typename T>
 hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, hipStream_t st) {
-  // Tile t + 1 is updated and factored inside the trailing-update launch of
-  // tile t (look-ahead), so per tile step the critical path is the strip
-  // solves followed by the longer of the trailing update and the next tile.
+  // Tile 0, then one launch per diagonal tile (k_lu_step): the launch of tile
+  // s factors tile s + 1, so consecutive launches form the critical path.
   hipLaunchKernelGGL((k_tile_lu<T>), dim3(count), dim3(64), 0, st, d_items, 0);
   for (int t0 = 0; t0 < b; t0 += kTile) {
-    const int ts = std::min(kTile, b - t0);
-    const int rest = b - t0 - ts;
-    const int nblk = 2 * cdiv(rest, 64) + cdiv(t0, 64);
-    if (nblk > 0) hipLaunchKernelGGL((k_tile_strips<T>), dim3(nblk, count), dim3(256), 0, st, d_items, t0);
-    if (rest > 0) {
-      GemmLaunch L{};
-      L.mode = GEMM_LU_TRAILING;
-      L.elem = sizeof(T);
-      L.items = d_items;
-      L.count = count;
-      L.j = t0;
-      L.w = ts;
-      L.npairs = 1;  // look-ahead
-      hipError_t e = launch_gemm<T>(L, rest, rest, st);
-      if (e != hipSuccess) return e;
-    }
+    const int grid = StepShape(b, t0).total();
+    if (grid > 0) hipLaunchKernelGGL((k_lu_step<T>), dim3(grid, count), dim3(256), 0, st, d_items, t0);
   }
   return hipGetLastError();
 }

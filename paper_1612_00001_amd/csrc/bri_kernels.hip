@@ -267,6 +267,29 @@ struct TileOp {
   }
 };
 
+// Work item and output tile of a workgroup.  Workgroups are numbered item
+// fastest (tile t of every item before tile t + 1 of any), so that
+// workgroups dispatched together spread over all items.  With a triangular
+// operand the K range of a tile depends on its position; the heaviest tiles
+// take the lowest numbers (dispatched first) so that a launch does not end
+// on a tail of long tiles.
+__device__ __forceinline__ void gemm_workgroup(int& item, int& tile) {
+  const int flat = blockIdx.y * gridDim.x + blockIdx.x;
+  item = flat % gridDim.y;
+  tile = flat / gridDim.y;
+}
+__device__ __forceinline__ void heavy_first(const GemmItem& it, int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  if (it.B.tri != 0 && it.A.tri == 0) {
+    tn = bid / tiles_m;
+    tm = bid % tiles_m;
+  } else {
+    tm = bid / tiles_n;
+    tn = bid % tiles_n;
+  }
+  if (it.A.tri == 1) tm = tiles_m - 1 - tm;  // lower A: rows further down use more of K
+  if (it.B.tri == 2) tn = tiles_n - 1 - tn;  // upper B: columns further right use more of K
+}
+
 // ---------------------------------------------------------------------------
 // Batched MFMA GEMM.  One workgroup computes a BM x BN output tile with
 // (BM/WM) x (BN/WN) wavefronts of WM x WN each; K is consumed BK at a time
@@ -288,11 +311,14 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
   constexpr bool USE_PERM = (MODE == GEMM_EXPLICIT) && !GEN;
 
   GemmItem it;
-  if (!gemm_item<T, MODE>(L, blockIdx.y + (GEN ? L.j : 0), it)) return;
+  int item, tile;
+  gemm_workgroup(item, tile);
+  if (!gemm_item<T, MODE>(L, item + (GEN ? L.j : 0), it)) return;
   const int tiles_n = (it.N + BN - 1) / BN;
   const int tiles_m = (it.M + BM - 1) / BM;
-  if (static_cast<int>(blockIdx.x) >= tiles_m * tiles_n) return;
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  if (tile >= tiles_m * tiles_n) return;
+  int tm, tn;
+  heavy_first(it, tile, tiles_m, tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
 
   int kb = 0, ke = it.K;
@@ -464,11 +490,14 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lp(GemmLaun
   constexpr int AE = OpA::E, BE = OpB::E;
 
   GemmItem it;
-  if (!gemm_item<float, MODE>(L, blockIdx.y + (GEN ? L.j : 0), it)) return;
+  int item, tile;
+  gemm_workgroup(item, tile);
+  if (!gemm_item<float, MODE>(L, item + (GEN ? L.j : 0), it)) return;
   const int tiles_n = (it.N + BN - 1) / BN;
   const int tiles_m = (it.M + BM - 1) / BM;
-  if (static_cast<int>(blockIdx.x) >= tiles_m * tiles_n) return;
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  if (tile >= tiles_m * tiles_n) return;
+  int tm, tn;
+  heavy_first(it, tile, tiles_m, tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   int kb = 0, ke = it.K;
   if (it.A.tri == 1) ke = min(ke, m0 + BM);
@@ -1078,30 +1107,27 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
   //   lanes 0..31 : column r of L^{-1}        (L unit lower: L[i][q] = sFT[q][i]);
   //   lanes 32..63: column r of (U^T)^{-1} = row r of U^{-1}
   //                 ((U^T)[i][q] = U[q][i] = sF[q][i], diagonal 1 / sD).
-  // Row q + 1 of the operand is read from LDS while step q computes
-  // (scheduling barriers keep every step's reads next to it).
+  // Element i of operand row q + 1 is read from LDS as soon as step q has
+  // used element i of row q (scheduling barriers keep every step's reads
+  // next to it), so one row of registers holds the operand.
   const T* Mq = half ? &sF[0][0] : &sFT[0][0];
   T xs[kTile];
 #pragma unroll
   for (int q = 0; q < kTile; ++q) xs[q] = (q == r) ? T(1) : T(0);
-  T mrow[2][kTile];
-  T dq[2];
+  T mrow[kTile];
 #pragma unroll
-  for (int i = 1; i < kTile; ++i) mrow[0][i] = Mq[i];
-  dq[0] = sD[0];
+  for (int i = 1; i < kTile; ++i) mrow[i] = Mq[i];
+  T dq = sD[0];
 #pragma unroll
   for (int q = 0; q < kTile; ++q) {
-    const int cur = q & 1, nxt = cur ^ 1;
-    if (q + 1 < kTile) {
-#pragma unroll
-      for (int i = q + 2; i < kTile; ++i) mrow[nxt][i] = Mq[(q + 1) * LD + i];
-      dq[nxt] = sD[q + 1];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    const T xq = half ? xs[q] * dq[cur] : xs[q];
+    const T xq = half ? xs[q] * dq : xs[q];
     xs[q] = xq;
+    if (q + 1 < kTile) dq = sD[q + 1];
 #pragma unroll
-    for (int i = q + 1; i < kTile; ++i) xs[i] = fma(-mrow[cur][i], xq, xs[i]);
+    for (int i = q + 1; i < kTile; ++i) {
+      xs[i] = fma(-mrow[i], xq, xs[i]);
+      if (i >= q + 2) mrow[i] = Mq[(q + 1) * LD + i];
+    }
     __builtin_amdgcn_sched_barrier(0);
   }
   T* aux = step_inv<T>(it, s);
@@ -1182,6 +1208,13 @@ __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem
   T* sLi = sB + kTile * kStepLd;
   T* sUi = sLi + kTile * kStepLd;
   const int32_t* pm = step_perm(it, s);
+  const int fi = wave >> 1, fj = wave & 1;
+  typename MF<T>::acc acc;  // this wavefront's 16 x 16 fragment of tile s + 1, requested first
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int x = 16 * fi + MF<T>::row(lane, v), y = 16 * fj + (lane & 15);
+    acc[v] = (x < ts1 && y < ts1) ? gload(A + static_cast<int64_t>(t1 + x) * b + t1 + y) : T(0);
+  }
   for (int e = tid; e < kTile * kTile; e += 256) {
     const int x = e >> 5, y = e & 31;
     sA[x * kStepLd + y] = x < ts1 ? gload(A + static_cast<int64_t>(t1 + x) * b + t0 + y) : T(0);
@@ -1190,7 +1223,6 @@ __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem
   stage_inverses<T>(it, s, sLi, sUi);
   __syncthreads();
   // L21 fragment (wave >> 1, wave & 1) and U12 fragment (wave >> 1, wave & 1)
-  const int fi = wave >> 1, fj = wave & 1;
   typename MF<T>::acc l21, u12;
   zero_acc<T>(l21);
   zero_acc<T>(u12);
@@ -1204,12 +1236,6 @@ __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem
     sB[x * kStepLd + y] = u12[v];
   }
   __syncthreads();
-  typename MF<T>::acc acc;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int x = 16 * fi + MF<T>::row(lane, v), y = 16 * fj + (lane & 15);
-    acc[v] = (x < ts1 && y < ts1) ? gload(A + static_cast<int64_t>(t1 + x) * b + t1 + y) : T(0);
-  }
   frag_mma<T, true>(sA + 16 * fi * kStepLd, kStepLd, sB + 16 * fj, kStepLd, acc);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -1231,6 +1257,19 @@ __device__ __forceinline__ void step_trailing(const LuItem& it, int t0, int ti, 
   T* sLi = sB + kTile * kStepLdw;
   T* sUi = sLi + kTile * kStepLd;
   const int32_t* pm = step_perm(it, s);
+  // The block of C (32 x 32 per wavefront) is requested first: its loads are
+  // in flight while the strip pieces are formed.
+  const int wr = wave >> 1, wc = wave & 1;
+  typename MF<T>::acc acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gr = r0 + 32 * wr + 16 * i + MF<T>::row(lane, v), gc = c0 + 32 * wc + 16 * j + (lane & 15);
+        acc[i][j][v] = (gr < b && gc < b) ? gload(A + static_cast<int64_t>(gr) * b + gc) : T(0);
+      }
   for (int e = tid; e < 64 * kTile; e += 256) {
     const int x = e >> 5, q = e & 31;
     sA[x * kStepLd + q] = r0 + x < b ? gload(A + static_cast<int64_t>(r0 + x) * b + t0 + q) : T(0);
@@ -1268,17 +1307,6 @@ __device__ __forceinline__ void step_trailing(const LuItem& it, int t0, int ti, 
   }
   __syncthreads();
   // C -= L21 U12 on the 32 x 32 quarter of wavefront w.
-  const int wr = wave >> 1, wc = wave & 1;
-  typename MF<T>::acc acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gr = r0 + 32 * wr + 16 * i + MF<T>::row(lane, v), gc = c0 + 32 * wc + 16 * j + (lane & 15);
-        acc[i][j][v] = (gr < b && gc < b) ? gload(A + static_cast<int64_t>(gr) * b + gc) : T(0);
-      }
 #pragma unroll
   for (int k0 = 0; k0 < kTile; k0 += 4) {
     const int k = k0 + (lane >> 4);

@@ -467,6 +467,7 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lp,
         L.count = s.count;
         L.w = s.nfast;
         L.lp = lp;
+        L.tri = (s.kind == ST_TRMM_L || s.kind == ST_TRMM_U) ? 1 : 0;
         e = launch_gemm<T>(L, bmax, bmax, st);
         break;
       }

@@ -85,6 +85,7 @@ struct GemmLaunch {
   int32_t s;            // TRTRI level: half-block size
   int32_t npairs;       // TRTRI level: block pairs per matrix
   int32_t lp;           // float storage only: 0 FP32 MFMA, 1 FP16 split, 2 BF16 split
+  int32_t tri;          // items have a triangular operand (uneven K per output tile)
 };
 
 constexpr int kMaxBlock = 4096;  // == BRI_MAX_BLOCK

@@ -1624,13 +1624,16 @@ hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n
   //   small: 64 x 64 tiles, 16 wavefronts of 16 x 16.
   // The generic (element-wise view) instance and the trailing updates of the
   // partial-pivoting LU take 64 x 64 tiles of four 32 x 32 wavefronts.
+  // Products with a triangular operand have uneven tiles and take the larger
+  // shapes only with at least two workgroups per compute unit.
   if constexpr (!GEN && MODE != GEMM_LU_TRAILING) {
+    const bool tri = L.tri != 0 || MODE == GEMM_TRTRI_STEP1 || MODE == GEMM_TRTRI_STEP2;
     const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 256) * count;
     const int64_t mid_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * count;
-    if (big_tiles >= 192) {
+    if (big_tiles >= (tri ? 512 : 192)) {
       dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 256), count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 256, 16, 64, 32>), grid, dim3(1024), 0, st, L);
-    } else if (mid_tiles >= 128) {
+    } else if (mid_tiles >= (tri ? 512 : 128)) {
       dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 128, 16, 32, 32>), grid, dim3(1024), 0, st, L);
     } else {

@@ -239,7 +239,7 @@ def main() -> int:
     p_la = sum(prof[t][1] for t in prod_kinds if t in prof)
     achieved = p_fl / (p_ms * 1e-3) / 1e12 if p_ms > 0 else 0.0
     roofline = {
-        "kernel": "k_gemm<double, GEMM_EXPLICIT, 128x256 (16 waves) or 64x64> (Schur and triangular products)",
+        "kernel": "k_gemm<double, GEMM_EXPLICIT> (Schur and triangular products; 128x256, 128x128 or 64x64 tiles of 16 wavefronts)",
         "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
         "frac": achieved / PEAK_TFLOPS["f64"], "traffic": counted_traffic(),
         "launches_per_step": p_la / args.steps, "avg_launch_ms": (p_ms / p_la) if p_la else None,

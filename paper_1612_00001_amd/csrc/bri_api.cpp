@@ -403,10 +403,10 @@ double step_flops(const Step& s, int b) {
   }
 }
 
-int64_t step_launches(const Step& s, int b) {
+int64_t step_launches(const Step& s, int b, int pivoting) {
   switch (s.kind) {
     case ST_GETRF:
-      return getrf_launches(b);
+      return getrf_launches(b, pivoting != BRI_PIVOT_PANEL);
     case ST_TRTRI:
       return trtri_launches(b);
     default:
@@ -442,7 +442,7 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lp,
     if (prof) {
       std::lock_guard<std::mutex> g(g_prof_mu);
       rec.kind = s.kind;
-      rec.launches = step_launches(*s.step, bmax);
+      rec.launches = step_launches(*s.step, bmax, pivoting);
       rec.flops = s.flops;
       rec.e0 = prof_event();
       rec.e1 = prof_event();
@@ -1158,7 +1158,9 @@ int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_pla
   s->slots = p.nslots;
   s->batch_width = p.width;
   s->steps = static_cast<int64_t>(p.steps.size());
-  s->kernel_launches = p.launches + 1;  // + clearing d_info
+  int64_t launches = 1;  // clearing d_info
+  for (const Step& st : p.steps) launches += step_launches(st, p.b, o->pivoting);
+  s->kernel_launches = launches;
   s->block = p.b;
   s->algorithmic_flops = p.algorithmic_flops;
   s->executed_flops = p.executed_flops;

@@ -166,7 +166,7 @@ struct Plan {
   int nslots = 0;           // high-water mark of simultaneously live slots
   int64_t schur_ops = 0;
   int64_t final_inversions = 0;
-  int64_t launches = 0;
+  int64_t launches = 0;     // kernel launches with tile pivoting
   double executed_flops = 0;
   double algorithmic_flops = 0;
 };
@@ -196,7 +196,8 @@ RefinePlans make_refine_plans(int64_t n, int k, int j, int width, bool reuse);
 Plan make_block_plan_reuse(int64_t n, int k, int i, int j, int width);
 
 // Launch/flop accounting of the kernels that realise a step.
-int64_t getrf_launches(int b);
+// Kernel launches of one batched LU (tile pivoting, or panels with partial pivoting).
+int64_t getrf_launches(int b, bool tile_pivoting);
 int64_t trtri_launches(int b);
 double getrf_flops(int b);
 double trtri_flops(int b);

@@ -438,7 +438,7 @@ void account(Plan& p) {
         p.launches += 1;
         break;
       case ST_GETRF:
-        p.launches += getrf_launches(p.b);
+        p.launches += getrf_launches(p.b, true);
         p.executed_flops += n * getrf_flops(p.b);
         break;
       case ST_TRTRI:
@@ -460,7 +460,8 @@ void account(Plan& p) {
 
 }  // namespace
 
-int64_t getrf_launches(int b) {
+int64_t getrf_launches(int b, bool tile_pivoting) {
+  if (tile_pivoting) return 1 + (b > kTile ? (b + kTile - 1) / kTile : 0);  // first tile, one launch per tile
   int64_t n = 0;
   for (int j = 0; j < b;) {
     const int w = std::min(panel_width(b - j), b - j);

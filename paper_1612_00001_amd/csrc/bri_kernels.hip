@@ -1434,10 +1434,17 @@ struct StepShape {
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_step(const LuItem* items, int t0) {
   __shared__ __attribute__((aligned(16))) T smem[kStepLdsElems];
-  const LuItem it = items[blockIdx.y];
+  // Workgroups are numbered matrix-fastest: the look-ahead workgroups of all
+  // matrices come first, and consecutive workgroups (which the dispatcher
+  // spreads over the XCDs in turn) of one matrix land on the same XCDs, so
+  // the strips and tile inverses every block of a matrix reads stay in
+  // those XCDs' L2.
+  int item, role;
+  gemm_workgroup(item, role);
+  const LuItem it = items[item];
   if (t0 >= it.b) return;  // a smaller matrix of a merged batch
   const StepShape sh(it.b, t0);
-  int bx = blockIdx.x;
+  int bx = role;
   if (bx < sh.look) {
     step_lookahead<T>(it, t0, smem);
     return;

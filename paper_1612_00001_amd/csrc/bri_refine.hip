@@ -27,15 +27,43 @@ __device__ __forceinline__ double bits_to_double(const double* p) {
   return __longlong_as_double(*reinterpret_cast<const long long*>(p));
 }
 
+// Maximum that propagates a NaN (fmax would drop it).
+__device__ __forceinline__ double nan_max(double m, double v) { return (v > m || v != v) ? v : m; }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  for (int o = 32; o >= 1; o >>= 1) v = nan_max(v, __shfl_xor(v, o, 64));
   return v;
 }
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// Reductions over the 256 threads of a workgroup (every thread gets the
+// result); one atomic per workgroup then updates the problem's scalar, so
+// the scalars see few atomic operations.
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double part[4];
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = part[0];
+#pragma unroll
+  for (int w = 1; w < 4; ++w) m = nan_max(m, part[w]);
+  return m;
+}
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+  __shared__ double part[2][4];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    part[0][threadIdx.x >> 6] = a;
+    part[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  a = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+  b = part[1][0] + part[1][1] + part[1][2] + part[1][3];
 }
 
 __device__ __forceinline__ int64_t first_elem() { return static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; }
@@ -49,10 +77,10 @@ __global__ __launch_bounds__(256) void k_absmax(const RefItem* items, int which)
   for (int64_t e = first_elem(); e < rows * cols; e += elem_stride()) {
     const int64_t r = e / cols, c = e - r * cols;
     const double v = fabs(p[r * ld + c]);
-    m = (v > m || v != v) ? v : m;  // a NaN propagates (its bits order above +inf)
+    m = nan_max(m, v);  // a NaN propagates (its bits order above +inf in the atomic maximum)
   }
-  m = wave_max(m);
-  if ((threadIdx.x & 63) == 0)
+  m = block_max(m);
+  if (threadIdx.x == 0)
     atomicMax(reinterpret_cast<unsigned long long*>(it.scal + which),
               static_cast<unsigned long long>(__double_as_longlong(m)));
 }
@@ -107,9 +135,8 @@ __global__ __launch_bounds__(256) void k_refine_update(const RefItem* items, int
     dd += d * d;
     xx += x * x;
   }
-  dd = wave_sum(dd);
-  xx = wave_sum(xx);
-  if ((threadIdx.x & 63) == 0) {
+  block_sum2(dd, xx);
+  if (threadIdx.x == 0) {
     atomicAdd(it.scal + 2, dd);
     atomicAdd(it.scal + 3, xx);
   }
@@ -137,6 +164,16 @@ __global__ void k_info_unconverged(int32_t* info) {
 
 // x extent: enough workgroups for the largest problem, fewer per problem when
 // there are many problems (every workgroup strides over its problem).
+// Reductions: at most 256 workgroups per problem (each thread then streams
+// many elements), so that few atomics reach the problem's scalars.
+inline dim3 grid_reduce(int64_t max_elems, int count) {
+  int64_t g = (max_elems + 255) / 256;
+  int64_t cap = 65536 / (count > 0 ? count : 1);
+  cap = cap < 16 ? 16 : (cap > 256 ? 256 : cap);
+  g = g < 1 ? 1 : (g > cap ? cap : g);
+  return dim3(static_cast<unsigned>(g), static_cast<unsigned>(count));
+}
+
 inline dim3 grid_for(int64_t max_elems, int count) {
   int64_t g = (max_elems + 255) / 256;
   int64_t cap = 65536 / (count > 0 ? count : 1);
@@ -149,7 +186,7 @@ inline dim3 grid_for(int64_t max_elems, int count) {
 
 hipError_t launch_absmax(const RefItem* items, int count, int which, int64_t max_elems, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_absmax, grid_for(max_elems, count), dim3(256), 0, st, items, which);
+  hipLaunchKernelGGL(k_absmax, grid_reduce(max_elems, count), dim3(256), 0, st, items, which);
   return hipGetLastError();
 }
 
@@ -173,7 +210,7 @@ hipError_t launch_rhs_scale(const RefItem* items, int count, int64_t max_elems, 
 
 hipError_t launch_refine_update(const RefItem* items, int count, int64_t max_elems, int first, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_refine_update, grid_for(max_elems, count), dim3(256), 0, st, items, first);
+  hipLaunchKernelGGL(k_refine_update, grid_reduce(max_elems, count), dim3(256), 0, st, items, first);
   return hipGetLastError();
 }
 

@@ -408,7 +408,7 @@ int64_t step_launches(const Step& s, int b, int pivoting) {
     case ST_GETRF:
       return getrf_launches(b, pivoting != BRI_PIVOT_PANEL);
     case ST_TRTRI:
-      return trtri_launches(b);
+      return trtri_launches(b, pivoting != BRI_PIVOT_PANEL);
     default:
       return 1;
   }
@@ -457,7 +457,7 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lp,
                                         : launch_getrf_tile<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
         break;
       case ST_TRTRI:
-        e = launch_trtri<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
+        e = launch_trtri<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, pivoting != BRI_PIVOT_PANEL, st);
         break;
       default: {
         GemmLaunch L{};

@@ -198,7 +198,7 @@ Plan make_block_plan_reuse(int64_t n, int k, int i, int j, int width);
 // Launch/flop accounting of the kernels that realise a step.
 // Kernel launches of one batched LU (tile pivoting, or panels with partial pivoting).
 int64_t getrf_launches(int b, bool tile_pivoting);
-int64_t trtri_launches(int b);
+int64_t trtri_launches(int b, bool tile_pivoting);
 double getrf_flops(int b);
 double trtri_flops(int b);
 

@@ -14,7 +14,8 @@ hipError_t launch_getrf(const LuItem* d_items, int count, int b, hipStream_t st)
 template <typename T>
 hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, hipStream_t st);
 template <typename T>
-hipError_t launch_trtri(const LuItem* d_items, int count, int b, hipStream_t st);
+// diag_inverted: the LU (tile pivoting) already left its diagonal 32 x 32 tiles inverted.
+hipError_t launch_trtri(const LuItem* d_items, int count, int b, bool diag_inverted, hipStream_t st);
 template <typename T>
 hipError_t launch_load(const LoadItem* d_items, int count, int rows, int cols, hipStream_t st);
 hipError_t launch_fill_int(int32_t* p, int n, int v, hipStream_t st);

@@ -1086,13 +1086,6 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
     sF[pos][c] = fv[t];
     sFT[c][pos] = fv[t];
   }
-  if (r < ts) {
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int c = 16 * half + t;
-      if (c < ts) gstore(A + static_cast<int64_t>(t0 + pos) * b + t0 + c, fv[t]);
-    }
-  }
   // Row movement of the tile: position pos holds original tile row r.  Rows
   // never leave their band, so the band's permutation entries are t0 + r.
   if (half == 0 && r < ts) {
@@ -1140,10 +1133,33 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
   }
 }
 
+static_assert(kTrtriTile == kTile, "the tile LU inverts the diagonal tiles of the triangular inversion");
+
+// Diagonal tile q receives its packed inverses from aux (L^{-1} below the
+// diagonal, U^{-1} on and above it), the form the triangular inversion that
+// follows every factorisation starts from; no kernel reads a tile's factors
+// once its inverses are in aux.  The tile steps copy them (off the critical
+// path); a matrix of a single tile is handled by k_tile_lu.
+template <typename T>
+__device__ __forceinline__ void step_diag_inverse(const LuItem& it, int q) {
+  T* A = static_cast<T*>(it.a);
+  const int b = it.b, tq = q * kTile, ts = min(kTile, b - tq);
+  const T* inv = step_inv<T>(it, q);
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int i = e >> 5, c = e & 31;
+    if (i < ts && c < ts)
+      gstore(A + static_cast<int64_t>(tq + i) * b + tq + c, gload(inv + (c < i ? 0 : kTile * kTile) + e));
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
   __shared__ __attribute__((aligned(16))) T lds[kLuLdsElems];
   tile_lu_wave<T>(items[blockIdx.x], t0, nullptr, 0, lds);
+  if (t0 == 0 && items[blockIdx.x].b <= kTile) {
+    __threadfence();  // the inverses this wavefront stored to aux
+    step_diag_inverse<T>(items[blockIdx.x], 0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1462,6 +1478,12 @@ __global__ __launch_bounds__(256) void k_lu_step(const LuItem* items, int t0) {
   bx -= sh.strip;
   if (bx < sh.strip) {
     step_strip_cols<T>(it, t0, bx, smem);
+    if (bx == 0) {
+      // The inverses of tile s - 1 (and of the last tile, which no later
+      // launch sees) go to their diagonal tiles.
+      step_diag_inverse<T>(it, t0 / kTile - 1);
+      if (t0 + kTile >= it.b) step_diag_inverse<T>(it, t0 / kTile);
+    }
     return;
   }
   bx -= sh.strip;
@@ -1737,8 +1759,11 @@ hipError_t launch_getrf(const LuItem* d_items, int count, int b, hipStream_t st)
 }
 
 template <typename T>
-hipError_t launch_trtri(const LuItem* d_items, int count, int b, hipStream_t st) {
-  hipLaunchKernelGGL((k_trtri_diag<T, kTrtriTile>), dim3(cdiv(b, kTrtriTile), count), dim3(128), 0, st, d_items);
+hipError_t launch_trtri(const LuItem* d_items, int count, int b, bool diag_inverted, hipStream_t st) {
+  // The tile-pivoting LU leaves the inverses of its 32 x 32 diagonal tiles in
+  // place; after the partial-pivoting LU they are formed here.
+  if (!diag_inverted)
+    hipLaunchKernelGGL((k_trtri_diag<T, kTrtriTile>), dim3(cdiv(b, kTrtriTile), count), dim3(128), 0, st, d_items);
   for (int s = kTrtriTile; s < b; s *= 2) {
     const int npairs = cdiv(b - s, 2 * s);
     GemmLaunch L{};
@@ -1777,8 +1802,8 @@ template hipError_t launch_getrf<double>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_getrf_tile<double>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_getrf_tile<float>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_getrf<float>(const LuItem*, int, int, hipStream_t);
-template hipError_t launch_trtri<double>(const LuItem*, int, int, hipStream_t);
-template hipError_t launch_trtri<float>(const LuItem*, int, int, hipStream_t);
+template hipError_t launch_trtri<double>(const LuItem*, int, int, bool, hipStream_t);
+template hipError_t launch_trtri<float>(const LuItem*, int, int, bool, hipStream_t);
 template hipError_t launch_load<double>(const LoadItem*, int, int, int, hipStream_t);
 template hipError_t launch_load<float>(const LoadItem*, int, int, int, hipStream_t);
 

@@ -442,7 +442,7 @@ void account(Plan& p) {
         p.executed_flops += n * getrf_flops(p.b);
         break;
       case ST_TRTRI:
-        p.launches += trtri_launches(p.b);
+        p.launches += trtri_launches(p.b, true);
         p.executed_flops += n * trtri_flops(p.b);
         break;
       case ST_TRMM_L:
@@ -473,8 +473,8 @@ int64_t getrf_launches(int b, bool tile_pivoting) {
   return n;
 }
 
-int64_t trtri_launches(int b) {
-  int64_t n = 1;
+int64_t trtri_launches(int b, bool tile_pivoting) {
+  int64_t n = tile_pivoting ? 0 : 1;  // diagonal tiles (left inverted by the tile-pivoting LU)
   for (int s = kTrtriTile; s < b; s *= 2) n += 2;
   return n;
 }

@@ -1212,6 +1212,18 @@ __device__ __forceinline__ void stage_inverses(const LuItem& it, int s, T* sLi, 
     if (sUi) sUi[q * kStepLd + c] = gload(inv + kTile * kTile + e);
   }
 }
+// Stages L_s^{-1} P_s instead of L_s^{-1}: column pm[c] receives column c of
+// L_s^{-1}, so that (L_s^{-1} P_s) A12 = L_s^{-1} (P_s A12) reads the band
+// rows of A12 in their stored order and no load waits for the permutation.
+template <typename T>
+__device__ __forceinline__ void stage_linv_perm(const LuItem& it, int s, T* sLi) {
+  const T* inv = step_inv<T>(it, s);
+  const int32_t* pm = step_perm(it, s);
+  for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+    const int q = e >> 5, c = e & 31;
+    sLi[q * kStepLd + gload(pm + c)] = gload(inv + e);
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem) {
@@ -1223,7 +1235,6 @@ __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem
   T* sB = sA + kTile * kStepLd;    // its columns of band s (P_s order), then U12
   T* sLi = sB + kTile * kStepLd;
   T* sUi = sLi + kTile * kStepLd;
-  const int32_t* pm = step_perm(it, s);
   const int fi = wave >> 1, fj = wave & 1;
   typename MF<T>::acc acc;  // this wavefront's 16 x 16 fragment of tile s + 1, requested first
 #pragma unroll
@@ -1234,9 +1245,10 @@ __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem
   for (int e = tid; e < kTile * kTile; e += 256) {
     const int x = e >> 5, y = e & 31;
     sA[x * kStepLd + y] = x < ts1 ? gload(A + static_cast<int64_t>(t1 + x) * b + t0 + y) : T(0);
-    sB[x * kStepLd + y] = y < ts1 ? gload(A + static_cast<int64_t>(t0 + gload(pm + x)) * b + t1 + y) : T(0);
+    sB[x * kStepLd + y] = y < ts1 ? gload(A + static_cast<int64_t>(t0 + x) * b + t1 + y) : T(0);
   }
-  stage_inverses<T>(it, s, sLi, sUi);
+  stage_linv_perm<T>(it, s, sLi);
+  stage_inverses<T>(it, s, static_cast<T*>(nullptr), sUi);
   __syncthreads();
   // L21 fragment (wave >> 1, wave & 1) and U12 fragment (wave >> 1, wave & 1)
   typename MF<T>::acc l21, u12;
@@ -1272,7 +1284,6 @@ __device__ __forceinline__ void step_trailing(const LuItem& it, int t0, int ti, 
   T* sB = sA + 64 * kStepLd;        // [kTile][kStepLdw]: band s (P_s order), columns c0.., then U12
   T* sLi = sB + kTile * kStepLdw;
   T* sUi = sLi + kTile * kStepLd;
-  const int32_t* pm = step_perm(it, s);
   // The block of C (32 x 32 per wavefront) is requested first: its loads are
   // in flight while the strip pieces are formed.
   const int wr = wave >> 1, wc = wave & 1;
@@ -1292,9 +1303,10 @@ __device__ __forceinline__ void step_trailing(const LuItem& it, int t0, int ti, 
   }
   for (int e = tid; e < kTile * 64; e += 256) {
     const int q = e >> 6, y = e & 63;
-    sB[q * kStepLdw + y] = c0 + y < b ? gload(A + static_cast<int64_t>(t0 + gload(pm + q)) * b + c0 + y) : T(0);
+    sB[q * kStepLdw + y] = c0 + y < b ? gload(A + static_cast<int64_t>(t0 + q) * b + c0 + y) : T(0);
   }
-  stage_inverses<T>(it, s, sLi, sUi);
+  stage_linv_perm<T>(it, s, sLi);
+  stage_inverses<T>(it, s, static_cast<T*>(nullptr), sUi);
   __syncthreads();
   // Strip pieces: L21 (64 x 32, fragments 0..7) and U12 (32 x 64, fragments
   // 8..15); wavefront w forms fragments w, w + 4, w + 8, w + 12.
@@ -1392,12 +1404,11 @@ __device__ __forceinline__ void step_strip_cols(const LuItem& it, int t0, int j,
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   T* sB = smem;                   // [kTile][kStepLdw]
   T* sLi = sB + kTile * kStepLdw;
-  const int32_t* pm = step_perm(it, s - 1);
   for (int e = tid; e < kTile * 64; e += 256) {
     const int q = e >> 6, y = e & 63;
-    sB[q * kStepLdw + y] = C0 + y < b ? gload(A + static_cast<int64_t>(tp + gload(pm + q)) * b + C0 + y) : T(0);
+    sB[q * kStepLdw + y] = C0 + y < b ? gload(A + static_cast<int64_t>(tp + q) * b + C0 + y) : T(0);
   }
-  stage_inverses<T>(it, s - 1, sLi, static_cast<T*>(nullptr));
+  stage_linv_perm<T>(it, s - 1, sLi);
   __syncthreads();
 #pragma unroll
   for (int jj = 0; jj < 2; ++jj) {

@@ -278,3 +278,45 @@ def test_reuse_config_n4096_k4_fp64():
     m = workloads.workload_matrix("spd_n4096_k4")
     got = bri.invert_block(gpu(m), 4, 0, 0, reuse=True).cpu().numpy()
     assert rel(got, oracle.invert_block(m, 4, 0, 0)) < 1e-12
+
+
+TILE_EDGE_ORDERS = [16, 31, 32, 33, 63, 64, 65, 95, 96, 97, 160]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tile_lu_edges_single_calls(precision):
+    # Block orders around the 32-column tiles of the tile-pivoting LU: a
+    # single tile (the factorisation alone leaves the inverses of its
+    # diagonal tile), a ragged last tile, and exact multiples; with and
+    # without identity padding (n = 2b - 1).
+    tol = 1e-12 if precision == "f64" else 64 * EPS32 * 2
+    for b in TILE_EDGE_ORDERS:
+        for n in (2 * b, 2 * b - 1):
+            m = workloads.gaussian_dd(n, 3 * n + 1)
+            print(f"case b={b} n={n} {precision}", flush=True)
+            for (i, j) in [(0, 0), (1, 0)]:
+                got = run(m, 2, i, j, precision=precision)
+                assert rel(got, oracle.invert_block(m, 2, i, j)) < tol, (b, n, i, j)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tile_lu_edges_merged_batch(precision):
+    # The same orders in one merged batch: matrices of one tile and of many
+    # share the tile-step launches sized for the largest.
+    tol = 1e-12 if precision == "f64" else 64 * EPS32 * 2
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    mats, ks, iis, jjs = [], [], [], []
+    for t, b in enumerate(TILE_EDGE_ORDERS):
+        for k in (2, 3):
+            n = k * b - (t % 2)
+            mats.append(workloads.gaussian_dd(n, 7 * n + k))
+            ks.append(k)
+            iis.append(t % k)
+            jjs.append((t + 1) % k)
+    info = torch.zeros(len(mats), dtype=torch.int32, device=DEV)
+    print(f"merged tile-edge batch {precision}: {len(mats)} problems", flush=True)
+    outs = bri.invert_block_batched([gpu(m, dtype) for m in mats], ks, iis, jjs, precision=precision, info=info)
+    torch.cuda.synchronize()
+    assert int(info.abs().sum().item()) == 0
+    for m, k, i, j, o in zip(mats, ks, iis, jjs, outs):
+        assert rel(o.double().cpu().numpy(), oracle.invert_block(m, k, i, j)) < tol, (m.shape[0], k, i, j)

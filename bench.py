@@ -164,7 +164,8 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the block recursive inverse runs on a single MI355X "
-              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+              "(its independent subtrees could be spread over GPUs, but no multi-GPU path is built); "
+              "use --gpus 1", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -1637,7 +1637,7 @@ hipError_t launch_gemm_lp(const GemmLaunch& L, int count, int max_m, int max_n, 
   // 64 x 64 tiles of four wavefronts).
   if constexpr (!GEN) {
     const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * count;
-    if (big_tiles >= 128) {
+    if (max_m >= 128 && max_n >= 128 && big_tiles >= 128) {
       if (L.lp == 1)
         launch_lp_shape<1, MODE, GEN, 128, 128, 32, 32>(L, count, max_m, max_n, st);
       else
@@ -1671,17 +1671,23 @@ hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n
   // The generic (element-wise view) instance and the trailing updates of the
   // partial-pivoting LU take 64 x 64 tiles of four 32 x 32 wavefronts.
   // Products with a triangular operand have uneven tiles and take the larger
-  // shapes only with at least two workgroups per compute unit.
+  // shapes only with at least two workgroups per compute unit.  A shape is
+  // used only when the products are at least as large as its tile (the
+  // small levels of the triangular inversion have many 32 x 32 products:
+  // 32 x 32 tiles of four 16 x 16 wavefronts).
   if constexpr (!GEN && MODE != GEMM_LU_TRAILING) {
     const bool tri = L.tri != 0 || MODE == GEMM_TRTRI_STEP1 || MODE == GEMM_TRTRI_STEP2;
     const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 256) * count;
     const int64_t mid_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * count;
-    if (big_tiles >= (tri ? 512 : 192)) {
+    if (max_m >= 128 && max_n >= 256 && big_tiles >= (tri ? 512 : 192)) {
       dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 256), count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 256, 16, 64, 32>), grid, dim3(1024), 0, st, L);
-    } else if (mid_tiles >= (tri ? 512 : 128)) {
+    } else if (max_m >= 128 && max_n >= 128 && mid_tiles >= (tri ? 512 : 128)) {
       dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 128, 16, 32, 32>), grid, dim3(1024), 0, st, L);
+    } else if (max_m <= 32 && max_n <= 32) {
+      dim3 grid(1, count);
+      hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 32, 32, 16, 16, 16>), grid, dim3(256), 0, st, L);
     } else {
       dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 64, 64, 16, 16, 16>), grid, dim3(1024), 0, st, L);

@@ -1665,9 +1665,12 @@ hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n
   // Tile shapes by the number of output tiles the launch has (four
   // wavefronts per SIMD where possible, so MFMA issue continues while other
   // wavefronts wait on LDS or memory):
-  //   large: 128 x 256 tiles, 16 wavefronts of 64 x 32;
-  //   medium: 128 x 128 tiles, 16 wavefronts of 32 x 32;
-  //   small: 64 x 64 tiles, 16 wavefronts of 16 x 16.
+  //   large: 128 x 256 tiles, 16 wavefronts of 64 x 32, K steps of 16;
+  //   medium: 128 x 128 tiles, 16 wavefronts of 32 x 32, K steps of 32;
+  //   small: 64 x 64 tiles, 16 wavefronts of 16 x 16, K steps of 64.
+  // The fewer the output tiles per compute unit, the longer the K step, so
+  // that the operand loads issued one step ahead still cover the memory
+  // latency (a single 1024 x 1024 product has one 64 x 64 tile per unit).
   // The generic (element-wise view) instance and the trailing updates of the
   // partial-pivoting LU take 64 x 64 tiles of four 32 x 32 wavefronts.
   // Products with a triangular operand have uneven tiles and take the larger
@@ -1684,13 +1687,13 @@ hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 256, 16, 64, 32>), grid, dim3(1024), 0, st, L);
     } else if (max_m >= 128 && max_n >= 128 && mid_tiles >= (tri ? 512 : 128)) {
       dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), count);
-      hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 128, 16, 32, 32>), grid, dim3(1024), 0, st, L);
+      hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 128, 32, 32, 32>), grid, dim3(1024), 0, st, L);
     } else if (max_m <= 32 && max_n <= 32) {
       dim3 grid(1, count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 32, 32, 16, 16, 16>), grid, dim3(256), 0, st, L);
     } else {
       dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), count);
-      hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 64, 64, 16, 16, 16>), grid, dim3(1024), 0, st, L);
+      hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 64, 64, 64, 16, 16>), grid, dim3(1024), 0, st, L);
     }
     return hipGetLastError();
   }

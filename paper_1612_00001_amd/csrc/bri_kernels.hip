@@ -290,6 +290,34 @@ __device__ __forceinline__ void heavy_first(const GemmItem& it, int bid, int til
   if (it.B.tri == 2) tn = tiles_n - 1 - tn;  // upper B: columns further right use more of K
 }
 
+// Cin and Sub values of the 16 x (16 FN) output fragments at (r0, c0) in the
+// MFMA accumulator layout, for plain (stored, unpermuted) views; positions
+// outside the product read its last row / column and are never stored.
+template <typename T, int FN>
+__device__ __forceinline__ void epilogue_operands(const GemmItem& it, int r0, int c0, int lane, T (&cv)[FN][4],
+                                                  T (&sv)[FN][4]) {
+  const T* cinp = static_cast<const T*>(it.Cin.p);
+  const T* subp = static_cast<const T*>(it.Sub.p);
+  if (it.has_cin) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = min(r0 + MF<T>::row(lane, v), it.M - 1), c = min(c0 + j * 16 + (lane & 15), it.N - 1);
+        cv[j][v] = gload(cinp + static_cast<int64_t>(r) * it.Cin.ld + c);
+      }
+  }
+  if (it.has_sub) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = min(r0 + MF<T>::row(lane, v), it.M - 1), c = min(c0 + j * 16 + (lane & 15), it.N - 1);
+        sv[j][v] = gload(subp + static_cast<int64_t>(r) * it.Sub.ld + c);
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Batched MFMA GEMM.  One workgroup computes a BM x BN output tile with
 // (BM/WM) x (BN/WN) wavefronts of WM x WN each; K is consumed BK at a time
@@ -410,26 +438,49 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
 
   T* out = static_cast<T*>(it.out);
   const T alpha = static_cast<T>(it.alpha), beta = static_cast<T>(it.beta);
-  const T* cinp = static_cast<const T*>(it.Cin.p);
-  const T* subp = static_cast<const T*>(it.Sub.p);
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < FM; ++i) {
+    // Cin and Sub of this row of fragments are requested together (addresses
+    // clamped into the product, so no load waits on a per-element branch).
+    // The fast instance only receives plain Cin / Sub (gemm_item_is_fast).
+    T cv[FN][4], sv[FN][4];
+    if (!GEN) epilogue_operands<T, FN>(it, m0 + wm * WM + i * 16, n0 + wn * WN, lane, cv, sv);
+    if (GEN) {
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+      for (int j = 0; j < FN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = m0 + wm * WM + i * 16 + MF<T>::row(lane, v);
-        const int c = n0 + wn * WN + j * 16 + (lane & 15);
-        if (r < it.M && c < it.N) {
-          T val = alpha * acc[i][j][v];
-          // The fast instance only receives plain Cin / Sub (gemm_item_is_fast).
-          if (it.has_cin)
-            val += beta * (GEN ? vget<T>(it.Cin, r, c) : gload(cinp + static_cast<int64_t>(r) * it.Cin.ld + c));
-          if (it.has_sub)
-            val -= GEN ? vget<T>(it.Sub, r, c) : gload(subp + static_cast<int64_t>(r) * it.Sub.ld + c);
-          out[static_cast<int64_t>(r) * it.ldo + c] = val;
+        for (int v = 0; v < 4; ++v) {
+          const int r = m0 + wm * WM + i * 16 + MF<T>::row(lane, v);
+          const int c = n0 + wn * WN + j * 16 + (lane & 15);
+          if (r < it.M && c < it.N) {
+            T val = alpha * acc[i][j][v];
+            if (it.has_cin) val += beta * vget<T>(it.Cin, r, c);
+            if (it.has_sub) val -= vget<T>(it.Sub, r, c);
+            out[static_cast<int64_t>(r) * it.ldo + c] = val;
+          }
         }
-      }
+    } else {
+      // Every value of the row first, then the stores (a load-use wait after
+      // a store would also wait for the store).
+      T val[FN][4];
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          val[j][v] = alpha * acc[i][j][v];
+          if (it.has_cin) val[j][v] += beta * cv[j][v];
+          if (it.has_sub) val[j][v] -= sv[j][v];
+        }
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = m0 + wm * WM + i * 16 + MF<T>::row(lane, v);
+          const int c = n0 + wn * WN + j * 16 + (lane & 15);
+          if (r < it.M && c < it.N) gstore(out + static_cast<int64_t>(r) * it.ldo + c, val[j][v]);
+        }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -612,26 +663,38 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lp(GemmLaun
 
   float* out = static_cast<float*>(it.out);
   const float alpha = static_cast<float>(it.alpha), beta = static_cast<float>(it.beta);
-  const float* cinp = static_cast<const float*>(it.Cin.p);
-  const float* subp = static_cast<const float*>(it.Sub.p);
   const float xs = (LP == 1) ? (1.0f / 2048.0f) : 1.0f;
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < FM; ++i) {
+    float cv[FN][4], sv[FN][4];
+    if (!GEN) epilogue_operands<float, FN>(it, m0 + wm * WM + i * 16, n0 + wn * WN, lane, cv, sv);
+    float val[FN][4];
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + v;
+        const int r = m0 + wm * WM + i * 16 + MF<float>::row(lane, v);
         const int c = n0 + wn * WN + j * 16 + (lane & 15);
-        if (r < it.M && c < it.N) {
-          float val = alpha * (acc[i][j][v] + accx[i][j][v] * xs);
-          if (it.has_cin)
-            val += beta * (GEN ? vget<float>(it.Cin, r, c) : gload(cinp + static_cast<int64_t>(r) * it.Cin.ld + c));
-          if (it.has_sub)
-            val -= GEN ? vget<float>(it.Sub, r, c) : gload(subp + static_cast<int64_t>(r) * it.Sub.ld + c);
-          out[static_cast<int64_t>(r) * it.ldo + c] = val;
+        val[j][v] = alpha * (acc[i][j][v] + accx[i][j][v] * xs);
+        if (GEN) {
+          if (r < it.M && c < it.N) {
+            if (it.has_cin) val[j][v] += beta * vget<float>(it.Cin, r, c);
+            if (it.has_sub) val[j][v] -= vget<float>(it.Sub, r, c);
+          }
+        } else {
+          if (it.has_cin) val[j][v] += beta * cv[j][v];
+          if (it.has_sub) val[j][v] -= sv[j][v];
         }
       }
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wm * WM + i * 16 + MF<float>::row(lane, v);
+        const int c = n0 + wn * WN + j * 16 + (lane & 15);
+        if (r < it.M && c < it.N) gstore(out + static_cast<int64_t>(r) * it.ldo + c, val[j][v]);
+      }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -30,6 +30,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   std::vector<int> nfast;        // explicit GEMM steps: items taking the fast kernel instance
+  std::vector<int> ndirect;      // of those, the leading items that qualify for the direct-to-LDS instance
   size_t slot_bytes = 0;
   size_t slots_off = 0, perm_off = 0, swap_off = 0, aux_off = 0, aux_bytes = 0, info_off = 0, desc_off = 0;
   size_t desc_bytes = 0;
@@ -260,19 +261,24 @@ GemmItem gemm_base(const Ctx& c) {
 }
 
 // Work descriptors of one plan step for context c, appended to the vectors
-// (product items split into those the fast kernel instance takes and the rest).
+// (product items split into those the direct-to-LDS instance can take, the
+// other ones the fast instance takes, and the rest).
 struct StepItems {
   std::vector<LoadItem> loads;
   std::vector<LuItem> lus;
-  std::vector<GemmItem> fast, slow;
+  std::vector<GemmItem> direct, fast, slow;
   void clear() {
     loads.clear();
     lus.clear();
+    direct.clear();
     fast.clear();
     slow.clear();
   }
-  size_t count() const { return loads.size() + lus.size() + fast.size() + slow.size(); }
-  // Writes the items to dst (fast products first); returns the bytes written.
+  size_t count() const { return loads.size() + lus.size() + direct.size() + fast.size() + slow.size(); }
+  int nfast() const { return static_cast<int>(direct.size() + fast.size()); }
+  int ndirect() const { return static_cast<int>(direct.size()); }
+  // Writes the items to dst (direct, then fast products first); returns the
+  // bytes written.
   size_t write(char* dst) const {
     size_t off = 0;
     auto put = [&](const void* src, size_t bytes) {
@@ -281,6 +287,7 @@ struct StepItems {
     };
     put(loads.data(), loads.size() * sizeof(LoadItem));
     put(lus.data(), lus.size() * sizeof(LuItem));
+    put(direct.data(), direct.size() * sizeof(GemmItem));
     put(fast.data(), fast.size() * sizeof(GemmItem));
     put(slow.data(), slow.size() * sizeof(GemmItem));
     return off;
@@ -341,21 +348,26 @@ void describe_step(const Ctx& c, const Step& s, StepItems& out) {
           }
           g.alpha = (s.kind == ST_GEMM_ACC) ? 1.0 : -1.0;
         }
-        (gemm_item_is_fast(g) ? out.fast : out.slow).push_back(g);
+        if (!gemm_item_is_fast(g))
+          out.slow.push_back(g);
+        else
+          (gemm_item_is_direct(g, c.elem) ? out.direct : out.fast).push_back(g);
         break;
       }
     }
   }
 }
 
-void build_descriptors(const Ctx& c, const Plan& p, char* host, std::vector<int>& nfast) {
+void build_descriptors(const Ctx& c, const Plan& p, char* host, std::vector<int>& nfast, std::vector<int>& ndirect) {
   nfast.assign(p.steps.size(), 0);
+  ndirect.assign(p.steps.size(), 0);
   StepItems items;
   for (size_t si = 0; si < p.steps.size(); ++si) {
     items.clear();
     describe_step(c, p.steps[si], items);
     items.write(host + c.lay->step_off[si]);
-    nfast[si] = static_cast<int>(items.fast.size());
+    nfast[si] = items.nfast();
+    ndirect[si] = items.ndirect();
   }
 }
 
@@ -420,6 +432,7 @@ struct ExecStep {
   StepKind kind;
   int count;
   int nfast;
+  int ndirect;
   const void* desc;
   const Step* step;
   double flops;  // algorithmic flops of all items (profile record)
@@ -466,6 +479,7 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lp,
         L.items = s.desc;
         L.count = s.count;
         L.w = s.nfast;
+        L.ndl = s.ndirect;
         L.lp = lp;
         L.tri = (s.kind == ST_TRMM_L || s.kind == ST_TRMM_U) ? 1 : 0;
         e = launch_gemm<T>(L, bmax, bmax, st);
@@ -489,7 +503,8 @@ int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
   ex.reserve(p.steps.size());
   for (size_t si = 0; si < p.steps.size(); ++si) {
     const Step& s = p.steps[si];
-    ex.push_back(ExecStep{s.kind, static_cast<int>(s.items.size()), c.lay->nfast[si], dbase + c.lay->step_off[si], &s,
+    ex.push_back(ExecStep{s.kind, static_cast<int>(s.items.size()), c.lay->nfast[si], c.lay->ndirect[si],
+                          dbase + c.lay->step_off[si], &s,
                           step_flops(s, c.b)});
   }
   return run_exec<T>(ex, c.b, c.pivoting, c.lp, st);
@@ -507,7 +522,7 @@ int execute(CachedPlan& cp, Ctx& c, hipStream_t st, bool clear_info) {
     if (hipEventSynchronize(cp.uploaded) != hipSuccess) return BRI_ERR_HIP;
   }
   try {
-    build_descriptors(c, cp.plan, static_cast<char*>(cp.host), cp.layout.nfast);
+    build_descriptors(c, cp.plan, static_cast<char*>(cp.host), cp.layout.nfast, cp.layout.ndirect);
   } catch (const std::exception&) {
     return BRI_ERR_UNSUPPORTED;
   }
@@ -627,9 +642,8 @@ MergedExec merge_write(const std::vector<const Plan*>& plans, const std::vector<
         flops += step_flops(st, ctx[t].b);
       }
       items.write(host + m.step_off[g][si]);
-      ex.groups.back().push_back(ExecStep{p0.steps[si].kind, static_cast<int>(items.count()),
-                                          static_cast<int>(items.fast.size()), dev + m.step_off[g][si],
-                                          &p0.steps[si], flops});
+      ex.groups.back().push_back(ExecStep{p0.steps[si].kind, static_cast<int>(items.count()), items.nfast(),
+                                          items.ndirect(), dev + m.step_off[g][si], &p0.steps[si], flops});
     }
   }
   return ex;

@@ -86,6 +86,8 @@ struct GemmLaunch {
   int32_t npairs;       // TRTRI level: block pairs per matrix
   int32_t lp;           // float storage only: 0 FP32 MFMA, 1 FP16 split, 2 BF16 split
   int32_t tri;          // items have a triangular operand (uneven K per output tile)
+  int32_t ndl;          // GEMM_EXPLICIT: the first ndl fast items also qualify for
+                        // the direct-to-LDS FP64 instance (gemm_item_is_direct)
 };
 
 constexpr int kMaxBlock = 4096;  // == BRI_MAX_BLOCK
@@ -102,6 +104,22 @@ inline bool view_fast(const DView& v, int xlim, int ylim) {
 // Plain: stored, untransposed, unpermuted, untriangular and covering M x N.
 inline bool view_plain(const DView& v, int xlim, int ylim) {
   return v.p != nullptr && !v.trans && !v.rowperm && v.tri == 0 && xlim <= v.rows && ylim <= v.cols;
+}
+// Direct-to-LDS operand: stored, untransposed, covering the product, rows
+// starting on 16-byte boundaries (the operand tiles move to LDS in 16-byte
+// pieces, two FP64 elements each).
+inline bool view_direct(const DView& v, int xlim, int ylim, int elem) {
+  return v.p != nullptr && !v.trans && xlim <= v.rows && ylim <= v.cols &&
+         reinterpret_cast<uintptr_t>(v.p) % 16 == 0 && (v.ld * elem) % 16 == 0;
+}
+// An item of the direct-to-LDS FP64 instance: A and B direct (a row
+// permutation only on B), even N and K (no 16-byte piece crosses the edge of
+// an operand), plain Cin / Sub.
+inline bool gemm_item_is_direct(const GemmItem& g, int elem) {
+  return elem == 8 && g.M > 0 && g.N > 0 && g.K > 0 && g.N % 2 == 0 && g.K % 2 == 0 &&
+         view_direct(g.A, g.M, g.K, elem) && g.A.rowperm == nullptr && view_direct(g.B, g.K, g.N, elem) &&
+         (g.B.rowperm == nullptr || g.K <= kMaxBlock) &&
+         (!g.has_cin || view_plain(g.Cin, g.M, g.N)) && (!g.has_sub || view_plain(g.Sub, g.M, g.N));
 }
 inline bool gemm_item_is_fast(const GemmItem& g) {
   return view_fast(g.A, g.M, g.K) && view_fast(g.B, g.K, g.N) && (!g.has_cin || view_plain(g.Cin, g.M, g.N)) &&

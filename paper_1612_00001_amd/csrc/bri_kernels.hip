@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 #include <utility>
 
 #include "bri_internal.h"
@@ -341,7 +342,8 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
   GemmItem it;
   int item, tile;
   gemm_workgroup(item, tile);
-  if (!gemm_item<T, MODE>(L, item + (GEN ? L.j : 0), it)) return;
+  // Explicit items: this launch takes items [L.j, L.j + gridDim.y).
+  if (!gemm_item<T, MODE>(L, item + (MODE == GEMM_EXPLICIT ? L.j : 0), it)) return;
   const int tiles_n = (it.N + BN - 1) / BN;
   const int tiles_m = (it.M + BM - 1) / BM;
   if (tile >= tiles_m * tiles_n) return;
@@ -480,6 +482,235 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
           if (r < it.M && c < it.N) gstore(out + static_cast<int64_t>(r) * it.ldo + c, val[j][v]);
         }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 product with direct-to-LDS operand loads (items of gemm_item_is_direct:
+// stored, untransposed A and B, even N and K, 16-byte aligned rows, plain Cin
+// / Sub).  Each thread moves 16-byte pieces of the operand tiles straight
+// from memory into LDS (global_load_lds_dwordx4), three K steps of 16 in
+// flight, so no register staging sits between the loads and the MFMAs and a
+// K step waits only for the loads issued two steps earlier.
+//   LDS tiles: A row-major (BM rows of 16), its 16-byte pieces swizzled by
+//   piece ^ (row & 7) so that the fragment reads of 8 consecutive rows hit
+//   distinct banks; B row-major (16 rows of BN).
+//   MFMA K slots: in k-step s of a 16-deep K step, lane group g = lane / 16
+//   supplies k = 4 g + s (A and B alike), so every lane reads its four A
+//   values as two 16-byte pieces.
+// Triangular operands, the last partial K step and the row permutation of B
+// are handled in the loads and in a masked variant of the K step that runs
+// only where a mask applies (uniform per K step).  Out-of-range rows and
+// columns load clamped addresses and feed only outputs that are not stored.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// s_waitcnt with vmcnt = N, expcnt and lgkmcnt left at their maxima.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 16, "vmcnt field");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmLaunch L) {
+  constexpr int BK = 16;
+  constexpr int NWN = BN / WN, NT = (BM / WM) * NWN * 64, FM = WM / 16, FN = WN / 16;
+  constexpr int AC = BM * BK / 2, BC = BK * BN / 2;  // 16-byte pieces per K step
+  constexpr int AI = AC / NT, BI = BC / NT;           // pieces per thread per K step
+  static_assert(AI * NT == AC && BI * NT == BC && AI >= 1 && BI >= 1, "tile/thread mismatch");
+  static_assert(AI + BI < 16, "outstanding loads per K step must fit the vmcnt field");
+  static_assert((BM * BK) % NT == 0 && (BK * BN) % NT == 0, "masking covers the tiles evenly");
+  // One array per buffer: the compiler then tells the loads in flight into
+  // one buffer from the reads of another and inserts no wait for them.
+  __shared__ __attribute__((aligned(16))) double sA0[BM * BK], sA1[BM * BK], sA2[BM * BK];
+  __shared__ __attribute__((aligned(16))) double sB0[BK * BN], sB1[BK * BN], sB2[BK * BN];
+  __shared__ int16_t s_perm[kMaxBlock];
+
+  GemmItem it;
+  int item, tile;
+  gemm_workgroup(item, tile);
+  if (!gemm_item<double, GEMM_EXPLICIT>(L, item, it)) return;
+  const int tiles_n = (it.N + BN - 1) / BN;
+  const int tiles_m = (it.M + BM - 1) / BM;
+  if (tile >= tiles_m * tiles_n) return;
+  int tm, tn;
+  heavy_first(it, tile, tiles_m, tiles_n, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  int kb = 0, ke = it.K;
+  if (it.A.tri == 1) ke = min(ke, m0 + BM);
+  if (it.A.tri == 2) kb = max(kb, m0);
+  if (it.B.tri == 1) kb = max(kb, n0);
+  if (it.B.tri == 2) ke = min(ke, n0 + BN);
+  kb = (kb / BK) * BK;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / NWN, wn = wave % NWN;
+  const int K = it.K;
+  const bool perm = it.B.rowperm != nullptr;
+  if (perm) {
+    for (int e = tid; e < K; e += NT) s_perm[e] = static_cast<int16_t>(it.B.rowperm[e]);
+    __syncthreads();
+  }
+
+  typename MF<double>::acc acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.0;
+
+  const int nk = kb < ke ? (ke - kb + BK - 1) / BK : 0;
+  if (nk > 0) {
+    const double* Ap = static_cast<const double*>(it.A.p);
+    const double* Bp = static_cast<const double*>(it.B.p);
+    const int64_t lda = it.A.ld, ldb = it.B.ld;
+    // Loads of K step t into (dA, dB); steps past the last repeat the last
+    // one (into a buffer no later step reads), so every step issues the same
+    // number of loads.  This thread's pieces (recomputed here rather than
+    // held in registers): A piece q is tile row r (clamped into the product)
+    // at K offset 2 ((P & 7) ^ (r & 7)); B piece q is row P / (BN / 2) of the
+    // step, columns from 2 (P % (BN / 2)) (clamped: N is even).
+    auto issue = [&](int t, double* dA, double* dB) {
+      const int k0 = kb + min(t, nk - 1) * BK;
+#pragma unroll
+      for (int q = 0; q < AI; ++q) {
+        const int P = q * NT + tid, r = P >> 3;
+        const int64_t row = static_cast<int64_t>(min(m0 + r, it.M - 1)) * lda;
+        const int col = min(k0 + 2 * ((P & 7) ^ (r & 7)), K - 2);
+        __builtin_amdgcn_global_load_lds((const void*)(Ap + row + col), (lds_void_t*)(dA + (q * NT + wave * 64) * 2),
+                                         16, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < BI; ++q) {
+        const int P = q * NT + tid;
+        int kr = min(k0 + P / (BN / 2), K - 1);
+        if (perm) kr = s_perm[kr];
+        const int col = min(n0 + 2 * (P % (BN / 2)), it.N - 2);
+        __builtin_amdgcn_global_load_lds((const void*)(Bp + kr * ldb + col), (lds_void_t*)(dB + (q * NT + wave * 64) * 2),
+                                         16, 0, 0);
+      }
+    };
+
+    const int kq = lane >> 4, li = lane & 15;
+    // One K step from LDS, in two halves: k slots 2h and 2h + 1 come from one
+    // 16-byte piece of A.
+    // Lane parts of the fragment addresses (elements): A piece (m, kc) of
+    // row m = wm WM + li (+ 16 i) sits at 2 (8 m + (kc ^ (m & 7))), and
+    // m & 7 = li & 7; B element (4 kq + s, wn WN + li (+ 16 j)).
+    const int a_lane = 16 * (wm * WM + li), a_x = li & 7;
+    const int b_lane = 4 * kq * BN + wn * WN + li;
+    auto compute = [&](const double* a_s, const double* b_s) {
+      // Opaque copies: the buffer addresses are formed here in every step
+      // instead of being held, three buffers' worth, across the loop.
+      int al = a_lane, bl = b_lane, ax = a_x;
+      asm volatile("" : "+v"(al), "+v"(bl), "+v"(ax));
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double av[FM][2], bv[FN][2];
+        const int apiece = 2 * ((2 * kq + h) ^ ax);
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          const double2 v = *reinterpret_cast<const double2*>(a_s + al + 256 * i + apiece);
+          av[i][0] = v.x;
+          av[i][1] = v.y;
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int u = 0; u < 2; ++u) bv[j][u] = b_s[bl + (2 * h + u) * BN + j * 16];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[i][j] = MF<double>::mma(av[i][u], bv[j][u], acc[i][j]);
+      }
+    };
+    // Whether the tiles of K step k0 need masking (uniform): a part past K,
+    // or a triangular operand whose diagonal crosses the tile.
+    auto needs_mask = [&](int k0) {
+      return k0 + BK > K || (it.A.tri == 1 && m0 <= k0 + BK - 1) || (it.A.tri == 2 && m0 + BM - 1 > k0) ||
+             (it.B.tri == 1 && k0 <= n0 + BN - 1) || (it.B.tri == 2 && k0 + BK - 1 > n0);
+    };
+    // Masks the landed tiles of K step k0 in place: zero past K, and the
+    // triangular forms (unit lower: 1 on, 0 above the diagonal; upper: 0
+    // below it) in logical coordinates.
+    auto mask_tiles = [&](double* a_s, double* b_s, int k0) {
+#pragma unroll
+      for (int u = 0; u < BM * BK / NT; ++u) {
+        const int e = tid + u * NT, r = e >> 4, kl = e & 15, x = m0 + r, k = k0 + kl;
+        double* p = a_s + r * 16 + (((kl >> 1) ^ (r & 7)) << 1) + (kl & 1);
+        double v = k < K ? *p : 0.0;
+        if (it.A.tri == 1) v = x > k ? v : (x == k ? 1.0 : 0.0);
+        if (it.A.tri == 2) v = x <= k ? v : 0.0;
+        *p = v;
+      }
+#pragma unroll
+      for (int u = 0; u < BK * BN / NT; ++u) {
+        const int e = tid + u * NT, kl = e / BN, y = n0 + e % BN, k = k0 + kl;
+        double v = k < K ? b_s[e] : 0.0;
+        if (it.B.tri == 1) v = k > y ? v : (k == y ? 1.0 : 0.0);
+        if (it.B.tri == 2) v = k <= y ? v : 0.0;
+        b_s[e] = v;
+      }
+    };
+    // Step t: once at most the loads of step t + 1 are outstanding, step t
+    // has landed for this thread; the barrier makes that true for every
+    // thread and ends all reads of step t - 1's buffer, which then receives
+    // step t + 2.
+    // The loop runs a multiple of three steps; steps past the last only wait
+    // and issue (their loads repeat the last step), so that every step of the
+    // unrolled body has the same loads in flight.
+    auto step = [&](int t, double* ra, double* rb, double* wa, double* wb) {
+      wait_vmcnt<AI + BI>();
+      __builtin_amdgcn_s_barrier();
+      issue(t + 2, wa, wb);
+      if (t < nk) {
+        const int k0 = kb + t * BK;
+        if (needs_mask(k0)) {
+          mask_tiles(ra, rb, k0);
+          __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this thread's LDS writes done
+          __builtin_amdgcn_s_barrier();
+        }
+        compute(ra, rb);
+      }
+    };
+    issue(0, sA0, sB0);
+    issue(1, sA1, sB1);
+    for (int t = 0; t < nk; t += 3) {
+      step(t, sA0, sB0, sA2, sB2);
+      step(t + 1, sA1, sB1, sA0, sB0);
+      step(t + 2, sA2, sB2, sA1, sB1);
+    }
+    wait_vmcnt<0>();  // no load into LDS may be in flight when the workgroup ends
+  }
+
+  double* out = static_cast<double*>(it.out);
+  const double alpha = it.alpha, beta = it.beta;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    double cv[FN][4], sv[FN][4];
+    epilogue_operands<double, FN>(it, m0 + wm * WM + i * 16, n0 + wn * WN, lane, cv, sv);
+    double val[FN][4];
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        val[j][v] = alpha * acc[i][j][v];
+        if (it.has_cin) val[j][v] += beta * cv[j][v];
+        if (it.has_sub) val[j][v] -= sv[j][v];
+      }
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wm * WM + i * 16 + MF<double>::row(lane, v);
+        const int c = n0 + wn * WN + j * 16 + (lane & 15);
+        if (r < it.M && c < it.N) gstore(out + static_cast<int64_t>(r) * it.ldo + c, val[j][v]);
+      }
   }
 }
 
@@ -1719,6 +1950,18 @@ hipError_t launch_gemm_lp(const GemmLaunch& L, int count, int max_m, int max_n, 
   return hipGetLastError();
 }
 
+// Tile shape of a product launch (see launch_gemm_mode).
+constexpr int kTierLarge = 0, kTierMedium = 1, kTierTiny = 2, kTierSmall = 3;
+inline int gemm_tier(const GemmLaunch& L, int mode, int count, int max_m, int max_n) {
+  const bool tri = L.tri != 0 || mode == GEMM_TRTRI_STEP1 || mode == GEMM_TRTRI_STEP2;
+  const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 256) * count;
+  const int64_t mid_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * count;
+  if (max_m >= 128 && max_n >= 256 && big_tiles >= (tri ? 512 : 192)) return kTierLarge;
+  if (max_m >= 128 && max_n >= 128 && mid_tiles >= (tri ? 512 : 128)) return kTierMedium;
+  if (max_m <= 32 && max_n <= 32) return kTierTiny;
+  return kTierSmall;
+}
+
 template <typename T, int MODE, bool GEN>
 hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n, hipStream_t st) {
   if (count <= 0) return hipSuccess;
@@ -1742,16 +1985,14 @@ hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n
   // small levels of the triangular inversion have many 32 x 32 products:
   // 32 x 32 tiles of four 16 x 16 wavefronts).
   if constexpr (!GEN && MODE != GEMM_LU_TRAILING) {
-    const bool tri = L.tri != 0 || MODE == GEMM_TRTRI_STEP1 || MODE == GEMM_TRTRI_STEP2;
-    const int64_t big_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 256) * count;
-    const int64_t mid_tiles = static_cast<int64_t>(cdiv(max_m, 128)) * cdiv(max_n, 128) * count;
-    if (max_m >= 128 && max_n >= 256 && big_tiles >= (tri ? 512 : 192)) {
+    const int tier = gemm_tier(L, MODE, count, max_m, max_n);
+    if (tier == kTierLarge) {
       dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 256), count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 256, 16, 64, 32>), grid, dim3(1024), 0, st, L);
-    } else if (max_m >= 128 && max_n >= 128 && mid_tiles >= (tri ? 512 : 128)) {
+    } else if (tier == kTierMedium) {
       dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 128, 128, 32, 32, 32>), grid, dim3(1024), 0, st, L);
-    } else if (max_m <= 32 && max_n <= 32) {
+    } else if (tier == kTierTiny) {
       dim3 grid(1, count);
       hipLaunchKernelGGL((k_gemm<T, MODE, GEN, 32, 32, 16, 16, 16>), grid, dim3(256), 0, st, L);
     } else {
@@ -1771,10 +2012,30 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
   switch (L.mode) {
     case GEMM_EXPLICIT: {
       // items [0, L.w) take the fast instance, [L.w, L.count) the generic one
-      // (GemmLaunch::w carries the split; the generic instance offsets its
-      // item index by GemmLaunch::j = L.w).
+      // (GemmLaunch::w carries the split; a launch takes items from
+      // GemmLaunch::j on).  With the two larger tile shapes, FP64 fast items
+      // take the direct-to-LDS instance instead when all of them qualify
+      // (L.ndl == L.w).
       const int nfast = L.w;
-      hipError_t e = launch_gemm_mode<T, GEMM_EXPLICIT, false>(L, nfast, max_m, max_n, st);
+      int ndl = 0;
+      if constexpr (sizeof(T) == 8) {
+        // Only when every fast item qualifies: a second launch for the rest
+        // would cost more than the direct instance gains (merged batches).
+        const int tier = gemm_tier(L, GEMM_EXPLICIT, nfast, max_m, max_n);
+        if (nfast > 0 && L.ndl == nfast && (tier == kTierLarge || tier == kTierMedium)) {
+          // 128 x 128 tiles of 16 wavefronts of 32 x 32 for both shapes: a
+          // 128 x 256 tile would need more than the 128 registers a thread of
+          // a 1024-thread workgroup has, and spill.
+          ndl = nfast;
+          dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
+          hipLaunchKernelGGL((k_gemm_dl<128, 128, 32, 32>), grid, dim3(1024), 0, st, L);
+          hipError_t e = hipGetLastError();
+          if (e != hipSuccess) return e;
+        }
+      }
+      GemmLaunch F = L;
+      F.j = ndl;
+      hipError_t e = launch_gemm_mode<T, GEMM_EXPLICIT, false>(F, nfast - ndl, max_m, max_n, st);
       if (e != hipSuccess) return e;
       GemmLaunch G = L;
       G.j = nfast;

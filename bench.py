@@ -53,15 +53,18 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1612_00001_amd", "csrc", "bri_kernels.
 
 def gemm_source_digest():
     """sha256 over the source of the product kernel: its operand loaders and
-    kernel body (from the "Operand tiles." section to the low-precision
-    kernel) and its tile-shape selection (launch_gemm_mode)."""
+    kernel bodies, register-staged and direct-to-LDS (from the "Operand
+    tiles." section to the low-precision kernel) and its tile-shape selection
+    (launch_gemm_mode, launch_gemm)."""
     import hashlib
     text = open(KERNEL_SOURCE).read()
     a = text.index("// Operand tiles.")
     e = text.index("// Low-precision products")
     c = text.index("hipError_t launch_gemm_mode(")
     d = text.index("\n}\n", c)
-    return hashlib.sha256((text[a:e] + text[c:d]).encode()).hexdigest()
+    f = text.index("hipError_t launch_gemm(const GemmLaunch& L")
+    g = text.index("\n}\n", f)
+    return hashlib.sha256((text[a:e] + text[c:d] + text[f:g]).encode()).hexdigest()
 
 
 def counted_traffic():
@@ -240,7 +243,9 @@ def main() -> int:
     p_la = sum(prof[t][1] for t in prod_kinds if t in prof)
     achieved = p_fl / (p_ms * 1e-3) / 1e12 if p_ms > 0 else 0.0
     roofline = {
-        "kernel": "k_gemm<double, GEMM_EXPLICIT> (Schur and triangular products; 128x256, 128x128 or 64x64 tiles of 16 wavefronts)",
+        "kernel": "explicit-item FP64 products (Schur and triangular): k_gemm_dl (direct-to-LDS loads, 128x128 tiles) "
+                  "where every item of a step has stored, aligned operands, else k_gemm<double, GEMM_EXPLICIT> "
+                  "(128x256, 128x128 or 64x64 tiles)",
         "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
         "frac": achieved / PEAK_TFLOPS["f64"], "traffic": counted_traffic(),
         "launches_per_step": p_la / args.steps, "avg_launch_ms": (p_ms / p_la) if p_la else None,

@@ -489,9 +489,9 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
 // FP64 product with direct-to-LDS operand loads (items of gemm_item_is_direct:
 // stored, untransposed A and B, even N and K, 16-byte aligned rows, plain Cin
 // / Sub).  Each thread moves 16-byte pieces of the operand tiles straight
-// from memory into LDS (global_load_lds_dwordx4), three K steps of 16 in
-// flight, so no register staging sits between the loads and the MFMAs and a
-// K step waits only for the loads issued two steps earlier.
+// from memory into LDS (global_load_lds_dwordx4) into three buffers: the
+// loads of K step t + 2 are issued before the MFMAs of step t, and no
+// register staging sits between the loads and the MFMAs.
 //   LDS tiles: A row-major (BM rows of 16), its 16-byte pieces swizzled by
 //   piece ^ (row & 7) so that the fragment reads of 8 consecutive rows hit
 //   distinct banks; B row-major (16 rows of BN).
@@ -510,6 +510,18 @@ template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
   static_assert(N >= 0 && N < 16, "vmcnt field");
   __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
+// Workgroup barrier that the compiler may not move LDS accesses across (the
+// s_waitcnt and s_barrier builtins are no memory barriers to it, and a read
+// hoisted above the barrier would see pieces other wavefronts have not
+// loaded yet), without the memory fence of __syncthreads, which would wait
+// for every load in flight.  WAIT is the s_waitcnt immediate issued first.
+template <int WAIT>
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(WAIT);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
 }
 
 template <int BM, int BN, int WM, int WN>
@@ -657,23 +669,24 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmLaun
         b_s[e] = v;
       }
     };
-    // Step t: once at most the loads of step t + 1 are outstanding, step t
-    // has landed for this thread; the barrier makes that true for every
-    // thread and ends all reads of step t - 1's buffer, which then receives
-    // step t + 2.
+    // Step t: after the wait, step t has landed for this thread; the barrier
+    // makes that true for every thread and ends all reads of step t - 1's
+    // buffer, which then receives step t + 2.
     // The loop runs a multiple of three steps; steps past the last only wait
     // and issue (their loads repeat the last step), so that every step of the
     // unrolled body has the same loads in flight.
     auto step = [&](int t, double* ra, double* rb, double* wa, double* wb) {
-      wait_vmcnt<AI + BI>();
-      __builtin_amdgcn_s_barrier();
+      // vmcnt(0): loads into LDS were seen to complete out of order (with
+      // two workgroups per compute unit, waiting for all but the last
+      // step's loads let a wavefront read pieces of step t not yet written),
+      // so the wait covers steps t and t + 1.
+      lds_barrier<0x0F70>();
       issue(t + 2, wa, wb);
       if (t < nk) {
         const int k0 = kb + t * BK;
         if (needs_mask(k0)) {
           mask_tiles(ra, rb, k0);
-          __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this thread's LDS writes done
-          __builtin_amdgcn_s_barrier();
+          lds_barrier<0xC07F>();  // lgkmcnt(0): this thread's LDS writes done
         }
         compute(ra, rb);
       }

@@ -2026,7 +2026,7 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
     case GEMM_EXPLICIT: {
       // items [0, L.w) take the fast instance, [L.w, L.count) the generic one
       // (GemmLaunch::w carries the split; a launch takes items from
-      // GemmLaunch::j on).  With the two larger tile shapes, FP64 fast items
+      // GemmLaunch::j on).  Except for the 32 x 32 shape, FP64 fast items
       // take the direct-to-LDS instance instead when all of them qualify
       // (L.ndl == L.w).
       const int nfast = L.w;
@@ -2035,13 +2035,19 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
         // Only when every fast item qualifies: a second launch for the rest
         // would cost more than the direct instance gains (merged batches).
         const int tier = gemm_tier(L, GEMM_EXPLICIT, nfast, max_m, max_n);
-        if (nfast > 0 && L.ndl == nfast && (tier == kTierLarge || tier == kTierMedium)) {
-          // 128 x 128 tiles of 16 wavefronts of 32 x 32 for both shapes: a
-          // 128 x 256 tile would need more than the 128 registers a thread of
-          // a 1024-thread workgroup has, and spill.
+        if (nfast > 0 && L.ndl == nfast && tier != kTierTiny) {
+          // 128 x 128 tiles of 16 wavefronts of 32 x 32 for the two larger
+          // shapes (a 128 x 256 tile would need more than the 128 registers a
+          // thread of a 1024-thread workgroup has, and spill); 64 x 64 tiles
+          // of 4 wavefronts of 32 x 32 for the small one.
           ndl = nfast;
-          dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
-          hipLaunchKernelGGL((k_gemm_dl<128, 128, 32, 32>), grid, dim3(1024), 0, st, L);
+          if (tier == kTierSmall) {
+            dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), ndl);
+            hipLaunchKernelGGL((k_gemm_dl<64, 64, 32, 32>), grid, dim3(256), 0, st, L);
+          } else {
+            dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
+            hipLaunchKernelGGL((k_gemm_dl<128, 128, 32, 32>), grid, dim3(1024), 0, st, L);
+          }
           hipError_t e = hipGetLastError();
           if (e != hipSuccess) return e;
         }

@@ -113,11 +113,13 @@ inline bool view_direct(const DView& v, int xlim, int ylim, int elem) {
          reinterpret_cast<uintptr_t>(v.p) % 16 == 0 && (v.ld * elem) % 16 == 0;
 }
 // An item of the direct-to-LDS FP64 instance: A and B direct (a row
-// permutation only on B), even N and K (no 16-byte piece crosses the edge of
-// an operand), plain Cin / Sub.
+// permutation only on B, a triangular form only on A, the forms the
+// explicit steps produce and the tests cover), even N and K (no 16-byte
+// piece crosses the edge of an operand), plain Cin / Sub.
 inline bool gemm_item_is_direct(const GemmItem& g, int elem) {
   return elem == 8 && g.M > 0 && g.N > 0 && g.K > 0 && g.N % 2 == 0 && g.K % 2 == 0 &&
          view_direct(g.A, g.M, g.K, elem) && g.A.rowperm == nullptr && view_direct(g.B, g.K, g.N, elem) &&
+         g.B.tri == 0 &&
          (g.B.rowperm == nullptr || g.K <= kMaxBlock) &&
          (!g.has_cin || view_plain(g.Cin, g.M, g.N)) && (!g.has_sub || view_plain(g.Sub, g.M, g.N));
 }

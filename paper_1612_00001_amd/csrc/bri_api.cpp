@@ -958,6 +958,9 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
   if (!host) return BRI_ERR_HIP;
   std::memcpy(host + (mb.items_off - d0), ri.data(), count * sizeof(RefItem));
   std::memcpy(host + (mb.gemm_off - d0), gi.data(), count * sizeof(GemmItem));
+  int ndl_resid = count;
+  for (const GemmItem& g : gi)
+    if (!gemm_item_is_direct(g, 8)) ndl_resid = 0;
   std::memcpy(host + (mb.load_off - d0), li.data(), count * sizeof(LoadItem));
   MergedExec ecol, esol;
   try {
@@ -1012,7 +1015,8 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
     L.elem = 8;
     L.items = ws + mb.gemm_off;
     L.count = count;
-    L.w = count;  // stored dense operands
+    L.w = count;        // stored dense operands
+    L.ndl = ndl_resid;  // all of them for the direct-to-LDS instance when they qualify
     if (launch_gemm<double>(L, max_n, max_b, st) != hipSuccess) return BRI_ERR_HIP;
     if (launch_resid_fix(d_items, count, max_fix, st) != hipSuccess) return BRI_ERR_HIP;
     if (launch_absmax(d_items, count, 1, max_kb_b, st) != hipSuccess) return BRI_ERR_HIP;

@@ -514,8 +514,8 @@ __device__ __forceinline__ void wait_vmcnt() {
 // Workgroup barrier that the compiler may not move LDS accesses across (the
 // s_waitcnt and s_barrier builtins are no memory barriers to it, and a read
 // hoisted above the barrier would see pieces other wavefronts have not
-// loaded yet), without the memory fence of __syncthreads, which would wait
-// for every load in flight.  WAIT is the s_waitcnt immediate issued first.
+// loaded yet), without the memory fence of __syncthreads.  WAIT is the
+// s_waitcnt immediate issued first.
 template <int WAIT>
 __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
@@ -679,8 +679,12 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmLaun
       // vmcnt(0): loads into LDS were seen to complete out of order (with
       // two workgroups per compute unit, waiting for all but the last
       // step's loads let a wavefront read pieces of step t not yet written),
-      // so the wait covers steps t and t + 1.
-      lds_barrier<0x0F70>();
+      // so the wait covers steps t and t + 1.  lgkmcnt(0): this wavefront's
+      // reads of step t - 1's buffer are complete before the barrier (the
+      // compiler places the MFMAs that consume them, and their waits, after
+      // it), since once past it other wavefronts load step t + 2 into that
+      // buffer.
+      lds_barrier<0x0070>();
       issue(t + 2, wa, wb);
       if (t < nk) {
         const int k0 = kb + t * BK;

@@ -280,6 +280,22 @@ def test_reuse_config_n4096_k4_fp64():
     assert rel(got, oracle.invert_block(m, 4, 0, 0)) < 1e-12
 
 
+def test_repeated_calls_n4096_k4_fp64():
+    # Back-to-back calls of the plain and the reused-pivot paths, each
+    # checked against the oracle: a synchronisation fault in the product
+    # kernels (a wavefront reading an operand buffer that another one is
+    # refilling) shows up as an intermittent wrong block, not in one call.
+    m = workloads.workload_matrix("spd_n4096_k4")
+    want = oracle.invert_block(m, 4, 0, 0)
+    g = gpu(m)
+    for rep in range(3):
+        for reuse in (False, True):
+            got = bri.invert_block(g, 4, 0, 0, reuse=reuse, concurrency=16).cpu().numpy()
+            err = rel(got, want)
+            print(f"  rep {rep} reuse={reuse}: rel err {err:.2e}", flush=True)
+            assert err < 1e-12
+
+
 TILE_EDGE_ORDERS = [16, 31, 32, 33, 63, 64, 65, 95, 96, 97, 160]
 
 

@@ -1514,13 +1514,24 @@ __device__ __forceinline__ void zero_acc(typename MF<T>::acc& acc) {
 }
 
 // Stages the two tile inverses of step s (kTile x kTile each) into LDS.
+// The staging functions below issue all their loads before any LDS store
+// (one wait per function, not one per element).
+constexpr int kStagePer = kTile * kTile / 256;  // elements per thread of a 32 x 32 operand
 template <typename T>
 __device__ __forceinline__ void stage_inverses(const LuItem& it, int s, T* sLi, T* sUi) {
   const T* inv = step_inv<T>(it, s);
-  for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
-    const int q = e >> 5, c = e & 31;
-    if (sLi) sLi[q * kStepLd + c] = gload(inv + e);
-    if (sUi) sUi[q * kStepLd + c] = gload(inv + kTile * kTile + e);
+  T vl[kStagePer], vu[kStagePer];
+#pragma unroll
+  for (int u = 0; u < kStagePer; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    if (sLi) vl[u] = gload(inv + e);
+    if (sUi) vu[u] = gload(inv + kTile * kTile + e);
+  }
+#pragma unroll
+  for (int u = 0; u < kStagePer; ++u) {
+    const int e = threadIdx.x + 256 * u, q = e >> 5, c = e & 31;
+    if (sLi) sLi[q * kStepLd + c] = vl[u];
+    if (sUi) sUi[q * kStepLd + c] = vu[u];
   }
 }
 // Stages L_s^{-1} P_s instead of L_s^{-1}: column pm[c] receives column c of
@@ -1530,9 +1541,18 @@ template <typename T>
 __device__ __forceinline__ void stage_linv_perm(const LuItem& it, int s, T* sLi) {
   const T* inv = step_inv<T>(it, s);
   const int32_t* pm = step_perm(it, s);
-  for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
-    const int q = e >> 5, c = e & 31;
-    sLi[q * kStepLd + gload(pm + c)] = gload(inv + e);
+  T v[kStagePer];
+  int col[kStagePer];
+#pragma unroll
+  for (int u = 0; u < kStagePer; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    v[u] = gload(inv + e);
+    col[u] = gload(pm + (e & 31));
+  }
+#pragma unroll
+  for (int u = 0; u < kStagePer; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    sLi[(e >> 5) * kStepLd + col[u]] = v[u];
   }
 }
 
@@ -1553,10 +1573,21 @@ __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem
     const int x = 16 * fi + MF<T>::row(lane, v), y = 16 * fj + (lane & 15);
     acc[v] = (x < ts1 && y < ts1) ? gload(A + static_cast<int64_t>(t1 + x) * b + t1 + y) : T(0);
   }
-  for (int e = tid; e < kTile * kTile; e += 256) {
-    const int x = e >> 5, y = e & 31;
-    sA[x * kStepLd + y] = x < ts1 ? gload(A + static_cast<int64_t>(t1 + x) * b + t0 + y) : T(0);
-    sB[x * kStepLd + y] = y < ts1 ? gload(A + static_cast<int64_t>(t0 + x) * b + t1 + y) : T(0);
+  {
+    // Rows / columns past the matrix read its last row / column and are zeroed.
+    T va[kStagePer], vb[kStagePer];
+#pragma unroll
+    for (int u = 0; u < kStagePer; ++u) {
+      const int e = tid + 256 * u, x = e >> 5, y = e & 31;
+      va[u] = gload(A + static_cast<int64_t>(min(t1 + x, b - 1)) * b + t0 + y);
+      vb[u] = gload(A + static_cast<int64_t>(t0 + x) * b + min(t1 + y, b - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < kStagePer; ++u) {
+      const int e = tid + 256 * u, x = e >> 5, y = e & 31;
+      sA[x * kStepLd + y] = x < ts1 ? va[u] : T(0);
+      sB[x * kStepLd + y] = y < ts1 ? vb[u] : T(0);
+    }
   }
   stage_linv_perm<T>(it, s, sLi);
   stage_inverses<T>(it, s, static_cast<T*>(nullptr), sUi);
@@ -1608,13 +1639,22 @@ __device__ __forceinline__ void step_trailing(const LuItem& it, int t0, int ti, 
         const int gr = r0 + 32 * wr + 16 * i + MF<T>::row(lane, v), gc = c0 + 32 * wc + 16 * j + (lane & 15);
         acc[i][j][v] = (gr < b && gc < b) ? gload(A + static_cast<int64_t>(gr) * b + gc) : T(0);
       }
-  for (int e = tid; e < 64 * kTile; e += 256) {
-    const int x = e >> 5, q = e & 31;
-    sA[x * kStepLd + q] = r0 + x < b ? gload(A + static_cast<int64_t>(r0 + x) * b + t0 + q) : T(0);
-  }
-  for (int e = tid; e < kTile * 64; e += 256) {
-    const int q = e >> 6, y = e & 63;
-    sB[q * kStepLdw + y] = c0 + y < b ? gload(A + static_cast<int64_t>(t0 + q) * b + c0 + y) : T(0);
+  {
+    // Rows / columns past the matrix read its last row / column and are zeroed.
+    constexpr int PER = 64 * kTile / 256;
+    T va[PER], vb[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      va[u] = gload(A + static_cast<int64_t>(min(r0 + (e >> 5), b - 1)) * b + t0 + (e & 31));
+      vb[u] = gload(A + static_cast<int64_t>(t0 + (e >> 6)) * b + min(c0 + (e & 63), b - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      sA[(e >> 5) * kStepLd + (e & 31)] = r0 + (e >> 5) < b ? va[u] : T(0);
+      sB[(e >> 6) * kStepLdw + (e & 63)] = c0 + (e & 63) < b ? vb[u] : T(0);
+    }
   }
   stage_linv_perm<T>(it, s, sLi);
   stage_inverses<T>(it, s, static_cast<T*>(nullptr), sUi);
@@ -1681,15 +1721,24 @@ __device__ __forceinline__ void step_strip_rows(const LuItem& it, int t0, int i,
   T* sX = smem;                   // [64][kStepLd]
   T* sUi = sX + 64 * kStepLd;
   const int32_t* pm = step_perm(it, s);
-  for (int e = tid; e < 64 * kTile; e += 256) {
-    const int x = e >> 5, q = e & 31;
-    const int g = R0 + x;
-    T v = T(0);
-    if (g < b) {
-      const int src = g < t0 + ts ? t0 + gload(pm + (g - t0)) : g;
-      v = gload(A + static_cast<int64_t>(src) * b + tp + q);
+  {
+    // Source rows first (rows of tile s's band through its permutation),
+    // then the values; rows past the matrix read its last row, zeroed.
+    constexpr int PER = 64 * kTile / 256;
+    int src[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int g = R0 + ((tid + 256 * u) >> 5);
+      src[u] = g < t0 + ts ? t0 + gload(pm + min(g - t0, ts - 1)) : min(g, b - 1);
     }
-    sX[x * kStepLd + q] = v;
+    T v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) v[u] = gload(A + static_cast<int64_t>(src[u]) * b + tp + ((tid + 256 * u) & 31));
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, x = e >> 5;
+      sX[x * kStepLd + (e & 31)] = R0 + x < b ? v[u] : T(0);
+    }
   }
   stage_inverses<T>(it, s - 1, static_cast<T*>(nullptr), sUi);
   __syncthreads();
@@ -1715,9 +1764,20 @@ __device__ __forceinline__ void step_strip_cols(const LuItem& it, int t0, int j,
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   T* sB = smem;                   // [kTile][kStepLdw]
   T* sLi = sB + kTile * kStepLdw;
-  for (int e = tid; e < kTile * 64; e += 256) {
-    const int q = e >> 6, y = e & 63;
-    sB[q * kStepLdw + y] = C0 + y < b ? gload(A + static_cast<int64_t>(tp + q) * b + C0 + y) : T(0);
+  {
+    // Columns past the matrix read its last column and are zeroed.
+    constexpr int PER = kTile * 64 / 256;
+    T v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      v[u] = gload(A + static_cast<int64_t>(tp + (e >> 6)) * b + min(C0 + (e & 63), b - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      sB[(e >> 6) * kStepLdw + (e & 63)] = C0 + (e & 63) < b ? v[u] : T(0);
+    }
   }
   stage_linv_perm<T>(it, s - 1, sLi);
   __syncthreads();

@@ -1571,7 +1571,7 @@ __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int x = 16 * fi + MF<T>::row(lane, v), y = 16 * fj + (lane & 15);
-    acc[v] = (x < ts1 && y < ts1) ? gload(A + static_cast<int64_t>(t1 + x) * b + t1 + y) : T(0);
+    acc[v] = gload(A + static_cast<int64_t>(min(t1 + x, b - 1)) * b + min(t1 + y, b - 1));
   }
   {
     // Rows / columns past the matrix read its last row / column and are zeroed.
@@ -1591,6 +1591,11 @@ __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem
   }
   stage_linv_perm<T>(it, s, sLi);
   stage_inverses<T>(it, s, static_cast<T*>(nullptr), sUi);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int x = 16 * fi + MF<T>::row(lane, v), y = 16 * fj + (lane & 15);
+    if (!(x < ts1 && y < ts1)) acc[v] = T(0);
+  }
   __syncthreads();
   // L21 fragment (wave >> 1, wave & 1) and U12 fragment (wave >> 1, wave & 1)
   typename MF<T>::acc l21, u12;
@@ -1628,6 +1633,8 @@ __device__ __forceinline__ void step_trailing(const LuItem& it, int t0, int ti, 
   T* sUi = sLi + kTile * kStepLd;
   // The block of C (32 x 32 per wavefront) is requested first: its loads are
   // in flight while the strip pieces are formed.
+  // (Unconditional loads from clamped addresses, zeroed past the matrix
+  // once they have landed: a load under a per-element branch waits.)
   const int wr = wave >> 1, wc = wave & 1;
   typename MF<T>::acc acc[2][2];
 #pragma unroll
@@ -1637,7 +1644,7 @@ __device__ __forceinline__ void step_trailing(const LuItem& it, int t0, int ti, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gr = r0 + 32 * wr + 16 * i + MF<T>::row(lane, v), gc = c0 + 32 * wc + 16 * j + (lane & 15);
-        acc[i][j][v] = (gr < b && gc < b) ? gload(A + static_cast<int64_t>(gr) * b + gc) : T(0);
+        acc[i][j][v] = gload(A + static_cast<int64_t>(min(gr, b - 1)) * b + min(gc, b - 1));
       }
   {
     // Rows / columns past the matrix read its last row / column and are zeroed.
@@ -1658,6 +1665,15 @@ __device__ __forceinline__ void step_trailing(const LuItem& it, int t0, int ti, 
   }
   stage_linv_perm<T>(it, s, sLi);
   stage_inverses<T>(it, s, static_cast<T*>(nullptr), sUi);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gr = r0 + 32 * wr + 16 * i + MF<T>::row(lane, v), gc = c0 + 32 * wc + 16 * j + (lane & 15);
+        if (!(gr < b && gc < b)) acc[i][j][v] = T(0);
+      }
   __syncthreads();
   // Strip pieces: L21 (64 x 32, fragments 0..7) and U12 (32 x 64, fragments
   // 8..15); wavefront w forms fragments w, w + 4, w + 8, w + 12.
@@ -1729,7 +1745,12 @@ __device__ __forceinline__ void step_strip_rows(const LuItem& it, int t0, int i,
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int g = R0 + ((tid + 256 * u) >> 5);
-      src[u] = g < t0 + ts ? t0 + gload(pm + min(g - t0, ts - 1)) : min(g, b - 1);
+      src[u] = gload(pm + min(g - t0, ts - 1));  // used only for rows of tile s's band
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int g = R0 + ((tid + 256 * u) >> 5);
+      src[u] = g < t0 + ts ? t0 + src[u] : min(g, b - 1);
     }
     T v[PER];
 #pragma unroll
@@ -1802,11 +1823,16 @@ __device__ __forceinline__ void step_band(const LuItem& it, int t0, int j) {
   T* A = static_cast<T*>(it.a);
   const int b = it.b, s = t0 / kTile, ts = min(kTile, b - t0), cend = t0 - kTile;
   const int32_t* pm = step_perm(it, s);
+  // Permutation entries first, then the rows (clamped addresses; entries
+  // past the band or the columns are not stored).
+  int src[kTile * 64 / 256];
+#pragma unroll
+  for (int t = 0; t < kTile * 64 / 256; ++t) src[t] = gload(pm + min(static_cast<int>(threadIdx.x + 256 * t) >> 6, ts - 1));
   T v[kTile * 64 / 256];
 #pragma unroll
   for (int t = 0; t < kTile * 64 / 256; ++t) {
-    const int e = threadIdx.x + 256 * t, q = e >> 6, y = 64 * j + (e & 63);
-    v[t] = (q < ts && y < cend) ? gload(A + static_cast<int64_t>(t0 + gload(pm + q)) * b + y) : T(0);
+    const int e = threadIdx.x + 256 * t, y = 64 * j + (e & 63);
+    v[t] = gload(A + static_cast<int64_t>(t0 + src[t]) * b + min(y, cend - 1));
   }
   __syncthreads();
 #pragma unroll

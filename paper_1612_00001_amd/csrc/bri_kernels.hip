@@ -676,10 +676,11 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmLaun
     // and issue (their loads repeat the last step), so that every step of the
     // unrolled body has the same loads in flight.
     auto step = [&](int t, double* ra, double* rb, double* wa, double* wb) {
-      // vmcnt(0): loads into LDS were seen to complete out of order (with
-      // two workgroups per compute unit, waiting for all but the last
-      // step's loads let a wavefront read pieces of step t not yet written),
-      // so the wait covers steps t and t + 1.  lgkmcnt(0): this wavefront's
+      // vmcnt(0): the wait covers steps t and t + 1 (a partial wait, for
+      // all but the last step's loads, gave wrong blocks with two
+      // workgroups per compute unit before the lgkmcnt(0) below was added,
+      // which may have been the cause; the full wait costs nothing
+      // measurable).  lgkmcnt(0): this wavefront's
       // reads of step t - 1's buffer are complete before the barrier (the
       // compiler places the MFMAs that consume them, and their waits, after
       // it), since once past it other wavefronts load step t + 2 into that

@@ -21,7 +21,6 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
-#include <type_traits>
 #include <utility>
 
 #include "bri_internal.h"

@@ -1314,12 +1314,19 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
   T (*sF)[LD] = reinterpret_cast<T (*)[LD]>(lds + 2 * kTile * LD);      // factored tile in pivot order
   T (*sFT)[LD] = reinterpret_cast<T (*)[LD]>(lds + 3 * kTile * LD);     // its transpose
   T* sD = lds + 4 * kTile * LD;                                         // reciprocals of U's diagonal
+  // The tile (rows and columns past the matrix become identity rows): all
+  // loads first, from the whole LDS tile or clamped matrix addresses, so
+  // that no load waits under a per-element branch.
   T a[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int c = 16 * half + t;
-    a[t] = (r < ts && c < ts) ? (sT ? sT[r * ldt + c] : gload(A + static_cast<int64_t>(t0 + r) * b + t0 + c))
-                              : (r == c ? T(1) : T(0));
+    a[t] = sT ? sT[r * ldt + c] : gload(A + static_cast<int64_t>(t0 + min(r, ts - 1)) * b + t0 + min(c, ts - 1));
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int c = 16 * half + t;
+    if (!(r < ts && c < ts)) a[t] = r == c ? T(1) : T(0);
   }
   bool done = false;
   int pos = r;  // position of this row in the factored tile (rows >= ts keep theirs)

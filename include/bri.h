@@ -93,6 +93,11 @@ typedef struct {
   size_t workspace_bytes;  /* its size                                                */
   int32_t* d_info;         /* device int32 status (see above), or NULL                */
   hipStream_t stream;      /* stream the work is enqueued on (NULL = default stream)  */
+  int factorization;       /* the LU of each pivot block (with tile pivoting):
+                              0 automatic; 1 tile steps (one launch per 32-column
+                              diagonal tile) followed by a triangular inversion;
+                              2 recursive halving with inverted factors (block
+                              orders 32 * 2^m only, else tile steps)              */
 } bri_opts;
 
 /* Fills *o with defaults: BRI_F64, automatic concurrency, tile pivoting, no

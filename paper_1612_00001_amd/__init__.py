@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libbri.so")
 
 PRECISIONS = {"f64": 0, "f32": 1, "mixed_f32": 2, "mixed_f16": 3, "mixed_bf16": 4}
 PIVOTING = {"tile": 0, "panel": 1}
+FACTORIZATIONS = {"auto": 0, "tile": 1, "recursive": 2}
 _DTYPE_OF = {"f64": torch.float64, "f32": torch.float32, "mixed_f32": torch.float64,
              "mixed_f16": torch.float64, "mixed_bf16": torch.float64}
 
@@ -42,6 +43,7 @@ class BriOpts(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("d_info", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
+        ("factorization", ctypes.c_int),
     ]
 
 
@@ -140,7 +142,8 @@ def _check(status: int) -> None:
 
 
 def make_opts(precision: str = "f64", concurrency: int = 0, refine_max_iters: int = 10,
-              refine_tol: float = 1e-12, pivoting: str = "tile", reuse: bool = False) -> BriOpts:
+              refine_tol: float = 1e-12, pivoting: str = "tile", reuse: bool = False,
+              factorization: str = "auto") -> BriOpts:
     o = BriOpts()
     lib().bri_default_opts(ctypes.byref(o))
     if precision not in PRECISIONS:
@@ -153,6 +156,9 @@ def make_opts(precision: str = "f64", concurrency: int = 0, refine_max_iters: in
     o.reuse = int(bool(reuse))
     o.refine_max_iters = int(refine_max_iters)
     o.refine_tol = float(refine_tol)
+    if factorization not in FACTORIZATIONS:
+        raise ValueError(f"unknown factorization {factorization!r}")
+    o.factorization = FACTORIZATIONS[factorization]
     return o
 
 
@@ -174,9 +180,9 @@ def block_size(n: int, k: int) -> int:
 
 
 def plan_describe(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
-                  reuse: bool = False) -> dict:
+                  reuse: bool = False, factorization: str = "auto") -> dict:
     """Host-only structure of the plan (no GPU needed)."""
-    o = make_opts(precision, concurrency, reuse=reuse)
+    o = make_opts(precision, concurrency, reuse=reuse, factorization=factorization)
     s = BriPlanStats()
     _check(lib().bri_plan_describe(n, k, i, j, ctypes.byref(o), ctypes.byref(s)))
     return {f: getattr(s, f) for f, _ in BriPlanStats._fields_}
@@ -231,7 +237,8 @@ def workspace_size(n: int, k: int, i: int, j: int, precision: str = "f64", concu
 def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
                  out: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
                  workspace: Optional[torch.Tensor] = None, refine_max_iters: int = 10,
-                 refine_tol: float = 1e-12, pivoting: str = "tile", reuse: bool = False) -> torch.Tensor:
+                 refine_tol: float = 1e-12, pivoting: str = "tile", reuse: bool = False,
+                 factorization: str = "auto") -> torch.Tensor:
     """Block N_ij (b x b, b = ceil(n/k)) of M^{-1} (of Gamma^{-1} when k does not divide n).
 
     ``info`` (optional int32 GPU tensor of one element) receives the device
@@ -243,7 +250,7 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
     if M.shape[1] != n:
         raise ValueError("M must be square")
     b = block_size(n, k)
-    o = make_opts(precision, concurrency, refine_max_iters, refine_tol, pivoting, reuse)
+    o = make_opts(precision, concurrency, refine_max_iters, refine_tol, pivoting, reuse, factorization)
     need = lib().bri_workspace_size(n, k, i, j, ctypes.byref(o))
     if need == 0:
         # Invalid arguments: let the library name the offending one (it
@@ -265,14 +272,14 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
 
 
 def block_column(M: torch.Tensor, k: int, j: int, transpose: bool = False, precision: str = "f64",
-                 concurrency: int = 0) -> torch.Tensor:
+                 concurrency: int = 0, factorization: str = "auto") -> torch.Tensor:
     """Block column j of Gamma^{-1} ((k*b) x b); with ``transpose`` the block
     column of (Gamma^T)^{-1}, i.e. the transposed block row j of Gamma^{-1}."""
     dtype = _DTYPE_OF[precision]
     _require_gpu(M, "M", dtype)
     n = M.shape[0]
     b = block_size(n, k)
-    o = make_opts(precision, concurrency)
+    o = make_opts(precision, concurrency, factorization=factorization)
     need = lib().bri_block_column_workspace_size(n, k, j, ctypes.byref(o))
     if need == 0:
         raise BriError(BRI_ERR_UNSUPPORTED, "invalid arguments")
@@ -310,7 +317,8 @@ def invert_block_backward(M: torch.Tensor, k: int, i: int, j: int, G: torch.Tens
 
 def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Sequence[int],
                          jjs: Sequence[int], precision: str = "f64", concurrency: int = 0,
-                         info: Optional[torch.Tensor] = None, reuse: bool = False) -> List[torch.Tensor]:
+                         info: Optional[torch.Tensor] = None, reuse: bool = False,
+                         factorization: str = "auto") -> List[torch.Tensor]:
     """One block per problem; all problems share one workspace and one call."""
     count = len(Ms)
     dtype = _DTYPE_OF[precision]
@@ -327,7 +335,7 @@ def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Seq
     ldo = (ctypes.c_int64 * count)(*[o_.stride(0) for o_ in outs])
     mp = (ctypes.c_void_p * count)(*[m.data_ptr() for m in Ms])
     op = (ctypes.c_void_p * count)(*[o_.data_ptr() for o_ in outs])
-    o = make_opts(precision, concurrency, reuse=reuse)
+    o = make_opts(precision, concurrency, reuse=reuse, factorization=factorization)
     need = lib().bri_batched_workspace_size(count, n, kk, ii, jj, ctypes.byref(o))
     if need == 0 and count > 0:
         raise BriError(BRI_ERR_UNSUPPORTED, "invalid arguments")

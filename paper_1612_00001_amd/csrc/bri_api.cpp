@@ -148,6 +148,7 @@ std::shared_ptr<CachedPlan> get_plan(int kind, int64_t n, int k, int i, int j, i
 // ---------------------------------------------------------------------------
 struct Ctx {
   int pivoting = BRI_PIVOT_TILE;
+  int lu = 0;           // factorisation variant (bri_opts::factorization)
   const char* M = nullptr;
   int64_t n = 0, ldm = 0;
   int b = 0;
@@ -314,7 +315,8 @@ void describe_step(const Ctx& c, const Step& s, StepItems& out) {
         lu.a = slot_ptr(c, it.dst.a);
         lu.perm = perm_ptr(c, it.dst.a);
         lu.swaps = swap_ptr(c, it.dst.a);
-        lu.tmp = s.kind == ST_TRTRI ? slot_ptr(c, it.x.a) : nullptr;
+        // scratch of the triangular inversion, or the shadow of the recursive LU
+        lu.tmp = it.x.kind == OPND_SLOT ? slot_ptr(c, it.x.a) : nullptr;
         lu.aux = aux_ptr(c, it.dst.a);
         lu.info = c.info;
         lu.node = it.node;
@@ -415,12 +417,12 @@ double step_flops(const Step& s, int b) {
   }
 }
 
-int64_t step_launches(const Step& s, int b, int pivoting) {
-  switch (s.kind) {
+int64_t step_launches(StepKind kind, int count, int b, int pivoting, bool uniform, int lu) {
+  switch (kind) {
     case ST_GETRF:
-      return getrf_launches(b, pivoting != BRI_PIVOT_PANEL);
+      return getrf_launches(b, lu_kind(count, b, pivoting == BRI_PIVOT_PANEL, uniform, lu));
     case ST_TRTRI:
-      return trtri_launches(b, pivoting != BRI_PIVOT_PANEL);
+      return trtri_launches(b, lu_kind(count, b, pivoting == BRI_PIVOT_PANEL, uniform, lu));
     default:
       return 1;
   }
@@ -436,13 +438,22 @@ struct ExecStep {
   const void* desc;
   const Step* step;
   double flops;  // algorithmic flops of all items (profile record)
+  bool uniform;  // every item has the block order bmax
 };
+
+// The factorisation of a step (and the triangular inversion after it) takes
+// the recursive LU with inverted factors when all its matrices have one
+// block order that the recursion halves down to tiles and the launch is
+// large enough (getrf_rec_applies); otherwise the tile-step LU.
+bool step_recursive(const ExecStep& s, int bmax, int pivoting, int lu) {
+  return lu_kind(s.count, bmax, pivoting == BRI_PIVOT_PANEL, s.uniform, lu) == LU_RECURSIVE;
+}
 
 // Enqueues the kernels of the steps; bmax is the largest block order among
 // the items (merged batches mix orders; every kernel skips the parts of a
 // smaller matrix).
 template <typename T>
-int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lp, hipStream_t st) {
+int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lu, int lp, hipStream_t st) {
   bool prof;
   {
     std::lock_guard<std::mutex> g(g_prof_mu);
@@ -455,7 +466,7 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lp,
     if (prof) {
       std::lock_guard<std::mutex> g(g_prof_mu);
       rec.kind = s.kind;
-      rec.launches = step_launches(*s.step, bmax, pivoting);
+      rec.launches = step_launches(s.kind, s.count, bmax, pivoting, s.uniform, lu);
       rec.flops = s.flops;
       rec.e0 = prof_event();
       rec.e1 = prof_event();
@@ -466,11 +477,17 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lp,
         e = launch_load<T>(static_cast<const LoadItem*>(s.desc), s.count, bmax, bmax, st);
         break;
       case ST_GETRF:
-        e = pivoting == BRI_PIVOT_PANEL ? launch_getrf<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st)
-                                        : launch_getrf_tile<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
+        if (pivoting == BRI_PIVOT_PANEL)
+          e = launch_getrf<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
+        else if (step_recursive(s, bmax, pivoting, lu))
+          e = launch_getrf_rec<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
+        else
+          e = launch_getrf_tile<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
         break;
       case ST_TRTRI:
-        e = launch_trtri<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, pivoting != BRI_PIVOT_PANEL, st);
+        // after the recursive LU the factors are already inverted
+        if (!step_recursive(s, bmax, pivoting, lu))
+          e = launch_trtri<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, pivoting != BRI_PIVOT_PANEL, st);
         break;
       default: {
         GemmLaunch L{};
@@ -505,9 +522,9 @@ int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
     const Step& s = p.steps[si];
     ex.push_back(ExecStep{s.kind, static_cast<int>(s.items.size()), c.lay->nfast[si], c.lay->ndirect[si],
                           dbase + c.lay->step_off[si], &s,
-                          step_flops(s, c.b)});
+                          step_flops(s, c.b), true});
   }
-  return run_exec<T>(ex, c.b, c.pivoting, c.lp, st);
+  return run_exec<T>(ex, c.b, c.pivoting, c.lu, c.lp, st);
 }
 
 // Uploads the descriptors of plan cp for context c and enqueues its kernels.
@@ -631,6 +648,8 @@ MergedExec merge_write(const std::vector<const Plan*>& plans, const std::vector<
     const Plan& p0 = *plans[grp[0]];
     int bmax = 0;
     for (int t : grp) bmax = std::max(bmax, ctx[t].b);
+    bool uniform = true;
+    for (int t : grp) uniform = uniform && ctx[t].b == bmax;
     ex.bmax.push_back(bmax);
     ex.groups.emplace_back();
     for (size_t si = 0; si < p0.steps.size(); ++si) {
@@ -643,16 +662,16 @@ MergedExec merge_write(const std::vector<const Plan*>& plans, const std::vector<
       }
       items.write(host + m.step_off[g][si]);
       ex.groups.back().push_back(ExecStep{p0.steps[si].kind, static_cast<int>(items.count()), items.nfast(),
-                                          items.ndirect(), dev + m.step_off[g][si], &p0.steps[si], flops});
+                                          items.ndirect(), dev + m.step_off[g][si], &p0.steps[si], flops, uniform});
     }
   }
   return ex;
 }
 
 template <typename T>
-int run_merged(const MergedExec& ex, int pivoting, int lp, hipStream_t st) {
+int run_merged(const MergedExec& ex, int pivoting, int lu, int lp, hipStream_t st) {
   for (size_t g = 0; g < ex.groups.size(); ++g) {
-    const int rc = run_exec<T>(ex.groups[g], ex.bmax[g], pivoting, lp, st);
+    const int rc = run_exec<T>(ex.groups[g], ex.bmax[g], pivoting, lu, lp, st);
     if (rc != BRI_OK) return rc;
   }
   return BRI_OK;
@@ -729,7 +748,7 @@ int run_batch(const BatchPlan& bp, const void* const* M, const int64_t* n, const
   if (hipEventRecord(sg.ev, st) != hipSuccess) return BRI_ERR_HIP;
   if (launch_fill_int(o->d_info ? o->d_info : shared_info, o->d_info ? count : 1, 0, st) != hipSuccess)
     return BRI_ERR_HIP;
-  return run_merged<T>(ex, BRI_PIVOT_TILE, 0, st);
+  return run_merged<T>(ex, BRI_PIVOT_TILE, o->factorization, 0, st);
 }
 
 // Merged execution of plain precisions needs tile pivoting (the panel
@@ -932,6 +951,8 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
     // float plans: sigma Gamma in place of M, D as the output, R32 as the right-hand side
     Ctx& c = cc[t];
     c.pivoting = o->pivoting;
+    c.lu = o->factorization;
+  c.lu = o->factorization;
     c.M = reinterpret_cast<const char*>(r.G);
     c.n = kb;
     c.ldm = kb;
@@ -986,12 +1007,12 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
   if (launch_scal_clear(d_items, count, 0, kRefineScalars, st) != hipSuccess) return BRI_ERR_HIP;
   if (launch_absmax(d_items, count, 0, max_nn, st) != hipSuccess) return BRI_ERR_HIP;
   if (launch_gamma_f32(d_items, count, max_kk, st) != hipSuccess) return BRI_ERR_HIP;
-  int rcode = run_merged<float>(ecol, o->pivoting, lp_of(o->precision), st);
+  int rcode = run_merged<float>(ecol, o->pivoting, o->factorization, lp_of(o->precision), st);
   if (rcode != BRI_OK) return rcode;
   if (!mb.rc[0]->column_gives_x0) {
     // Pivots only (reuse): X0 = (sigma Gamma)^{-1} E_j by the solve plan.
     if (launch_set_ej(d_items, count, max_kb_b, st) != hipSuccess) return BRI_ERR_HIP;
-    rcode = run_merged<float>(esol, o->pivoting, lp_of(o->precision), st);
+    rcode = run_merged<float>(esol, o->pivoting, o->factorization, lp_of(o->precision), st);
     if (rcode != BRI_OK) return rcode;
   }
   if (launch_refine_update(d_items, count, max_kb_b, 1, st) != hipSuccess) return BRI_ERR_HIP;
@@ -1021,7 +1042,7 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
     if (launch_resid_fix(d_items, count, max_fix, st) != hipSuccess) return BRI_ERR_HIP;
     if (launch_absmax(d_items, count, 1, max_kb_b, st) != hipSuccess) return BRI_ERR_HIP;
     if (launch_rhs_scale(d_items, count, max_kb_b, st) != hipSuccess) return BRI_ERR_HIP;
-    rcode = run_merged<float>(esol, o->pivoting, lp_of(o->precision), st);
+    rcode = run_merged<float>(esol, o->pivoting, o->factorization, lp_of(o->precision), st);
     if (rcode != BRI_OK) return rcode;
     if (launch_refine_update(d_items, count, max_kb_b, 0, st) != hipSuccess) return BRI_ERR_HIP;
     if (hipMemcpyAsync(hs.data(), scal_all, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -1177,7 +1198,8 @@ int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_pla
   s->batch_width = p.width;
   s->steps = static_cast<int64_t>(p.steps.size());
   int64_t launches = 1;  // clearing d_info
-  for (const Step& st : p.steps) launches += step_launches(st, p.b, o->pivoting);
+  for (const Step& st : p.steps)
+    launches += step_launches(st.kind, static_cast<int>(st.items.size()), p.b, o->pivoting, true, o->factorization);
   s->kernel_launches = launches;
   s->block = p.b;
   s->algorithmic_flops = p.algorithmic_flops;
@@ -1262,6 +1284,7 @@ int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, voi
   if (!o->workspace || o->workspace_bytes < cp->layout.total) return BRI_ERR_WORKSPACE;
   Ctx c;
   c.pivoting = o->pivoting;
+  c.lu = o->factorization;
   c.M = static_cast<const char*>(M);
   c.n = n;
   c.ldm = ldm;
@@ -1305,6 +1328,7 @@ int bri_block_column(const void* M, int64_t n, int64_t ldm, int k, int j, int tr
   if (!o->workspace || o->workspace_bytes < cp->layout.total) return BRI_ERR_WORKSPACE;
   Ctx c;
   c.pivoting = o->pivoting;
+  c.lu = o->factorization;
   c.M = static_cast<const char*>(M);
   c.n = n;
   c.ldm = ldm;

@@ -72,6 +72,13 @@ enum GemmMode : int32_t {
   GEMM_LU_TRAILING = 1, // trailing update of a right-looking LU step
   GEMM_TRTRI_STEP1 = 2, // recursive-doubling triangular inversion, first product
   GEMM_TRTRI_STEP2 = 3, // second product
+  // Recursive LU with inverted factors (launch_getrf_rec): the products of
+  // one node (origin j, halves of order s) of the recursion, formed on the
+  // device from the LuItem (a: the matrix, tmp: a b x b shadow of it).
+  GEMM_RLU_A = 4,       // U12 = L11^{-1} P1 A12 and L21 = A21 U11^{-1}, into the shadow
+  GEMM_RLU_B = 5,       // A22 -= L21 U12 and Y = U11^{-1} U12 (shadow)
+  GEMM_RLU_C = 6,       // X = L22^{-1} P2 L21 (shadow) and A12 <- -Y U22^{-1}
+  GEMM_RLU_D = 7,       // A21 <- -X L11^{-1}
 };
 
 struct GemmLaunch {
@@ -217,8 +224,27 @@ Plan make_block_plan_reuse(int64_t n, int k, int i, int j, int width);
 
 // Launch/flop accounting of the kernels that realise a step.
 // Kernel launches of one batched LU (tile pivoting, or panels with partial pivoting).
-int64_t getrf_launches(int b, bool tile_pivoting);
-int64_t trtri_launches(int b, bool tile_pivoting);
+// LU variants: tile-step LU (tile pivoting), panel LU (partial pivoting),
+// recursive LU with inverted factors (tile pivoting; no triangular
+// inversion follows).
+enum LuKind : int { LU_TILE = 0, LU_PANEL = 1, LU_RECURSIVE = 2 };
+// The recursive LU halves the matrix down to kTile x kTile tiles: b must be
+// kTile times a power of two.
+inline bool getrf_rec_possible(int b) { return b >= 2 * kTile && b <= kMaxBlock && (b & (b - 1)) == 0; }
+// Variant of a factorisation launch of count matrices of order b (uniform:
+// all of that order).  choice: 0 automatic, 1 tile steps, 2 recursive where
+// possible.  Automatic: the recursion's products keep the MFMA pipes busy
+// when there are many or large matrices; for few small ones the tile-step
+// LU's shorter chain of launches wins.
+inline LuKind lu_kind(int count, int b, bool panel_pivoting, bool uniform, int choice) {
+  if (panel_pivoting) return LU_PANEL;
+  if (!uniform || !getrf_rec_possible(b) || choice == 1) return LU_TILE;
+  if (choice == 2) return LU_RECURSIVE;
+  const double work = static_cast<double>(count) * b * b * b;
+  return work >= 64.0 * 1024.0 * 1024.0 * 1024.0 ? LU_RECURSIVE : LU_TILE;
+}
+int64_t getrf_launches(int b, LuKind kind);
+int64_t trtri_launches(int b, LuKind kind);
 double getrf_flops(int b);
 double trtri_flops(int b);
 

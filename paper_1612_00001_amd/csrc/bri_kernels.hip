@@ -113,6 +113,77 @@ __device__ bool gemm_item(const GemmLaunch& L, int idx, GemmItem& it) {
     it.beta = 1.0;
     return true;
   }
+  if (MODE == GEMM_RLU_A || MODE == GEMM_RLU_B || MODE == GEMM_RLU_C || MODE == GEMM_RLU_D) {
+    // Node of the recursive LU at origin o with halves of order h.  Packed
+    // block (1,1) holds L11^{-1} (strictly lower) and U11^{-1} (upper) once
+    // the first half is done, likewise (2,2); the shadow sh (b x b, same
+    // coordinates) holds the node's intermediate blocks at their positions.
+    constexpr int P = MODE == GEMM_RLU_D ? 1 : 2;
+    const int part = idx % P;
+    const LuItem lu = static_cast<const LuItem*>(L.items)[idx / P];
+    const int b = lu.b, o = L.j, h = L.s;
+    if (o + 2 * h > b) return false;
+    char* a = static_cast<char*>(lu.a);
+    char* sh = static_cast<char*>(lu.tmp);
+    it.has_cin = 0;
+    it.has_sub = 0;
+    it.beta = 0.0;
+    it.alpha = 1.0;
+    it.Cin = dense_view(a, b, 0, 0, 0, 0, E);
+    it.Sub = it.Cin;
+    it.M = it.N = it.K = h;
+    it.ldo = b;
+    // A row-permuted view: element (x, y) is stored row perm[x] (an index
+    // of the b x b matrix) of column c0 + y.
+    auto permuted = [&](char* base, int c0, int r0) {
+      DView v = dense_view(base, b, 0, c0, b, h, E);
+      v.rowperm = lu.perm + r0;
+      return v;
+    };
+    const int64_t o1 = o, o2 = o + h;
+    if (MODE == GEMM_RLU_A) {
+      if (part == 0) {  // U12 = L11^{-1} (P1 A12)
+        it.A = dense_view(a, b, o1, o1, h, h, E, 1);
+        it.B = permuted(a, o2, o1);
+        it.out = sh + (o1 * b + o2) * E;
+      } else {          // L21 = A21 U11^{-1}
+        it.A = dense_view(a, b, o2, o1, h, h, E);
+        it.B = dense_view(a, b, o1, o1, h, h, E, 2);
+        it.out = sh + (o2 * b + o1) * E;
+      }
+    } else if (MODE == GEMM_RLU_B) {
+      if (part == 0) {  // A22 = A22 - L21 U12 (the Schur complement the second half factors)
+        it.A = dense_view(sh, b, o2, o1, h, h, E);
+        it.B = dense_view(sh, b, o1, o2, h, h, E);
+        it.Cin = dense_view(a, b, o2, o2, h, h, E);
+        it.has_cin = 1;
+        it.beta = 1.0;
+        it.alpha = -1.0;
+        it.out = a + (o2 * b + o2) * E;
+      } else {          // Y = U11^{-1} U12
+        it.A = dense_view(a, b, o1, o1, h, h, E, 2);
+        it.B = dense_view(sh, b, o1, o2, h, h, E);
+        it.out = sh + (o1 * b + o1) * E;
+      }
+    } else if (MODE == GEMM_RLU_C) {
+      if (part == 0) {  // X = L22^{-1} (P2 L21)
+        it.A = dense_view(a, b, o2, o2, h, h, E, 1);
+        it.B = permuted(sh, o1, o2);
+        it.out = sh + (o2 * b + o2) * E;
+      } else {          // block (1,2) of U^{-1}: -Y U22^{-1}
+        it.A = dense_view(sh, b, o1, o1, h, h, E);
+        it.B = dense_view(a, b, o2, o2, h, h, E, 2);
+        it.alpha = -1.0;
+        it.out = a + (o1 * b + o2) * E;
+      }
+    } else {            // block (2,1) of L^{-1}: -X L11^{-1}
+      it.A = dense_view(sh, b, o2, o2, h, h, E);
+      it.B = dense_view(a, b, o1, o1, h, h, E, 1);
+      it.alpha = -1.0;
+      it.out = a + (o2 * b + o1) * E;
+    }
+    return true;
+  }
   // Recursive-doubling inversion of the packed triangular factors.  Pair pi of
   // level s covers rows/cols [o, o + s + s2), o = 2 s pi, s2 = min(s, b - o - s).
   // L part: inv([[A, 0], [C, D]]) lower-left = -D^{-1} C A^{-1}.
@@ -336,7 +407,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
   typedef TileOp<T, BK, BN, NT> OpB;
   constexpr int AE = OpA::E, BE = OpB::E;
   static_assert(AE * NT == BM * BK && BE * NT == BK * BN, "tile/thread mismatch");
-  constexpr bool USE_PERM = (MODE == GEMM_EXPLICIT) && !GEN;
+  constexpr bool USE_PERM = (MODE == GEMM_EXPLICIT || MODE == GEMM_RLU_A || MODE == GEMM_RLU_C) && !GEN;
 
   GemmItem it;
   int item, tile;
@@ -370,7 +441,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
   const int32_t* permB = nullptr;
   if (USE_PERM) {
     // At most one operand carries a row permutation (the B operand of
-    // L^{-1} P B); stage it in LDS once.
+    // L^{-1} P B); stage it in LDS once (K entries for B).
     const int32_t* gp = it.B.rowperm ? it.B.rowperm : it.A.rowperm;
     const int np = it.B.rowperm ? it.K : it.M;
     if (gp) {
@@ -523,7 +594,7 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int MODE, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmLaunch L) {
   constexpr int BK = 16;
   constexpr int NWN = BN / WN, NT = (BM / WM) * NWN * 64, FM = WM / 16, FN = WN / 16;
@@ -541,7 +612,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmLaun
   GemmItem it;
   int item, tile;
   gemm_workgroup(item, tile);
-  if (!gemm_item<double, GEMM_EXPLICIT>(L, item, it)) return;
+  if (!gemm_item<double, MODE>(L, item, it)) return;
   const int tiles_n = (it.N + BN - 1) / BN;
   const int tiles_m = (it.M + BM - 1) / BM;
   if (tile >= tiles_m * tiles_n) return;
@@ -559,6 +630,8 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmLaun
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / NWN, wn = wave % NWN;
   const int K = it.K;
+  // (The recursive LU's items keep A unpermuted and B either permuted or
+  // triangular, never both.)
   const bool perm = it.B.rowperm != nullptr;
   if (perm) {
     for (int e = tid; e < K; e += NT) s_perm[e] = static_cast<int16_t>(it.B.rowperm[e]);
@@ -1480,6 +1553,17 @@ __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
   }
 }
 
+// Base case of the recursive LU (launch_getrf_rec): diagonal tile t0 / kTile
+// is factored and replaced by its packed inverses (L^{-1} strictly below the
+// diagonal, U^{-1} on and above it), its permutation composed into perm.
+template <typename T>
+__global__ __launch_bounds__(64) void k_tile_lu_inv(const LuItem* items, int t0) {
+  __shared__ __attribute__((aligned(16))) T lds[kLuLdsElems];
+  tile_lu_wave<T>(items[blockIdx.x], t0, nullptr, 0, lds);
+  __threadfence();  // the inverses this wavefront stored to aux
+  step_diag_inverse<T>(items[blockIdx.x], t0 / kTile);
+}
+
 // ---------------------------------------------------------------------------
 // Tile step of the tile-pivoting LU.  The launch for diagonal tile s (rows
 // and columns [t0, t0 + kTile)) runs after tile s has been factored, and its
@@ -2116,6 +2200,29 @@ hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n
   return hipGetLastError();
 }
 
+// Products of the recursive LU: every operand is a stored block at a
+// multiple of 32 rows and columns of a b x b matrix (b even), so FP64 items
+// all qualify for the direct-to-LDS instance (shapes as for explicit items);
+// the 32 x 32 products of the lowest level and FP32 take the register-staged
+// kernel.
+template <typename T, int MODE>
+hipError_t launch_gemm_rlu(const GemmLaunch& L, int max_m, int max_n, hipStream_t st) {
+  if constexpr (sizeof(T) == 8) {
+    const int tier = gemm_tier(L, MODE, L.count, max_m, max_n);
+    if (tier == kTierSmall) {
+      dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), L.count);
+      hipLaunchKernelGGL((k_gemm_dl<MODE, 64, 64, 32, 32>), grid, dim3(256), 0, st, L);
+      return hipGetLastError();
+    }
+    if (tier != kTierTiny) {
+      dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), L.count);
+      hipLaunchKernelGGL((k_gemm_dl<MODE, 128, 128, 32, 32>), grid, dim3(1024), 0, st, L);
+      return hipGetLastError();
+    }
+  }
+  return launch_gemm_mode<T, MODE, false>(L, L.count, max_m, max_n, st);
+}
+
 template <typename T>
 hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st) {
   if (L.count <= 0 || max_m <= 0 || max_n <= 0) return hipSuccess;
@@ -2140,10 +2247,10 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
           ndl = nfast;
           if (tier == kTierSmall) {
             dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), ndl);
-            hipLaunchKernelGGL((k_gemm_dl<64, 64, 32, 32>), grid, dim3(256), 0, st, L);
+            hipLaunchKernelGGL((k_gemm_dl<GEMM_EXPLICIT, 64, 64, 32, 32>), grid, dim3(256), 0, st, L);
           } else {
             dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
-            hipLaunchKernelGGL((k_gemm_dl<128, 128, 32, 32>), grid, dim3(1024), 0, st, L);
+            hipLaunchKernelGGL((k_gemm_dl<GEMM_EXPLICIT, 128, 128, 32, 32>), grid, dim3(1024), 0, st, L);
           }
           hipError_t e = hipGetLastError();
           if (e != hipSuccess) return e;
@@ -2161,6 +2268,14 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
       return launch_gemm_mode<T, GEMM_LU_TRAILING, false>(L, L.count, max_m, max_n, st);
     case GEMM_TRTRI_STEP1:
       return launch_gemm_mode<T, GEMM_TRTRI_STEP1, false>(L, L.count, max_m, max_n, st);
+    case GEMM_RLU_A:
+      return launch_gemm_rlu<T, GEMM_RLU_A>(L, max_m, max_n, st);
+    case GEMM_RLU_B:
+      return launch_gemm_rlu<T, GEMM_RLU_B>(L, max_m, max_n, st);
+    case GEMM_RLU_C:
+      return launch_gemm_rlu<T, GEMM_RLU_C>(L, max_m, max_n, st);
+    case GEMM_RLU_D:
+      return launch_gemm_rlu<T, GEMM_RLU_D>(L, max_m, max_n, st);
     default:
       return launch_gemm_mode<T, GEMM_TRTRI_STEP2, false>(L, L.count, max_m, max_n, st);
   }
@@ -2176,6 +2291,51 @@ hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, hipStream_
     if (grid > 0) hipLaunchKernelGGL((k_lu_step<T>), dim3(grid, count), dim3(256), 0, st, d_items, t0);
   }
   return hipGetLastError();
+}
+
+// Recursive LU with inverted factors.  For a node of order 2h at origin o,
+// with P1 A11 = L11 U11 and P2 S = L22 U22 (S = A22 - L21 U12 the Schur
+// complement of the first half):
+//   U12 = L11^{-1} P1 A12,  L21 = A21 U11^{-1},  S = A22 - L21 U12,
+//   L^{-1} = [[L11^{-1}, 0], [-L22^{-1} P2 L21 L11^{-1}, L22^{-1}]],
+//   U^{-1} = [[U11^{-1}, -U11^{-1} U12 U22^{-1}], [0, U22^{-1}]],
+// and P = diag(P1, P2).  Every step is a product on MFMA; the recursion ends
+// at kTile x kTile diagonal tiles factored (pivoting inside the tile) and
+// inverted by one wavefront.  The result is the packed form the triangular
+// inversion would leave (L^{-1} below the diagonal, U^{-1} on and above it)
+// together with perm, so no triangular inversion follows.  Needs b =
+// kTile * 2^m and a b x b shadow in LuItem::tmp.
+template <typename T>
+hipError_t getrf_rec_node(const LuItem* d_items, int count, int o, int n, hipStream_t st) {
+  if (n <= kTile) {
+    hipLaunchKernelGGL((k_tile_lu_inv<T>), dim3(count), dim3(64), 0, st, d_items, o);
+    return hipGetLastError();
+  }
+  const int h = n / 2;
+  hipError_t e = getrf_rec_node<T>(d_items, count, o, h, st);
+  if (e != hipSuccess) return e;
+  GemmLaunch L{};
+  L.elem = sizeof(T);
+  L.items = d_items;
+  L.j = o;
+  L.s = h;
+  L.tri = 1;
+  L.count = 2 * count;
+  L.mode = GEMM_RLU_A;
+  if ((e = launch_gemm<T>(L, h, h, st)) != hipSuccess) return e;
+  L.mode = GEMM_RLU_B;
+  if ((e = launch_gemm<T>(L, h, h, st)) != hipSuccess) return e;
+  if ((e = getrf_rec_node<T>(d_items, count, o + h, h, st)) != hipSuccess) return e;
+  L.mode = GEMM_RLU_C;
+  if ((e = launch_gemm<T>(L, h, h, st)) != hipSuccess) return e;
+  L.mode = GEMM_RLU_D;
+  L.count = count;
+  return launch_gemm<T>(L, h, h, st);
+}
+
+template <typename T>
+hipError_t launch_getrf_rec(const LuItem* d_items, int count, int b, hipStream_t st) {
+  return getrf_rec_node<T>(d_items, count, 0, b, st);
 }
 
 template <typename T>
@@ -2260,6 +2420,8 @@ template hipError_t launch_gemm<double>(const GemmLaunch&, int, int, hipStream_t
 template hipError_t launch_gemm<float>(const GemmLaunch&, int, int, hipStream_t);
 template hipError_t launch_getrf<double>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_getrf_tile<double>(const LuItem*, int, int, hipStream_t);
+template hipError_t launch_getrf_rec<double>(const LuItem*, int, int, hipStream_t);
+template hipError_t launch_getrf_rec<float>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_getrf_tile<float>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_getrf<float>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_trtri<double>(const LuItem*, int, int, bool, hipStream_t);

@@ -128,16 +128,19 @@ class Builder {
   void factor_and_solve(const std::vector<int>& lu, const std::vector<Opnd>& rhs, const std::vector<Opnd>& xdst,
                         bool count_schur) {
     const size_t n = lu.size();
+    // The scratch block of the triangular inversion is also the shadow of
+    // the recursive LU, so it is taken before the factorisation.
+    std::vector<int> tmp(n);
+    for (size_t t = 0; t < n; ++t) tmp[t] = pool_.alloc();
     Step& g = step(ST_GETRF);
     for (size_t t = 0; t < n; ++t) {
       StepItem it;
       it.dst = Opnd::slot(lu[t]);
+      it.x = Opnd::slot(tmp[t]);
       it.node = next_node();
       g.items.push_back(it);
       if (count_schur) plan_.schur_ops++;
     }
-    std::vector<int> tmp(n);
-    for (size_t t = 0; t < n; ++t) tmp[t] = pool_.alloc();
     Step& tr = step(ST_TRTRI);
     for (size_t t = 0; t < n; ++t) {
       StepItem it;
@@ -322,16 +325,17 @@ class Builder {
 
  public:
   void factor_only(const std::vector<int>& lu) {
+    std::vector<int> tmp;
+    for (size_t t = 0; t < lu.size(); ++t) tmp.push_back(pool_.alloc());
     Step& g = step(ST_GETRF);
-    for (int s : lu) {
+    for (size_t t = 0; t < lu.size(); ++t) {
       StepItem it;
-      it.dst = Opnd::slot(s);
+      it.dst = Opnd::slot(lu[t]);
+      it.x = Opnd::slot(tmp[t]);
       it.node = next_node();
       g.items.push_back(it);
       plan_.schur_ops++;
     }
-    std::vector<int> tmp;
-    for (size_t t = 0; t < lu.size(); ++t) tmp.push_back(pool_.alloc());
     Step& tr = step(ST_TRTRI);
     for (size_t t = 0; t < lu.size(); ++t) {
       StepItem it;
@@ -368,13 +372,14 @@ class Builder {
   // Inverse of the matrix in slot z written to dst: getrf, triangular
   // inversion, then U^{-1} (L^{-1} P I).
   void final_inverse(int z, Opnd dst, bool count_final) {
+    int tmp = pool_.alloc();
     Step& g = step(ST_GETRF);
     StepItem it;
     it.dst = Opnd::slot(z);
+    it.x = Opnd::slot(tmp);
     it.node = next_node();
     g.items.push_back(it);
     if (count_final) plan_.final_inversions++;
-    int tmp = pool_.alloc();
     Step& tr = step(ST_TRTRI);
     StepItem t1;
     t1.dst = Opnd::slot(z);
@@ -438,12 +443,12 @@ void account(Plan& p) {
         p.launches += 1;
         break;
       case ST_GETRF:
-        p.launches += getrf_launches(p.b, true);
+        p.launches += getrf_launches(p.b, lu_kind(static_cast<int>(n), p.b, false, true, 0));
         p.executed_flops += n * getrf_flops(p.b);
         break;
       case ST_TRTRI:
-        p.launches += trtri_launches(p.b, true);
-        p.executed_flops += n * trtri_flops(p.b);
+        p.launches += trtri_launches(p.b, lu_kind(static_cast<int>(n), p.b, false, true, 0));
+        p.executed_flops += n * trtri_flops(p.b);  // the recursive LU forms the inverses itself
         break;
       case ST_TRMM_L:
       case ST_TRMM_U:
@@ -460,7 +465,10 @@ void account(Plan& p) {
 
 }  // namespace
 
-int64_t getrf_launches(int b, bool tile_pivoting) {
+int64_t getrf_launches(int b, LuKind kind) {
+  // recursive: one launch per diagonal tile, four per inner node
+  if (kind == LU_RECURSIVE) return b / kTile + 4 * (b / kTile - 1);
+  const bool tile_pivoting = kind == LU_TILE;
   if (tile_pivoting) return 1 + (b > kTile ? (b + kTile - 1) / kTile : 0);  // first tile, one launch per tile
   int64_t n = 0;
   for (int j = 0; j < b;) {
@@ -473,8 +481,9 @@ int64_t getrf_launches(int b, bool tile_pivoting) {
   return n;
 }
 
-int64_t trtri_launches(int b, bool tile_pivoting) {
-  int64_t n = tile_pivoting ? 0 : 1;  // diagonal tiles (left inverted by the tile-pivoting LU)
+int64_t trtri_launches(int b, LuKind kind) {
+  if (kind == LU_RECURSIVE) return 0;
+  int64_t n = kind == LU_TILE ? 0 : 1;  // diagonal tiles (left inverted by the tile-pivoting LU)
   for (int s = kTrtriTile; s < b; s *= 2) n += 2;
   return n;
 }

@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the block recursive inverse on one MI355X.
 
-One step = one ``invert_block`` call on the n = 4096, k = 4 workload
-(b = 1024, Q Lam Q^T with Lam log-uniform in [1, 100], Haar Q, seed 2),
-FP64, target block (0, 0), inputs resident in HBM.  The throughput is the
-algorithmic flop count of one block,
+Headline step = one ``invert_block`` call on the precision workload
+spd_n16384_k8: n = 16384, k = 8 (b = 2048), M = Q Lam Q^T with Haar Q and
+cond(M) = 1e4 (eigenvalues log-uniform, endpoints pinned), target block
+(0, 0), FP64, inputs resident in HBM.  The throughput is the algorithmic
+flop count of one block,
     F = T(k) (14/3) b^3 + 2 b^3 (+ 2 b^3 for an off-diagonal block),
     T(k) = (4^(k-1) - 1) / 3 Schur operations (Theorem "C_BRI"),
-divided by the measured time.  The line also carries variants (the
-off-diagonal target, FP32, the n = 256, k = 2 latency case), the roofline of
-the dominant kernel (HIP events around every plan step, summed per kernel
-role) and the FP64 CPU oracle timed on the host cores.
+divided by the measured time.  Beside it, on the same matrix, the mixed
+paths (split FP16 / BF16 MFMA products with FP64 refinement) with their
+relative errors against the closed-form inverse block and their speed
+relative to FP64.  The line also carries the roofline of the dominant kernel
+(HIP events around every plan step, summed per kernel family), the FP64 CPU
+oracle timed on the host cores on a sample of the same workload, and further
+workloads (n = 4096, k = 4; n = 256, k = 2; 512 batched problems; the
+n = 8192 adjoint) as variants.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -18,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +38,8 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "f16": 2500.0, "bf16": 2500.0}
 HBM_PEAK_GBS = 8000.0
 KIND_NAMES = {1: "load", 2: "getrf", 3: "trtri", 4: "trmm_lower", 5: "trmm_upper", 6: "gemm_schur",
               7: "gemm_acc", 8: "gemm_neg"}
+PRODUCT_KINDS = (4, 5, 6, 7, 8)
+FACTOR_KINDS = (2, 3)
 
 
 class ProfEntry(ctypes.Structure):
@@ -47,16 +55,15 @@ def profile_read(lib):
     return {t: (arr[t].steps, arr[t].launches, arr[t].ms, arr[t].flops) for t in range(1, n)}
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_gemm_explicit_hbm_traffic_spd_n4096_k4_f64.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_gemm_dl_explicit_hbm_traffic_spd_n16384_k8_f64.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1612_00001_amd", "csrc", "bri_kernels.hip")
 
 
 def gemm_source_digest():
-    """sha256 over the source of the product kernel: its operand loaders and
-    kernel bodies, register-staged and direct-to-LDS (from the "Operand
-    tiles." section to the low-precision kernel) and its tile-shape selection
-    (launch_gemm_mode, launch_gemm)."""
-    import hashlib
+    """sha256 over the source of the explicit-item product kernel: its
+    operand loaders and kernel bodies, register-staged and direct-to-LDS (from
+    the "Operand tiles." section to the low-precision kernel) and its
+    tile-shape selection (launch_gemm_mode, launch_gemm)."""
     text = open(KERNEL_SOURCE).read()
     a = text.index("// Operand tiles.")
     e = text.index("// Low-precision products")
@@ -68,7 +75,7 @@ def gemm_source_digest():
 
 
 def counted_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
+    """HBM bytes per launch of the product kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size),
     or None when the summary is missing or the kernel source has changed
     since the counters were taken."""
@@ -92,6 +99,9 @@ def rel_err(a, b):
 
 
 def time_calls(fn, steps, warmup, torch):
+    """Mean ms per call over ``steps`` calls after ``warmup`` untimed ones:
+    HIP events on the current stream (the one the library enqueues on),
+    with a device synchronisation on both sides of the timed region."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -107,61 +117,29 @@ def time_calls(fn, steps, warmup, torch):
     return ev0.elapsed_time(ev1) / steps, wall
 
 
-def precision_workload(bri, workloads, torch, np) -> int:
-    """n = 16384, k = 8 (b = 2048), Q Lam Q^T with cond 1e4 (generated on the
-    device, same recipe as the host generator), block (0,0): the plain FP64
-    path and the mixed paths, each timed once, against a dense FP64 solve of
-    M X = E_0 on the device (torch.linalg.solve, not this library)."""
-    wl = workloads.WORKLOADS["spd_n16384_k8"]
-    n, k = wl.n, wl.k
-    i, j = wl.targets[0]
-    b = bri.block_size(n, k)
-    dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    M = workloads.haar_spd_device(n, wl.seed, 0.0, 4.0, pin_endpoints=True, device=dev)
-    torch.cuda.synchronize()
-    gen_s = time.perf_counter() - t0
-    e = torch.zeros(n, b, dtype=torch.float64, device=dev)
-    e[j * b:(j + 1) * b] = torch.eye(b, dtype=torch.float64, device=dev)
-    ref = torch.linalg.solve(M, e)[i * b:(i + 1) * b].contiguous()
-    del e
-    torch.cuda.synchronize()
-    flops = bri.plan_describe(n, k, i, j, "f64")["algorithmic_flops"]
-    runs = []
-    for prec, reuse in (("f64", False), ("mixed_f16", False), ("mixed_bf16", False), ("mixed_f32", False),
-                        ("f64", True), ("mixed_f16", True), ("mixed_bf16", True)):
-        info = torch.zeros(1, dtype=torch.int32, device=dev)
-        ws = torch.empty(bri.workspace_size(n, k, i, j, prec, reuse=reuse), dtype=torch.uint8, device=dev)
-        print(f"precision workload: {prec} reuse={reuse}", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        out = bri.invert_block(M, k, i, j, precision=prec, info=info, workspace=ws, reuse=reuse)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        err = float(torch.linalg.norm(out - ref) / torch.linalg.norm(ref))
-        sweeps = bri.refine_last()[0] if prec.startswith("mixed") else 0
-        runs.append({"precision": prec, "reuse_pivots": reuse, "s": dt, "paper_equivalent_tflops": flops / dt / 1e12,
-                     "rel_error_vs_dense_solve": err,
-                     "refine_sweeps": sweeps, "info": int(info.item()), "workspace_bytes": ws.numel()})
-        print(json.dumps(runs[-1]), file=sys.stderr, flush=True)
-        del ws, out
-    print(json.dumps({"workload": "spd_n16384_k8: n=16384 k=8 b=2048, Q Lam Q^T, cond 1e4 (Lam pinned at 1 and 1e4), "
-                                  "block (0,0), matrix generated on the device",
-                      "algorithmic_flops": flops, "generation_s": gen_s, "runs": runs}), flush=True)
-    return 0
+def family_roofline(prof, kinds, steps, name, flops_note):
+    ms = sum(prof[t][2] for t in kinds if t in prof)
+    fl = sum(prof[t][3] for t in kinds if t in prof)
+    la = sum(prof[t][1] for t in kinds if t in prof)
+    achieved = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS["f64"], "ms_per_step": ms / steps, "launches_per_step": la / steps,
+            "avg_launch_ms": (ms / la) if la else None, "flops_per_launch": (fl / la) if la else None,
+            "algorithmic_flops": flops_note}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
-    ap.add_argument("--precision-workload", action="store_true",
-                    help="run only the n=16384, k=8 (cond 1e4) precision workload once per precision and exit")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the FP64 headline calls (no profiled pass, no reference, no other workloads)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -188,18 +166,10 @@ def main() -> int:
     import paper_1612_00001_amd as bri
     import workloads
 
-    if args.precision_workload:
-        return precision_workload(bri, workloads, torch, np)
-
     dev = torch.device("cuda:0")
     lib = bri.lib()
-    wl = workloads.WORKLOADS["spd_n4096_k4"]
-    n, k = wl.n, wl.k
-    m_host = workloads.workload_matrix(wl.name)
-    M64 = torch.from_numpy(m_host).to(dev)
-    M32 = M64.float()
 
-    def setup(M, i, j, precision, reuse=False):
+    def setup(M, n, k, i, j, precision, reuse=False):
         need = bri.workspace_size(n, k, i, j, precision, reuse=reuse)
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
         b = bri.block_size(n, k)
@@ -208,67 +178,105 @@ def main() -> int:
 
         def call():
             bri.invert_block(M, k, i, j, precision=precision, out=out, info=info, workspace=ws, reuse=reuse)
-        return call, out, info
+        return call, out, info, ws
 
-    # ---- headline: FP64, block (0, 0) ------------------------------------
+    # ---- headline: spd_n16384_k8, FP64, block (0, 0) -------------------------
+    wl = workloads.WORKLOADS["spd_n16384_k8"]
+    n, k = wl.n, wl.k
     i, j = wl.targets[0]
+    b = bri.block_size(n, k)
+    print("generating spd_n16384_k8 on the device", file=sys.stderr, flush=True)
+    M3, q, lam = workloads.haar_spd_device(n, wl.seed, 0.0, 4.0, pin_endpoints=True, device=dev,
+                                           return_factors=True)
+    # Reference block from the matrix's known inverse Q Lam^{-1} Q^T (torch,
+    # FP64; not this library): N_00 = Q[0:b] Lam^{-1} Q[0:b]^T.
+    qb = q[i * b:(i + 1) * b].contiguous()
+    del q
+    ref = ((qb * torch.from_numpy(1.0 / lam).to(dev)[None, :]) @ qb.T.contiguous()).cpu().numpy()
+    del qb
+    torch.cuda.synchronize()
     stats = bri.plan_describe(n, k, i, j, "f64")
     flops = stats["algorithmic_flops"]
-    call, out, info = setup(M64, i, j, "f64")
-    for _ in range(args.warmup):
-        call()
-    torch.cuda.synchronize()
-    # Timed steps without instrumentation, then the same steps again with HIP
-    # events around every plan step for the per-kernel breakdown.
-    ms, wall_ms = time_calls(call, args.steps, 0, torch)
-    lib.bri_profile_enable(1)
-    profile_read(lib)  # clear
-    prof_ms, _ = time_calls(call, args.steps, 0, torch)
-    prof = profile_read(lib)
-    lib.bri_profile_enable(0)
-    assert int(info.item()) == 0, "device status"
-    got = out.cpu().numpy()
-
+    call, out, info, ws = setup(M3, n, k, i, j, "f64")
+    print(f"headline: FP64 n={n} k={k}, {args.warmup} warm-up + {args.steps} timed calls", file=sys.stderr,
+          flush=True)
+    ms, wall_ms = time_calls(call, args.steps, args.warmup, torch)
     value = flops / (ms * 1e-3) / 1e12
-    breakdown = {}
-    for t, (st, la, pms, pfl) in prof.items():
-        if st:
-            breakdown[KIND_NAMES[t]] = {"ms_per_step": pms / args.steps, "launches_per_step": la / args.steps,
-                                        "tflops": (pfl / (pms * 1e-3) / 1e12) if pms > 0 else None}
-    # Dominant kernel: the MFMA product kernel in its explicit-item instance
-    # (triangular products and Schur updates, one launch per plan step).
-    prod_kinds = (4, 5, 6, 7, 8)
-    p_ms = sum(prof[t][2] for t in prod_kinds if t in prof)
-    p_fl = sum(prof[t][3] for t in prod_kinds if t in prof)
-    p_la = sum(prof[t][1] for t in prod_kinds if t in prof)
-    achieved = p_fl / (p_ms * 1e-3) / 1e12 if p_ms > 0 else 0.0
-    roofline = {
-        "kernel": "explicit-item FP64 products (Schur and triangular): k_gemm_dl (direct-to-LDS loads, 128x128 tiles) "
-                  "where every item of a step has stored, aligned operands, else k_gemm<double, GEMM_EXPLICIT> "
-                  "(128x256, 128x128 or 64x64 tiles)",
-        "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
-        "frac": achieved / PEAK_TFLOPS["f64"], "traffic": counted_traffic(),
-        "launches_per_step": p_la / args.steps, "avg_launch_ms": (p_ms / p_la) if p_la else None,
-        "flops_per_launch": (p_fl / p_la) if p_la else None,
-    }
-
     line = {
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "spd_n4096_k4: n=4096 k=4 b=1024, block (0,0), Q Lam Q^T, Lam in [1,100]",
-                   "n": n, "k": k, "b": stats["block"], "block": [i, j], "precision": "f64",
+        "config": {"workload": "spd_n16384_k8: n=16384 k=8 b=2048, block (0,0), Q Lam Q^T, cond 1e4",
+                   "n": n, "k": k, "b": b, "block": [i, j], "precision": "f64",
                    "concurrency": stats["batch_width"]},
         "pct_fp64_mfma_peak": 100.0 * value / PEAK_TFLOPS["f64"],
-        "wall_ms_per_step": wall_ms, "profiled_ms_per_step": prof_ms,
+        "wall_ms_per_step": wall_ms,
         "schur_ops": stats["schur_ops"], "algorithmic_flops": flops, "executed_flops": stats["executed_flops"],
+        "executed_tflops": stats["executed_flops"] / (ms * 1e-3) / 1e12,
         "workspace_bytes": stats["workspace_bytes"], "workspace_blocks": stats["slots"],
+        "workspace_over_M": stats["workspace_bytes"] / (8.0 * n * n),
         "kernel_launches_per_step": stats["kernel_launches"],
-        "roofline": roofline, "breakdown": breakdown,
     }
+    if args.headline_only:
+        print(json.dumps(line), flush=True)
+        return 0
 
-    # ---- CPU baseline (the FP64 oracle) -------------------------------------
-    ref = None
+    # One more call with HIP events around every plan step (per-kernel-family
+    # times on the library's stream), then the result against the reference.
+    lib.bri_profile_enable(1)
+    profile_read(lib)  # clear
+    prof_ms, _ = time_calls(call, 1, 0, torch)
+    prof = profile_read(lib)
+    lib.bri_profile_enable(0)
+    assert int(info.item()) == 0, "device status"
+    got = out.cpu().numpy()
+    line["rel_error"] = rel_err(got, ref)
+    line["rel_error_reference"] = "closed form Q[0:b] Lam^-1 Q[0:b]^T of the generated matrix (torch FP64)"
+    line["profiled_ms_per_step"] = prof_ms
+    breakdown = {}
+    for t, (st, la, pms, pfl) in prof.items():
+        if st:
+            breakdown[KIND_NAMES[t]] = {"ms_per_step": pms, "launches_per_step": la,
+                                        "tflops": (pfl / (pms * 1e-3) / 1e12) if pms > 0 else None}
+    line["breakdown"] = breakdown
+    # Dominant kernel family: the explicit-item products (triangular
+    # multiplies and Schur products; one launch per plan step) or the
+    # factorisation of the pivot blocks, whichever takes longer.
+    prods = family_roofline(prof, PRODUCT_KINDS, 1,
+                            "k_gemm_dl<GEMM_EXPLICIT, 128, 128, 32, 32> (direct-to-LDS FP64 products: "
+                            "triangular multiplies and Schur products of a plan step)",
+                            "b^3 per triangular multiply, 2 b^3 per Schur product")
+    prods["traffic"] = counted_traffic()
+    facts = family_roofline(prof, FACTOR_KINDS, 1,
+                            "pivot-block LU: recursive LU with inverted factors (k_tile_lu_inv + "
+                            "k_gemm_dl<GEMM_RLU_*>) or tile steps (k_lu_step) + triangular inversion",
+                            "2/3 b^3 per factorisation (section 8(d)); the inverses of the factors are "
+                            "executed work on top")
+    facts["traffic"] = None
+    if prods["ms_per_step"] >= facts["ms_per_step"]:
+        line["roofline"], line["roofline_secondary"] = prods, facts
+    else:
+        line["roofline"], line["roofline_secondary"] = facts, prods
+
+    # ---- mixed precisions on the same matrix ---------------------------------
+    del ws
+    variants = []
+    if not args.no_mixed:
+        for prec in ("mixed_f16", "mixed_bf16"):
+            print(f"mixed {prec} n={n} k={k}", file=sys.stderr, flush=True)
+            c2, o2, inf2, ws2 = setup(M3, n, k, i, j, prec)
+            vms, _ = time_calls(c2, 1, 1, torch)
+            sweeps, last = bri.refine_last()
+            st2 = bri.plan_describe(n, k, i, j, prec)
+            variants.append({"workload": "spd_n16384_k8", "block": [i, j], "precision": prec, "ms_per_step": vms,
+                             "tflops": flops / (vms * 1e-3) / 1e12, "speed_vs_f64": ms / vms,
+                             "rel_error": rel_err(o2.cpu().numpy(), ref), "refine_sweeps": sweeps,
+                             "last_rel_correction": last, "info": int(inf2.item()),
+                             "workspace_bytes": st2["workspace_bytes"],
+                             "workspace_over_M": st2["workspace_bytes"] / (8.0 * n * n)})
+            del ws2, o2
+
+    # ---- CPU baseline: the FP64 oracle on a sample of the same workload -------
     if not args.no_cpu_baseline:
         import oracle
         try:
@@ -276,61 +284,71 @@ def main() -> int:
             cores = sum(x.get("num_threads", 0) for x in threadpool_info() if x.get("user_api") == "blas")
         except Exception:  # threadpoolctl missing: report the process's CPU count
             cores = os.cpu_count()
+        m_host = M3.cpu().numpy()
+        # v(0, 0, {1, 2, 3, 4}): one depth-4 node of the recursion for block
+        # (0, 0), T(5) = 85 Schur operations of order 2048 (of the 5461 of
+        # the whole step), same recursion and same blocks as the step.
+        depth = 4
+        counter = oracle.OpCounter()
         t0 = time.perf_counter()
-        ref = oracle.invert_block(m_host, k, i, j)
+        oracle.principal_value(m_host, b, 0, 0, list(range(1, depth + 1)), counter)
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-                                "sample": f"the whole step: oracle recursion for block ({i},{j}) of the "
-                                          f"n={n}, k={k} workload ({stats['schur_ops']} Schur operations), "
-                                          f"{dt:.2f} s"}
-        line["rel_error"] = rel_err(got, ref)
+        sflops = counter.schur * (14.0 / 3.0) * float(b) ** 3
+        line["cpu_baseline"] = {"value": sflops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+                                "sample": f"oracle value v(0,0,{{1..{depth}}}) of the spd_n16384_k8 matrix: "
+                                          f"{counter.schur} Schur operations of order {b} (the step has "
+                                          f"{stats['schur_ops']}), {dt:.1f} s; rate = their (14/3) b^3 flops "
+                                          f"per second; the whole step would take about "
+                                          f"{dt * stats['schur_ops'] / counter.schur:.0f} s"}
+        del m_host
 
-    # ---- variants -------------------------------------------------------------
+    del M3
+
+    # ---- n = 4096, k = 4 workload -----------------------------------------------
     if not args.no_variants:
-        variants = []
-        import oracle
-        refs = {(i, j): ref}
-        for (vi, vj, prec) in [(1, 2, "f64"), (0, 0, "f32"), (1, 2, "f32")]:
-            M = M64 if prec == "f64" else M32
-            st = bri.plan_describe(n, k, vi, vj, prec)
-            c2, o2, inf2 = setup(M, vi, vj, prec)
-            vms, _ = time_calls(c2, args.steps, args.warmup, torch)
-            entry = {"block": [vi, vj], "precision": prec, "ms_per_step": vms,
-                     "tflops": st["algorithmic_flops"] / (vms * 1e-3) / 1e12,
-                     "pct_mfma_peak": 100.0 * st["algorithmic_flops"] / (vms * 1e-3) / 1e12 / PEAK_TFLOPS[prec]}
-            if not args.no_cpu_baseline:
-                if refs.get((vi, vj)) is None:
-                    refs[(vi, vj)] = oracle.invert_block(m_host, k, vi, vj)
-                entry["rel_error"] = rel_err(o2.double().cpu().numpy(), refs[(vi, vj)])
+        wl2 = workloads.WORKLOADS["spd_n4096_k4"]
+        n2, k2 = wl2.n, wl2.k
+        spd2 = workloads.haar_spd(n2, wl2.seed, 0.0, 2.0)
+        m2 = spd2.m
+        b2 = bri.block_size(n2, k2)
+        M64 = torch.from_numpy(m2).to(dev)
+        M32 = M64.float()
+        refs = {}
+        f64_ms = None
+        for (vi, vj, prec, reuse) in [(0, 0, "f64", False), (1, 2, "f64", False), (0, 0, "f32", False),
+                                      (1, 2, "f32", False), (0, 0, "mixed_f32", False), (0, 0, "mixed_f16", False),
+                                      (0, 0, "mixed_bf16", False), (0, 0, "f64", True), (0, 0, "mixed_f16", True)]:
+            M = M32 if prec == "f32" else M64
+            st = bri.plan_describe(n2, k2, vi, vj, prec, reuse=reuse)
+            c2, o2, inf2, ws2 = setup(M, n2, k2, vi, vj, prec, reuse=reuse)
+            mixed = prec.startswith("mixed")
+            vms, _ = time_calls(c2, 3 if mixed else 10, 1 if mixed else 3, torch)
+            if prec == "f64" and not reuse and (vi, vj) == (0, 0):
+                f64_ms = vms
+            entry = {"workload": "spd_n4096_k4: n=4096 k=4 b=1024, Q Lam Q^T, Lam in [1,100]", "block": [vi, vj],
+                     "precision": prec, "ms_per_step": vms, "info": int(inf2.item()),
+                     "executed_tflops": st["executed_flops"] / (vms * 1e-3) / 1e12}
+            if reuse:
+                # the paper's suggested reuse across branches: fewer executed
+                # operations; F / time is then not a throughput
+                entry["reuse_pivots"] = True
+                entry["paper_equivalent_tflops"] = st["algorithmic_flops"] / (vms * 1e-3) / 1e12
+            else:
+                entry["tflops"] = st["algorithmic_flops"] / (vms * 1e-3) / 1e12
+                if not mixed:
+                    entry["pct_mfma_peak"] = 100.0 * entry["tflops"] / PEAK_TFLOPS[prec]
+            if mixed:
+                entry["refine_sweeps"], entry["last_rel_correction"] = bri.refine_last()
+            if f64_ms is not None and (mixed or reuse):
+                entry["speed_vs_f64"] = f64_ms / vms
+            if (vi, vj) not in refs:
+                # block of the known inverse Q Lam^{-1} Q^T of this matrix
+                qr_ = spd2.q[vi * b2:(vi + 1) * b2]
+                qc_ = spd2.q[vj * b2:(vj + 1) * b2]
+                refs[(vi, vj)] = (qr_ / spd2.lam[None, :]) @ qc_.T
+            entry["rel_error"] = rel_err(o2.double().cpu().numpy(), refs[(vi, vj)])
             variants.append(entry)
-        # mixed precision on the same workload: float recursion (FP32, split
-        # FP16 or split BF16 MFMA products) with FP64 refinement of the block
-        # column; value = F / time including refinement (extra work not credited)
-        f64_ms = ms
-        for prec in ("mixed_f32", "mixed_f16", "mixed_bf16"):
-            c2, o2, inf2 = setup(M64, i, j, prec)
-            vms, _ = time_calls(c2, max(1, args.steps // 3), 1, torch)
-            sweeps, last = bri.refine_last()
-            entry = {"block": [i, j], "precision": prec, "ms_per_step": vms,
-                     "tflops": flops / (vms * 1e-3) / 1e12, "speed_vs_f64": f64_ms / vms,
-                     "refine_sweeps": sweeps, "last_rel_correction": last, "info": int(inf2.item())}
-            if not args.no_cpu_baseline:
-                entry["rel_error"] = rel_err(o2.cpu().numpy(), refs[(i, j)])
-            variants.append(entry)
-        # the paper's suggested reuse across branches (elimination pivots kept
-        # and factored once); value still counts the paper's operations F
-        for prec in ("f64", "mixed_f16"):
-            c2, o2, inf2 = setup(M64, i, j, prec, reuse=True)
-            vms, _ = time_calls(c2, max(1, args.steps // 3), 1, torch)
-            entry = {"block": [i, j], "precision": prec, "reuse_pivots": True, "ms_per_step": vms,
-                     "paper_equivalent_tflops": flops / (vms * 1e-3) / 1e12, "speed_vs_f64": f64_ms / vms,
-                     "executed_flops": bri.plan_describe(n, k, i, j, prec, reuse=True)["executed_flops"],
-                     "info": int(inf2.item())}
-            if prec.startswith("mixed"):
-                entry["refine_sweeps"] = bri.refine_last()[0]
-            if not args.no_cpu_baseline:
-                entry["rel_error"] = rel_err(o2.cpu().numpy(), refs[(i, j)])
-            variants.append(entry)
+            del ws2
         # latency case n = 256, k = 2 (FP64)
         m1 = workloads.workload_matrix("dd_n256_k2")
         M1 = torch.from_numpy(m1).to(dev)
@@ -338,13 +356,14 @@ def main() -> int:
         o1 = torch.empty(128, 128, dtype=torch.float64, device=dev)
         w1 = torch.empty(bri.workspace_size(256, 2, 0, 0), dtype=torch.uint8, device=dev)
         c1 = lambda: bri.invert_block(M1, 2, 0, 0, out=o1, workspace=w1)  # noqa: E731
-        ms1, _ = time_calls(c1, 50, 5, torch)
+        ms1, wall1 = time_calls(c1, 50, 5, torch)
         e1 = {"workload": "dd_n256_k2: n=256 k=2 b=128 block (0,0), Gaussian + nI", "precision": "f64",
-              "us_per_call": ms1 * 1e3, "tflops": st1["algorithmic_flops"] / (ms1 * 1e-3) / 1e12}
-        if not args.no_cpu_baseline:
-            e1["rel_error"] = rel_err(o1.cpu().numpy(), oracle.invert_block(m1, 2, 0, 0))
+              "us_per_call": ms1 * 1e3, "wall_us_per_call": wall1 * 1e3,
+              "tflops": st1["algorithmic_flops"] / (ms1 * 1e-3) / 1e12}
+        e1["rel_error"] = rel_err(o1.cpu().numpy(), np.linalg.inv(m1)[:128, :128])
         variants.append(e1)
-        line["variants"] = variants
+        del M64, M32
+    line["variants"] = variants
 
     # ---- batched workload: 512 problems, n in [64, 1024], k in {2,3,4} ---------
     if not args.no_batched:
@@ -356,14 +375,14 @@ def main() -> int:
         dense = {}
         for t in sample:
             p = probs[t]
-            b = bri.block_size(p.n, p.k)
-            g = np.eye(p.k * b)
+            bb = bri.block_size(p.n, p.k)
+            g = np.eye(p.k * bb)
             g[:p.n, :p.n] = mats[t]
-            dense[t] = np.linalg.inv(g)[p.i * b:(p.i + 1) * b, p.j * b:(p.j + 1) * b]
+            dense[t] = np.linalg.inv(g)[p.i * bb:(p.i + 1) * bb, p.j * bb:(p.j + 1) * bb]
         batched = []
         for prec in ("mixed_f32", "f64", "f32"):
-            dt = torch.float32 if prec == "f32" else torch.float64
-            Ms = [torch.from_numpy(m).to(dev, dt) for m in mats]
+            dt_ = torch.float32 if prec == "f32" else torch.float64
+            Ms = [torch.from_numpy(m).to(dev, dt_) for m in mats]
             binfo = torch.zeros(len(probs), dtype=torch.int32, device=dev)
             outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo)
             torch.cuda.synchronize()

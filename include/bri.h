@@ -72,8 +72,19 @@ typedef enum {
 /* Pivoting of the b x b pivot factorisations (the method itself never
  * pivots across blocks: every pivot is a principal Schur complement). */
 typedef enum {
-  BRI_PIVOT_TILE = 0,   /* partial pivoting inside each 32-row diagonal tile (default) */
-  BRI_PIVOT_PANEL = 1   /* partial pivoting over all rows of the pivot block (LAPACK getrf) */
+  BRI_PIVOT_TILE = 0,   /* partial pivoting inside each 32-row diagonal tile.  Stable
+                           for SPD and diagonally dominant matrices (whose pivot
+                           blocks, principal Schur complements, stay such).  A
+                           factorisation whose largest |U| exceeds 64 times its
+                           largest |A| (element growth; partial pivoting keeps this
+                           ratio near 10 on Gaussian matrices) is reported through
+                           d_info like a failed pivot.                            */
+  BRI_PIVOT_PANEL = 1,  /* partial pivoting over all rows of the pivot block (LAPACK getrf) */
+  BRI_PIVOT_AUTO = 2    /* default: tile pivoting; the call then waits for the stream
+                           and, if a factorisation reported a failed pivot or element
+                           growth, computes the block again with panel pivoting
+                           (batched calls: the flagged problems, one by one, in the
+                           same workspace).  Synchronous.                            */
 } bri_pivoting;
 
 typedef struct {
@@ -98,11 +109,20 @@ typedef struct {
                               diagonal tile) followed by a triangular inversion;
                               2 recursive halving with inverted factors (block
                               orders 32 * 2^m only, else tile steps)              */
+  size_t workspace_budget; /* 0: none.  Otherwise, with automatic concurrency, the
+                              width is the widest one (the automatic width, then
+                              down by factors of 4) whose workspace fits in this
+                              many bytes: fewer Schur operations side by side,
+                              more launches (the memory / time trade-off of
+                              Theorem "MC_BRI").  Size queries return 0 and calls
+                              BRI_ERR_WORKSPACE when even width 1 does not fit.
+                              Batched calls ignore it.                            */
 } bri_opts;
 
-/* Fills *o with defaults: BRI_F64, automatic concurrency, tile pivoting, no
- * reuse, 10 refinement sweeps, tolerance 1e-12, no workspace, no d_info,
- * default stream. */
+/* Fills *o with defaults: BRI_F64, automatic concurrency, automatic pivoting
+ * (BRI_PIVOT_AUTO), no reuse, 10 refinement sweeps, tolerance 1e-12, no
+ * workspace, no d_info, default stream, automatic factorisation, no
+ * workspace budget. */
 void bri_default_opts(bri_opts* o);
 
 /* Bytes of device workspace invert_block() needs for (n, k, i, j) with the
@@ -227,9 +247,12 @@ int bri_profile_enable(int on);
 int bri_profile_read(bri_profile_entry* entries, int cap);
 
 /* Diagnostics of the calling thread's last mixed-precision invert_block:
- * the number of refinement sweeps it ran and the relative size
- * ||dX||_F / ||X||_F of its last correction (0 and 0 before any such call). */
-int bri_refine_last(int* sweeps, double* last_update);
+ * the number of refinement sweeps it ran, the relative size
+ * ||dX||_F / ||X||_F of its last correction, and whether its FP16 split
+ * products met an operand outside the FP16 range and the call was computed
+ * again with BF16 split products (0, 0 and 0 before any such call).  Any
+ * pointer may be NULL. */
+int bri_refine_last(int* sweeps, double* last_update, int* bf16_fallback);
 
 /* Human-readable text for a status code returned by any entry point. */
 const char* bri_status_string(int status);

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbri.so")
 
 PRECISIONS = {"f64": 0, "f32": 1, "mixed_f32": 2, "mixed_f16": 3, "mixed_bf16": 4}
-PIVOTING = {"tile": 0, "panel": 1}
+PIVOTING = {"tile": 0, "panel": 1, "auto": 2}
 FACTORIZATIONS = {"auto": 0, "tile": 1, "recursive": 2}
 _DTYPE_OF = {"f64": torch.float64, "f32": torch.float32, "mixed_f32": torch.float64,
              "mixed_f16": torch.float64, "mixed_bf16": torch.float64}
@@ -44,6 +44,7 @@ class BriOpts(ctypes.Structure):
         ("d_info", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
         ("factorization", ctypes.c_int),
+        ("workspace_budget", ctypes.c_size_t),
     ]
 
 
@@ -111,7 +112,8 @@ _SIGNATURES = [
       ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64,
       ctypes.c_double, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.POINTER(BriOpts)]),
     ("bri_profile_enable", ctypes.c_int, [ctypes.c_int]),
-    ("bri_refine_last", ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
+    ("bri_refine_last", ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int)]),
     ("bri_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("bri_version", ctypes.c_char_p, []),
 ]
@@ -142,8 +144,8 @@ def _check(status: int) -> None:
 
 
 def make_opts(precision: str = "f64", concurrency: int = 0, refine_max_iters: int = 10,
-              refine_tol: float = 1e-12, pivoting: str = "tile", reuse: bool = False,
-              factorization: str = "auto") -> BriOpts:
+              refine_tol: float = 1e-12, pivoting: str = "auto", reuse: bool = False,
+              factorization: str = "auto", workspace_budget: int = 0) -> BriOpts:
     o = BriOpts()
     lib().bri_default_opts(ctypes.byref(o))
     if precision not in PRECISIONS:
@@ -159,6 +161,7 @@ def make_opts(precision: str = "f64", concurrency: int = 0, refine_max_iters: in
     if factorization not in FACTORIZATIONS:
         raise ValueError(f"unknown factorization {factorization!r}")
     o.factorization = FACTORIZATIONS[factorization]
+    o.workspace_budget = int(workspace_budget)
     return o
 
 
@@ -180,9 +183,10 @@ def block_size(n: int, k: int) -> int:
 
 
 def plan_describe(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
-                  reuse: bool = False, factorization: str = "auto") -> dict:
+                  reuse: bool = False, factorization: str = "auto", workspace_budget: int = 0) -> dict:
     """Host-only structure of the plan (no GPU needed)."""
-    o = make_opts(precision, concurrency, reuse=reuse, factorization=factorization)
+    o = make_opts(precision, concurrency, reuse=reuse, factorization=factorization,
+                  workspace_budget=workspace_budget)
     s = BriPlanStats()
     _check(lib().bri_plan_describe(n, k, i, j, ctypes.byref(o), ctypes.byref(s)))
     return {f: getattr(s, f) for f, _ in BriPlanStats._fields_}
@@ -229,16 +233,16 @@ def refine_plan_dump(n: int, k: int, j: int, which: str, concurrency: int = 0, r
 
 
 def workspace_size(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
-                   reuse: bool = False) -> int:
-    o = make_opts(precision, concurrency, reuse=reuse)
+                   reuse: bool = False, workspace_budget: int = 0) -> int:
+    o = make_opts(precision, concurrency, reuse=reuse, workspace_budget=workspace_budget)
     return int(lib().bri_workspace_size(n, k, i, j, ctypes.byref(o)))
 
 
 def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
                  out: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
                  workspace: Optional[torch.Tensor] = None, refine_max_iters: int = 10,
-                 refine_tol: float = 1e-12, pivoting: str = "tile", reuse: bool = False,
-                 factorization: str = "auto") -> torch.Tensor:
+                 refine_tol: float = 1e-12, pivoting: str = "auto", reuse: bool = False,
+                 factorization: str = "auto", workspace_budget: int = 0) -> torch.Tensor:
     """Block N_ij (b x b, b = ceil(n/k)) of M^{-1} (of Gamma^{-1} when k does not divide n).
 
     ``info`` (optional int32 GPU tensor of one element) receives the device
@@ -250,7 +254,8 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
     if M.shape[1] != n:
         raise ValueError("M must be square")
     b = block_size(n, k)
-    o = make_opts(precision, concurrency, refine_max_iters, refine_tol, pivoting, reuse, factorization)
+    o = make_opts(precision, concurrency, refine_max_iters, refine_tol, pivoting, reuse, factorization,
+                  workspace_budget)
     need = lib().bri_workspace_size(n, k, i, j, ctypes.byref(o))
     if need == 0:
         # Invalid arguments: let the library name the offending one (it
@@ -404,8 +409,16 @@ def refine_last() -> tuple:
     """(sweeps, last relative correction) of this thread's last mixed-precision call."""
     s = ctypes.c_int(0)
     d = ctypes.c_double(0.0)
-    lib().bri_refine_last(ctypes.byref(s), ctypes.byref(d))
+    lib().bri_refine_last(ctypes.byref(s), ctypes.byref(d), None)
     return s.value, d.value
+
+
+def refine_last_bf16_fallback() -> bool:
+    """Whether this thread's last mixed FP16 call met an operand outside the
+    FP16 range and was computed again with BF16 split products."""
+    f = ctypes.c_int(0)
+    lib().bri_refine_last(None, None, ctypes.byref(f))
+    return bool(f.value)
 
 
 def version() -> str:

@@ -100,6 +100,8 @@ std::map<PlanKey, std::shared_ptr<CachedPlan>>& cache() {
 }
 
 int elem_size(int precision) { return precision == BRI_F32 ? 4 : 8; }
+// Element size of the workspace slots: the mixed paths keep their recursion in float.
+int slot_elem_size(int precision) { return precision == BRI_F64 ? 8 : 4; }
 
 int64_t leaves_of(int k) { return static_cast<int64_t>(std::pow(4.0, std::max(0, k - 2))); }
 
@@ -114,7 +116,7 @@ int auto_width(int64_t n, int k, int precision) {
   while (w * tiles < 2048) w *= 4;
   while (w < 256 && w * 4 <= leaves_of(k) && w * 16 <= leaves_of(k)) w *= 4;
   // Keep the live workspace of the batch within 32 GiB.
-  const double per = static_cast<double>(k + 4) * b * b * elem_size(precision);
+  const double per = static_cast<double>(k + 4) * b * b * slot_elem_size(precision);
   int64_t wmem = 1;
   while (wmem * 4 * per <= 32.0 * (1ull << 30)) wmem *= 4;
   w = std::min(w, wmem);
@@ -124,6 +126,33 @@ int auto_width(int64_t n, int k, int precision) {
 int resolve_width(int64_t n, int k, const bri_opts* o) {
   if (o && o->concurrency > 0) return static_cast<int>(std::min<int64_t>(o->concurrency, leaves_of(k)));
   return auto_width(n, k, o ? o->precision : BRI_F64);
+}
+
+// With a workspace budget and automatic concurrency, a copy of *o whose
+// concurrency is the widest width (the automatic one, then down by factors
+// of 4) whose workspace, as size() computes it for the copy, fits the
+// budget; fits = false when even width 1 does not.
+template <typename F>
+bri_opts with_budget(const bri_opts* o, int64_t n, int k, F size, bool& fits) {
+  bri_opts r = *o;
+  fits = true;
+  if (o->workspace_budget == 0 || o->concurrency > 0) return r;
+  int w = auto_width(n, k, o->precision);
+  for (;;) {
+    r.concurrency = w;
+    size_t s = 0;
+    try {
+      s = size(r);
+    } catch (const std::exception&) {
+      s = 0;
+    }
+    if (s != 0 && s <= o->workspace_budget) return r;
+    if (w <= 1) {
+      fits = false;
+      return r;
+    }
+    w = std::max(1, w / 4);
+  }
 }
 
 std::shared_ptr<CachedPlan> get_plan(int kind, int64_t n, int k, int i, int j, int width, int elem, int transpose) {
@@ -162,7 +191,20 @@ struct Ctx {
   char* rhs = nullptr;  // right-hand side of a solve plan (OPND_RHS), (k b) x b
   int64_t ldr = 0;
   int lp = 0;           // float products: 0 FP32 MFMA, 1 FP16 split, 2 BF16 split
+  bool wide = false;    // float recursion whose tile factorisations compute in double
+  int m_elem = 0;       // element size of M when it differs from elem (mixed: double M, float plan)
+  const double* m_max = nullptr;  // mixed: max |M| on the device (blocks of M read scaled)
 };
+
+// How the kernels of a plan are launched.
+struct ExecCfg {
+  int pivoting = BRI_PIVOT_TILE;
+  int lu = 0;           // factorisation variant (bri_opts::factorization)
+  int lp = 0;           // float products: 0 FP32 MFMA, 1 FP16 split, 2 BF16 split
+  bool wide = false;    // tile factorisations of float matrices in double
+  int32_t* range_flag = nullptr;  // FP16 split products: operand outside the FP16 range
+};
+ExecCfg cfg_of(const Ctx& c) { return ExecCfg{c.pivoting, c.lu, c.lp, c.wide, nullptr}; }
 
 DView zero_view() {
   DView v;
@@ -174,6 +216,7 @@ DView zero_view() {
   v.diag = INT_MIN / 2;
   v.trans = 0;
   v.tri = 0;
+  v.src64_max = nullptr;
   return v;
 }
 
@@ -213,11 +256,12 @@ DView resolve(const Ctx& c, const Opnd& o) {
       if (rows > 0 && cols > 0) {
         // Block (r, c) of Gamma, or of Gamma^T (stored transposed).
         const int64_t off = c.transpose ? (col * b) * c.ldm + r * b : (r * b) * c.ldm + col * b;
-        v.p = c.M + off * c.elem;
+        v.p = c.M + off * (c.m_elem ? c.m_elem : c.elem);
       } else {
         v.p = c.M;
       }
       v.trans = static_cast<int16_t>(c.transpose ? 1 : 0);
+      v.src64_max = c.m_max;
       return v;
     }
     case OPND_IDENT:
@@ -325,6 +369,10 @@ void describe_step(const Ctx& c, const Step& s, StepItems& out) {
         break;
       }
       default: {
+        // A matrix in another precision is read through load steps only.
+        if (c.m_max && (it.x.kind == OPND_MBLK || it.y.kind == OPND_MBLK || it.cin.kind == OPND_MBLK ||
+                        it.sub.kind == OPND_MBLK))
+          throw std::logic_error("unstaged block of M in a product");
         GemmItem g = gemm_base(c);
         g.out = dst_ptr(c, it.dst, g.ldo);
         if (s.kind == ST_TRMM_L) {
@@ -453,7 +501,8 @@ bool step_recursive(const ExecStep& s, int bmax, int pivoting, int lu) {
 // the items (merged batches mix orders; every kernel skips the parts of a
 // smaller matrix).
 template <typename T>
-int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lu, int lp, hipStream_t st) {
+int run_exec(const std::vector<ExecStep>& steps, int bmax, const ExecCfg& cfg, hipStream_t st) {
+  const int pivoting = cfg.pivoting, lu = cfg.lu, lp = cfg.lp;
   bool prof;
   {
     std::lock_guard<std::mutex> g(g_prof_mu);
@@ -480,9 +529,9 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lu,
         if (pivoting == BRI_PIVOT_PANEL)
           e = launch_getrf<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
         else if (step_recursive(s, bmax, pivoting, lu))
-          e = launch_getrf_rec<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
+          e = launch_getrf_rec<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, cfg.wide, st);
         else
-          e = launch_getrf_tile<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
+          e = launch_getrf_tile<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, cfg.wide, st);
         break;
       case ST_TRTRI:
         // after the recursive LU the factors are already inverted
@@ -499,6 +548,7 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, int pivoting, int lu,
         L.ndl = s.ndirect;
         L.lp = lp;
         L.tri = (s.kind == ST_TRMM_L || s.kind == ST_TRMM_U) ? 1 : 0;
+        L.range_flag = cfg.range_flag;
         e = launch_gemm<T>(L, bmax, bmax, st);
         break;
       }
@@ -524,7 +574,7 @@ int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
                           dbase + c.lay->step_off[si], &s,
                           step_flops(s, c.b), true});
   }
-  return run_exec<T>(ex, c.b, c.pivoting, c.lu, c.lp, st);
+  return run_exec<T>(ex, c.b, cfg_of(c), st);
 }
 
 // Uploads the descriptors of plan cp for context c and enqueues its kernels.
@@ -669,9 +719,9 @@ MergedExec merge_write(const std::vector<const Plan*>& plans, const std::vector<
 }
 
 template <typename T>
-int run_merged(const MergedExec& ex, int pivoting, int lu, int lp, hipStream_t st) {
+int run_merged(const MergedExec& ex, const ExecCfg& cfg, hipStream_t st) {
   for (size_t g = 0; g < ex.groups.size(); ++g) {
-    const int rc = run_exec<T>(ex.groups[g], ex.bmax[g], pivoting, lu, lp, st);
+    const int rc = run_exec<T>(ex.groups[g], ex.bmax[g], cfg, st);
     if (rc != BRI_OK) return rc;
   }
   return BRI_OK;
@@ -703,8 +753,8 @@ BatchPlan make_batch_plan(int count, const int64_t* n, const int* k, const int* 
     off += align_up(bp.plans[t]->layout.desc_off);  // slots, permutations, tile scratch, status
   }
   bp.merged = merge_layout(pl);
-  bp.info_off = off;
-  off += kAlign;
+  bp.info_off = off;  // a status word per problem (when the caller passes no d_info)
+  off += align_up(sizeof(int32_t) * count);
   bp.desc_off = off;
   bp.total = off + bp.merged.bytes;
   return bp;
@@ -715,7 +765,7 @@ int run_batch(const BatchPlan& bp, const void* const* M, const int64_t* n, const
               const int64_t* ldo, int count, const bri_opts* o) {
   hipStream_t st = o->stream;
   char* ws = static_cast<char*>(o->workspace);
-  int32_t* shared_info = reinterpret_cast<int32_t*>(ws + bp.info_off);
+  int32_t* info_words = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(ws + bp.info_off);
   std::vector<Ctx> ctx(count);
   std::vector<const Plan*> pl(count);
   for (int t = 0; t < count; ++t) {
@@ -730,7 +780,7 @@ int run_batch(const BatchPlan& bp, const void* const* M, const int64_t* n, const
     c.lay = &bp.plans[t]->layout;
     c.out = static_cast<char*>(out[t]);
     c.ldo = ldo[t];
-    c.info = o->d_info ? o->d_info + t : shared_info;
+    c.info = info_words + t;
     pl[t] = &bp.plans[t]->plan;
   }
   Staging& sg = staging();
@@ -746,15 +796,24 @@ int run_batch(const BatchPlan& bp, const void* const* M, const int64_t* n, const
   if (hipMemcpyAsync(ws + bp.desc_off, host, bp.merged.bytes, hipMemcpyHostToDevice, st) != hipSuccess)
     return BRI_ERR_HIP;
   if (hipEventRecord(sg.ev, st) != hipSuccess) return BRI_ERR_HIP;
-  if (launch_fill_int(o->d_info ? o->d_info : shared_info, o->d_info ? count : 1, 0, st) != hipSuccess)
-    return BRI_ERR_HIP;
-  return run_merged<T>(ex, BRI_PIVOT_TILE, o->factorization, 0, st);
+  if (launch_fill_int(info_words, count, 0, st) != hipSuccess) return BRI_ERR_HIP;
+  return run_merged<T>(ex, ExecCfg{BRI_PIVOT_TILE, o->factorization, 0, false, nullptr}, st);
 }
 
 // Merged execution of plain precisions needs tile pivoting (the panel
 // pivoting kernels assume one block order per launch).
 bool batch_mergeable(const bri_opts* o) {
-  return o->pivoting == BRI_PIVOT_TILE && (plain_precision(o->precision) || mixed_precision(o->precision));
+  return (o->pivoting == BRI_PIVOT_TILE || o->pivoting == BRI_PIVOT_AUTO) &&
+         (plain_precision(o->precision) || mixed_precision(o->precision));
+}
+
+// Status words of a finished call (waits for the stream).
+int read_info(const int32_t* d, int count, std::vector<int32_t>& h, hipStream_t st) {
+  h.assign(count, 0);
+  if (hipMemcpyAsync(h.data(), d, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return BRI_ERR_HIP;
+  return BRI_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -772,6 +831,7 @@ typedef std::tuple<int64_t, int, int, int, int> RefineKey;  // n, k, j, width, r
 // Outcome of the calling thread's last mixed-precision call.
 thread_local int t_last_sweeps = 0;
 thread_local double t_last_update = 0.0;
+thread_local int t_last_range_fallback = 0;  // FP16 products redone in BF16
 
 std::shared_ptr<RefineCache> get_refine(int64_t n, int k, int j, int width, int reuse) {
   static std::map<RefineKey, std::shared_ptr<RefineCache>> c;
@@ -796,7 +856,7 @@ std::shared_ptr<RefineCache> get_refine(int64_t n, int k, int j, int width, int 
 
 // Per-problem buffers of the mixed path (offsets inside the problem's region).
 struct MixedRegion {
-  size_t g32 = 0, x64 = 0, r64 = 0, r32 = 0, d32 = 0, plans = 0, total = 0;
+  size_t x64 = 0, r64 = 0, r32 = 0, d32 = 0, plans = 0, total = 0;
 };
 
 MixedRegion mixed_region(int64_t n, int k, const RefineCache& rc) {
@@ -804,8 +864,6 @@ MixedRegion mixed_region(int64_t n, int k, const RefineCache& rc) {
   const size_t b = static_cast<size_t>((n + k - 1) / k);
   const size_t kb = static_cast<size_t>(k) * b;
   size_t off = 0;
-  L.g32 = off;
-  off += align_up(kb * kb * 4);
   L.x64 = off;
   off += align_up(kb * b * 8);
   L.r64 = off;
@@ -829,7 +887,7 @@ struct MixedBatch {
   std::vector<MixedRegion> reg;
   std::vector<size_t> region;
   MergedLayout col, sol;
-  size_t info_off = 0, scal_off = 0, items_off = 0, gemm_off = 0, load_off = 0, col_off = 0, sol_off = 0;
+  size_t info_off = 0, flag_off = 0, scal_off = 0, items_off = 0, gemm_off = 0, load_off = 0, col_off = 0, sol_off = 0;
   size_t desc_bytes = 0, total = 0;
 };
 
@@ -852,7 +910,9 @@ MixedBatch make_mixed_batch(int count, const int64_t* n, const int* k, const int
   }
   mb.col = merge_layout(pc);
   mb.sol = merge_layout(ps);
-  mb.info_off = off;
+  mb.info_off = off;  // a status word per problem (when the caller passes no d_info)
+  off += align_up(sizeof(int32_t) * count);
+  mb.flag_off = off;  // FP16 range flag
   off += kAlign;
   const size_t c = static_cast<size_t>(count);
   mb.scal_off = off;
@@ -882,7 +942,7 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
                     const int* i, const int* j, void* const* out, const int64_t* ldo, const bri_opts* o) {
   hipStream_t st = o->stream;
   char* ws = static_cast<char*>(o->workspace);
-  int32_t* shared_info = reinterpret_cast<int32_t*>(ws + mb.info_off);
+  int32_t* info_words = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(ws + mb.info_off);
   double* scal_all = reinterpret_cast<double*>(ws + mb.scal_off);
   const size_t d0 = mb.items_off;
   std::vector<Ctx> cc(count), cs(count);
@@ -890,7 +950,7 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
   std::vector<RefItem> ri(count);
   std::vector<GemmItem> gi(count);
   std::vector<LoadItem> li(count);
-  int64_t max_nn = 0, max_kk = 0, max_kb_b = 0, max_fix = 0;
+  int64_t max_nn = 0, max_kb_b = 0, max_fix = 0;
   int max_n = 0, max_b = 0;
   for (int t = 0; t < count; ++t) {
     const RefineCache& rc = *mb.rc[t];
@@ -906,14 +966,12 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
     r.kb = kb;
     r.b = b;
     r.j = j[t];
-    r.G = reinterpret_cast<float*>(base + R.g32);
     r.X = reinterpret_cast<double*>(base + R.x64);
     r.R = reinterpret_cast<double*>(base + R.r64);
     r.R32 = reinterpret_cast<float*>(base + R.r32);
     r.D = reinterpret_cast<float*>(base + R.d32);
     r.scal = scal_all + static_cast<size_t>(t) * kRefineScalars;
     max_nn = std::max<int64_t>(max_nn, n[t] * n[t]);
-    max_kk = std::max<int64_t>(max_kk, kb * kb);
     max_kb_b = std::max<int64_t>(max_kb_b, kb * b);
     max_fix = std::max<int64_t>(max_fix, static_cast<int64_t>(b) * (1 + kb - n[t]));
     max_n = std::max<int>(max_n, static_cast<int>(n[t]));
@@ -948,21 +1006,23 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
     l.ldd = ldo[t];
     l.rows = b;
     l.cols = b;
-    // float plans: sigma Gamma in place of M, D as the output, R32 as the right-hand side
+    // float plans: blocks of sigma Gamma loaded from M (converted and scaled
+    // by the load steps), D as the output, R32 as the right-hand side
     Ctx& c = cc[t];
     c.pivoting = o->pivoting;
     c.lu = o->factorization;
-  c.lu = o->factorization;
-    c.M = reinterpret_cast<const char*>(r.G);
-    c.n = kb;
-    c.ldm = kb;
+    c.M = static_cast<const char*>(M[t]);
+    c.n = n[t];
+    c.ldm = ldm[t];
+    c.m_elem = 8;
+    c.m_max = r.scal;  // scal[0]: max |M|
     c.b = b;
     c.elem = 4;
     c.ws = base + R.plans;
     c.lay = &rc.col->layout;
     c.out = reinterpret_cast<char*>(r.D);
     c.ldo = b;
-    c.info = o->d_info ? o->d_info + t : shared_info;
+    c.info = info_words + t;
     c.rhs = reinterpret_cast<char*>(r.R32);
     c.ldr = b;
     c.lp = lp_of(o->precision);
@@ -999,20 +1059,30 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
   if (hipMemcpyAsync(ws + d0, host, mb.desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return BRI_ERR_HIP;
   if (hipEventRecord(sg.ev, st) != hipSuccess) return BRI_ERR_HIP;
   const RefItem* d_items = reinterpret_cast<const RefItem*>(ws + mb.items_off);
-  if (launch_fill_int(o->d_info ? o->d_info : shared_info, o->d_info ? count : 1, 0, st) != hipSuccess)
-    return BRI_ERR_HIP;
+  if (launch_fill_int(info_words, count, 0, st) != hipSuccess) return BRI_ERR_HIP;
 
-  // sigma Gamma in float, then X0 = sigma (sigma Gamma)^{-1} E_j by the float
+  // Float recursion: products per the precision, tile factorisations in FP64.
+  // The FP16 split products flag operand values outside the FP16 range; the
+  // call then starts again with the BF16 split products (same exponent range
+  // as FP32), found at the first sweep's synchronisation.
+  int32_t* range_flag = reinterpret_cast<int32_t*>(ws + mb.flag_off);
+  ExecCfg mcfg{o->pivoting, o->factorization, lp_of(o->precision), true, range_flag};
+  t_last_range_fallback = 0;
+  std::vector<char> conv;
+  std::vector<double> prev;
+  std::vector<double> hs(static_cast<size_t>(count) * kRefineScalars);
+  for (int pass = 0;; ++pass) {
+  if (mcfg.lp == 1 && launch_fill_int(range_flag, 1, 0, st) != hipSuccess) return BRI_ERR_HIP;
+  // sigma from max |M|, then X0 = sigma (sigma Gamma)^{-1} E_j by the float
   // block-column plans (which keep their pivots for the correction solves).
   if (launch_scal_clear(d_items, count, 0, kRefineScalars, st) != hipSuccess) return BRI_ERR_HIP;
   if (launch_absmax(d_items, count, 0, max_nn, st) != hipSuccess) return BRI_ERR_HIP;
-  if (launch_gamma_f32(d_items, count, max_kk, st) != hipSuccess) return BRI_ERR_HIP;
-  int rcode = run_merged<float>(ecol, o->pivoting, o->factorization, lp_of(o->precision), st);
+  int rcode = run_merged<float>(ecol, mcfg, st);
   if (rcode != BRI_OK) return rcode;
   if (!mb.rc[0]->column_gives_x0) {
     // Pivots only (reuse): X0 = (sigma Gamma)^{-1} E_j by the solve plan.
     if (launch_set_ej(d_items, count, max_kb_b, st) != hipSuccess) return BRI_ERR_HIP;
-    rcode = run_merged<float>(esol, o->pivoting, o->factorization, lp_of(o->precision), st);
+    rcode = run_merged<float>(esol, mcfg, st);
     if (rcode != BRI_OK) return rcode;
   }
   if (launch_refine_update(d_items, count, max_kb_b, 1, st) != hipSuccess) return BRI_ERR_HIP;
@@ -1023,13 +1093,23 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
   // contraction rho = ||dX_t|| / ||dX_{t-1}|| < 1/2 bounds the remaining
   // error rho / (1 - rho) ||dX_t|| below it.  All problems sweep together
   // until every one has converged.
-  std::vector<char> conv(count, o->refine_max_iters <= 0 ? 1 : 0);
-  std::vector<double> prev(count, 0.0);
-  std::vector<double> hs(static_cast<size_t>(count) * kRefineScalars);
+  conv.assign(count, o->refine_max_iters <= 0 ? 1 : 0);
+  prev.assign(count, 0.0);
   const double tol = o->refine_tol;
   t_last_sweeps = 0;
   t_last_update = 0.0;
-  for (int it = 0; it < o->refine_max_iters; ++it) {
+  bool restart = false;
+  for (int it = 0; it < std::max(1, o->refine_max_iters); ++it) {
+    if (o->refine_max_iters <= 0) {
+      // no sweeps: only the range check of the FP16 products
+      if (mcfg.lp != 1) break;
+      int32_t hf = 0;
+      if (hipMemcpyAsync(&hf, range_flag, sizeof(hf), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return BRI_ERR_HIP;
+      restart = hf != 0;
+      break;
+    }
     if (launch_scal_clear(d_items, count, 1, 4, st) != hipSuccess) return BRI_ERR_HIP;
     GemmLaunch L{};
     L.mode = GEMM_EXPLICIT;
@@ -1042,12 +1122,20 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
     if (launch_resid_fix(d_items, count, max_fix, st) != hipSuccess) return BRI_ERR_HIP;
     if (launch_absmax(d_items, count, 1, max_kb_b, st) != hipSuccess) return BRI_ERR_HIP;
     if (launch_rhs_scale(d_items, count, max_kb_b, st) != hipSuccess) return BRI_ERR_HIP;
-    rcode = run_merged<float>(esol, o->pivoting, o->factorization, lp_of(o->precision), st);
+    rcode = run_merged<float>(esol, mcfg, st);
     if (rcode != BRI_OK) return rcode;
     if (launch_refine_update(d_items, count, max_kb_b, 0, st) != hipSuccess) return BRI_ERR_HIP;
     if (hipMemcpyAsync(hs.data(), scal_all, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
       return BRI_ERR_HIP;
+    int32_t hflag = 0;
+    if (mcfg.lp == 1 && it == 0 &&
+        hipMemcpyAsync(&hflag, range_flag, sizeof(hflag), hipMemcpyDeviceToHost, st) != hipSuccess)
+      return BRI_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return BRI_ERR_HIP;
+    if (hflag) {
+      restart = true;
+      break;
+    }
     t_last_sweeps = it + 1;
     bool all = true;
     double worst = 0.0;
@@ -1070,11 +1158,15 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
     t_last_update = worst;
     if (all) break;
   }
+  if (!restart) break;
+  mcfg.lp = 2;
+  t_last_range_fallback = 1;
+  }  // passes
   if (launch_load<double>(reinterpret_cast<const LoadItem*>(ws + mb.load_off), count, max_b, max_b, st) !=
       hipSuccess)
     return BRI_ERR_HIP;
   for (int t = 0; t < count; ++t)
-    if (!conv[t] && launch_info_unconverged(o->d_info ? o->d_info + t : shared_info, st) != hipSuccess)
+    if (!conv[t] && launch_info_unconverged(info_words + t, st) != hipSuccess)
       return BRI_ERR_HIP;
   return BRI_OK;
 }
@@ -1103,7 +1195,7 @@ void bri_default_opts(bri_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->precision = BRI_F64;
   o->concurrency = 0;
-  o->pivoting = BRI_PIVOT_TILE;
+  o->pivoting = BRI_PIVOT_AUTO;
   o->refine_max_iters = 10;
   o->refine_tol = 1e-12;
 }
@@ -1131,9 +1223,10 @@ static int check_block_args(int64_t n, int64_t ldm, int k, int i, int j, int64_t
   return 0;
 }
 
-int bri_refine_last(int* sweeps, double* last_update) {
+int bri_refine_last(int* sweeps, double* last_update, int* bf16_fallback) {
   if (sweeps) *sweeps = t_last_sweeps;
   if (last_update) *last_update = t_last_update;
+  if (bf16_fallback) *bf16_fallback = t_last_range_fallback;
   return 0;
 }
 
@@ -1165,8 +1258,7 @@ int bri_profile_read(bri_profile_entry* entries, int cap) {
   return n;
 }
 
-size_t bri_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
-  if (!o || check_block_args(n, n, k, i, j, (n + k - 1) / k) != 0) return 0;
+static size_t workspace_size_of(int64_t n, int k, int i, int j, const bri_opts* o) {
   const int w = resolve_width(n, k, o);
   if (mixed_precision(o->precision)) {
     try {
@@ -1184,11 +1276,47 @@ size_t bri_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
   }
 }
 
+// The status word a single invert_block call uses when the caller passes no
+// d_info (inside the workspace), or null when the workspace is too small.
+static int32_t* block_info_word(int64_t n, int k, int i, int j, const bri_opts* o) {
+  try {
+    size_t off = 0, need = 0;
+    if (mixed_precision(o->precision)) {
+      const MixedBatch mb = make_mixed_batch(1, &n, &k, &j, o, false);
+      off = mb.info_off;
+      need = mb.total;
+    } else {
+      auto cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, resolve_width(n, k, o), elem_size(o->precision), 0);
+      off = cp->layout.info_off;
+      need = cp->layout.total;
+    }
+    if (!o->workspace || o->workspace_bytes < need) return nullptr;
+    return reinterpret_cast<int32_t*>(static_cast<char*>(o->workspace) + off);
+  } catch (const std::exception&) {
+    return nullptr;
+  }
+}
+
+static bri_opts block_budget(const bri_opts* o, int64_t n, int k, int i, int j, bool& fits) {
+  return with_budget(o, n, k, [&](const bri_opts& r) { return workspace_size_of(n, k, i, j, &r); }, fits);
+}
+
+size_t bri_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
+  if (!o || check_block_args(n, n, k, i, j, (n + k - 1) / k) != 0) return 0;
+  bool fits;
+  const bri_opts ob = block_budget(o, n, k, i, j, fits);
+  return fits ? workspace_size_of(n, k, i, j, &ob) : 0;
+}
+
 int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_plan_stats* s) {
   if (!s) return -6;
   if (!o) return -5;
   const int rc = check_block_args(n, n, k, i, j, (n + k - 1) / k);
   if (rc) return rc;
+  bool fits;
+  const bri_opts ob = block_budget(o, n, k, i, j, fits);
+  if (!fits) return BRI_ERR_WORKSPACE;
+  o = &ob;
   const int w = resolve_width(n, k, o);
   auto cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, w, elem_size(o->precision), 0);
   const Plan& p = cp->plan;
@@ -1271,6 +1399,26 @@ int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, voi
   if (!o) return -9;
   const int rc = check_block_args(n, ldm, k, i, j, ldo);
   if (rc) return rc;
+  bool fits;
+  const bri_opts ob = block_budget(o, n, k, i, j, fits);
+  if (!fits) return BRI_ERR_WORKSPACE;
+  o = &ob;
+  if (o->pivoting == BRI_PIVOT_AUTO) {
+    // Tile pivoting first; if a factorisation reported a failed pivot or
+    // element growth, the block again with panel pivoting.
+    bri_opts t = *o;
+    t.pivoting = BRI_PIVOT_TILE;
+    if (!t.d_info) {
+      t.d_info = block_info_word(n, k, i, j, o);
+      if (!t.d_info) return BRI_ERR_WORKSPACE;
+    }
+    int rc2 = invert_block(M, n, ldm, k, i, j, out, ldo, &t);
+    std::vector<int32_t> h;
+    if (rc2 == BRI_OK) rc2 = read_info(t.d_info, 1, h, o->stream);
+    if (rc2 != BRI_OK || h[0] <= 0) return rc2;
+    t.pivoting = BRI_PIVOT_PANEL;
+    return invert_block(M, n, ldm, k, i, j, out, ldo, &t);
+  }
   if (mixed_precision(o->precision)) return invert_block_mixed(M, n, ldm, k, i, j, out, ldo, o);
   if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
   const int elem = elem_size(o->precision);
@@ -1297,9 +1445,7 @@ int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, voi
   return execute(*cp, c, o->stream, true);
 }
 
-size_t bri_block_column_workspace_size(int64_t n, int k, int j, const bri_opts* o) {
-  if (!o || check_block_args(n, n, k, 0, j, (n + k - 1) / k) != 0) return 0;
-  if (!plain_precision(o->precision)) return 0;
+static size_t column_size_of(int64_t n, int k, int j, const bri_opts* o) {
   const int w = resolve_width(n, k, o);
   try {
     auto cp = get_plan(1, n, k, 0, j, w, elem_size(o->precision), 0);
@@ -1307,6 +1453,18 @@ size_t bri_block_column_workspace_size(int64_t n, int k, int j, const bri_opts* 
   } catch (const std::exception&) {
     return 0;
   }
+}
+
+static bri_opts column_budget(const bri_opts* o, int64_t n, int k, int j, bool& fits) {
+  return with_budget(o, n, k, [&](const bri_opts& r) { return column_size_of(n, k, j, &r); }, fits);
+}
+
+size_t bri_block_column_workspace_size(int64_t n, int k, int j, const bri_opts* o) {
+  if (!o || check_block_args(n, n, k, 0, j, (n + k - 1) / k) != 0) return 0;
+  if (!plain_precision(o->precision)) return 0;
+  bool fits;
+  const bri_opts ob = column_budget(o, n, k, j, fits);
+  return fits ? column_size_of(n, k, j, &ob) : 0;
 }
 
 int bri_block_column(const void* M, int64_t n, int64_t ldm, int k, int j, int transpose, void* X, int64_t ldx,
@@ -1317,6 +1475,30 @@ int bri_block_column(const void* M, int64_t n, int64_t ldm, int k, int j, int tr
   const int rc = check_block_args(n, ldm, k, 0, j, ldx);
   if (rc) return rc == -8 ? -8 : (rc == -6 ? -5 : rc);
   if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
+  bool fits;
+  const bri_opts ob = column_budget(o, n, k, j, fits);
+  if (!fits) return BRI_ERR_WORKSPACE;
+  o = &ob;
+  if (o->pivoting == BRI_PIVOT_AUTO) {
+    bri_opts t = *o;
+    t.pivoting = BRI_PIVOT_TILE;
+    if (!t.d_info) {
+      std::shared_ptr<CachedPlan> cp;
+      try {
+        cp = get_plan(1, n, k, 0, j, resolve_width(n, k, o), elem_size(o->precision), transpose ? 1 : 0);
+      } catch (const std::exception&) {
+        return BRI_ERR_UNSUPPORTED;
+      }
+      if (!o->workspace || o->workspace_bytes < cp->layout.total) return BRI_ERR_WORKSPACE;
+      t.d_info = reinterpret_cast<int32_t*>(static_cast<char*>(o->workspace) + cp->layout.info_off);
+    }
+    int rc2 = bri_block_column(M, n, ldm, k, j, transpose, X, ldx, &t);
+    std::vector<int32_t> h;
+    if (rc2 == BRI_OK) rc2 = read_info(t.d_info, 1, h, o->stream);
+    if (rc2 != BRI_OK || h[0] <= 0) return rc2;
+    t.pivoting = BRI_PIVOT_PANEL;
+    return bri_block_column(M, n, ldm, k, j, transpose, X, ldx, &t);
+  }
   const int elem = elem_size(o->precision);
   const int w = resolve_width(n, k, o);
   std::shared_ptr<CachedPlan> cp;
@@ -1390,6 +1572,46 @@ int invert_block_batched(int count, const void* const* M, const int64_t* n, cons
     if (!out[t]) return -8;
     const int rc = check_block_args(n[t], ldm[t], k[t], i[t], j[t], ldo[t]);
     if (rc) return rc == -2 ? -3 : rc == -3 ? -4 : rc == -4 ? -5 : rc == -5 ? -6 : rc == -6 ? -7 : rc == -8 ? -9 : rc;
+  }
+  if (o->pivoting == BRI_PIVOT_AUTO && batch_mergeable(o)) {
+    // Merged tile-pivoting pass; problems whose factorisations reported a
+    // failed pivot or element growth are then computed again one by one with
+    // panel pivoting in the same workspace.
+    bri_opts t = *o;
+    t.pivoting = BRI_PIVOT_TILE;
+    if (!t.d_info) {
+      size_t off = 0, need = 0;
+      try {
+        if (mixed_precision(o->precision)) {
+          const MixedBatch mb = make_mixed_batch(count, n, k, j, o, true);
+          off = mb.info_off;
+          need = mb.total;
+        } else {
+          const BatchPlan bp = make_batch_plan(count, n, k, i, j, elem_size(o->precision), o->reuse);
+          off = bp.info_off;
+          need = bp.total;
+        }
+      } catch (const std::exception&) {
+        return BRI_ERR_UNSUPPORTED;
+      }
+      if (!o->workspace || o->workspace_bytes < need) return BRI_ERR_WORKSPACE;
+      t.d_info = reinterpret_cast<int32_t*>(static_cast<char*>(o->workspace) + off);
+    }
+    int rc2 = invert_block_batched(count, M, n, ldm, k, i, j, out, ldo, &t);
+    std::vector<int32_t> h;
+    if (rc2 == BRI_OK) rc2 = read_info(t.d_info, count, h, o->stream);
+    if (rc2 != BRI_OK) return rc2;
+    for (int p = 0; p < count; ++p) {
+      if (h[p] <= 0) continue;
+      bri_opts tt = *o;
+      tt.pivoting = BRI_PIVOT_PANEL;
+      tt.concurrency = 0;
+      tt.workspace_budget = o->workspace_bytes;
+      tt.d_info = o->d_info ? o->d_info + p : nullptr;
+      rc2 = invert_block(M[p], n[p], ldm[p], k[p], i[p], j[p], out[p], ldo[p], &tt);
+      if (rc2 != BRI_OK && rc2 != BRI_ERR_WORKSPACE) return rc2;  // too large for the workspace: stays flagged
+    }
+    return BRI_OK;
   }
   if (batch_mergeable(o) && mixed_precision(o->precision)) {
     MixedBatch mb;
@@ -1498,9 +1720,21 @@ int bri_gemm(int count, int64_t m, int64_t n, int64_t kk, double alpha, const vo
   return e == hipSuccess ? BRI_OK : BRI_ERR_HIP;
 }
 
+static size_t backward_size_of(int64_t n, int k, int i, int j, const bri_opts* o);
+
+static bri_opts backward_budget(const bri_opts* o, int64_t n, int k, int i, int j, bool& fits) {
+  return with_budget(o, n, k, [&](const bri_opts& r) { return backward_size_of(n, k, i, j, &r); }, fits);
+}
+
 size_t bri_backward_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
   if (!o || check_block_args(n, n, k, i, j, (n + k - 1) / k) != 0) return 0;
   if (!plain_precision(o->precision)) return 0;
+  bool fits;
+  const bri_opts ob = backward_budget(o, n, k, i, j, fits);
+  return fits ? backward_size_of(n, k, i, j, &ob) : 0;
+}
+
+static size_t backward_size_of(int64_t n, int k, int i, int j, const bri_opts* o) {
   const int elem = elem_size(o->precision);
   const int64_t b = (n + k - 1) / k;
   const size_t colbuf = align_up(static_cast<size_t>(k * b) * b * elem);
@@ -1530,7 +1764,11 @@ int invert_block_backward(const void* M, int64_t n, int64_t ldm, int k, int i, i
   if (ldgm < n) return -10;
   if (b > BRI_MAX_BLOCK) return BRI_ERR_UNSUPPORTED;
   if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
-  const size_t need = bri_backward_workspace_size(n, k, i, j, o);
+  bool fits;
+  const bri_opts ob = backward_budget(o, n, k, i, j, fits);
+  if (!fits) return BRI_ERR_WORKSPACE;
+  o = &ob;
+  const size_t need = backward_size_of(n, k, i, j, o);
   if (need == 0) return BRI_ERR_UNSUPPORTED;
   if (!o->workspace || o->workspace_bytes < need) return BRI_ERR_WORKSPACE;
   const int elem = elem_size(o->precision);

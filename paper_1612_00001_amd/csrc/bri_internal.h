@@ -16,6 +16,11 @@ namespace bri {
 //     (x - y == diag) ? 1 : 0, which realises the identity padding of the
 //     augmented matrix Gamma without a padded copy.
 //   - trans: the stored element (x, y) lives at p[y * ld + x].
+//   - src64_max: when set, the stored data are doubles and every element
+//     (synthesised ones included) is multiplied by the power of two 2^-e
+//     with max |M| 2^-e in [0.5, 1), max |M| being the double at src64_max
+//     (the scaled matrix the mixed paths' float recursion works on).  Only
+//     the block loads (k_load) read such views.
 // ---------------------------------------------------------------------------
 struct DView {
   const void* p;
@@ -24,6 +29,7 @@ struct DView {
   int32_t rows, cols;
   int32_t diag;
   int16_t trans, tri;
+  const double* src64_max;
 };
 
 // out[x, y] = beta * Cin[x, y] + alpha * sum_t A[x, t] B[t, y] - Sub[x, y]
@@ -34,6 +40,8 @@ struct GemmItem {
   int32_t M, N, K;
   int32_t has_cin, has_sub, pad_;
   double alpha, beta;
+  int32_t* umax;     // when set: the largest magnitude of the output goes here (element
+                     // growth of the recursive LU, see kUmaxWord); null otherwise
 };
 
 // One b x b matrix factored in place (P A = L U, unit L strictly below the
@@ -95,6 +103,8 @@ struct GemmLaunch {
   int32_t tri;          // items have a triangular operand (uneven K per output tile)
   int32_t ndl;          // GEMM_EXPLICIT: the first ndl fast items also qualify for
                         // the direct-to-LDS FP64 instance (gemm_item_is_direct)
+  int32_t* range_flag;  // FP16 split products: set to 1 when an operand value lies
+                        // outside the FP16 range (or is not finite); may be null
 };
 
 constexpr int kMaxBlock = 4096;  // == BRI_MAX_BLOCK
@@ -137,6 +147,19 @@ inline bool gemm_item_is_fast(const GemmItem& g) {
 
 constexpr int kSwapWords = 1 + 2 * 2 * 64;  // count + up to 128 (dest, src) pairs
 static_assert(1 + kStepBufs * kTile <= kSwapWords, "tile permutations exceed the swap words");
+// Element growth of the tile-pivoting LUs, in the swap words they leave
+// free: kAmaxParts partial maxima of |A| over bands of rows (taken before
+// the factorisation) from word kAmaxWord on, and the largest |U| entry formed
+// (float bits, updated by atomic maximum) in word kUmaxWord.  A
+// factorisation whose largest |U| exceeds kGrowthLimit times the largest |A|
+// is reported through info like a failed pivot (partial pivoting keeps this
+// ratio near 10 on Gaussian matrices of these orders; SPD and diagonally
+// dominant matrices keep it at most 1 and 2).
+constexpr int kAmaxParts = 64;
+constexpr int kAmaxWord = 128;
+constexpr int kUmaxWord = kSwapWords - 1;
+constexpr float kGrowthLimit = 64.0f;
+static_assert(1 + kStepBufs * kTile <= kAmaxWord && kAmaxWord + kAmaxParts <= kUmaxWord, "growth words");
 constexpr int kTrtriTile = 32;                // diagonal tile of the triangular inversion
 
 // Width of the LU panel held in registers for a panel of h rows (512 threads

@@ -11,14 +11,16 @@ template <typename T>
 hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st);
 template <typename T>
 hipError_t launch_getrf(const LuItem* d_items, int count, int b, hipStream_t st);
+// wide: a float matrix's tile factorisations (pivot selection and the
+// 32 x 32 LU with its triangular inverses) computed in double.
 template <typename T>
-hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, hipStream_t st);
+hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, bool wide, hipStream_t st);
 // Recursive LU that leaves the inverted factors in packed form (no
 // triangular inversion follows); needs LuItem::tmp (a b x b shadow) and
 // b = 32 * 2^m.  getrf_rec_applies() tells whether a launch of count
 // matrices of order b takes it.
 template <typename T>
-hipError_t launch_getrf_rec(const LuItem* d_items, int count, int b, hipStream_t st);
+hipError_t launch_getrf_rec(const LuItem* d_items, int count, int b, bool wide, hipStream_t st);
 template <typename T>
 // diag_inverted: the LU (tile pivoting) already left its diagonal 32 x 32 tiles inverted.
 hipError_t launch_trtri(const LuItem* d_items, int count, int b, bool diag_inverted, hipStream_t st);

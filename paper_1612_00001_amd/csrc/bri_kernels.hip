@@ -34,6 +34,14 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // Views
 // ---------------------------------------------------------------------------
+// 2^-e with |x| 2^-e in [0.5, 1); 1 for zero or non-finite x.
+__device__ __forceinline__ double pow2_scale_of(double x) {
+  if (!(x > 0.0) || !isfinite(x)) return 1.0;
+  int e = 0;
+  (void)frexp(x, &e);
+  return ldexp(1.0, -e);
+}
+
 template <typename T>
 __device__ __forceinline__ T vget(const DView& v, int x, int y) {
   if (v.tri == 1) {
@@ -43,6 +51,14 @@ __device__ __forceinline__ T vget(const DView& v, int x, int y) {
     if (x > y) return T(0);
   }
   const int xs = v.rowperm ? v.rowperm[x] : x;
+  if (v.src64_max) {
+    double e = (xs - y == v.diag) ? 1.0 : 0.0;
+    if (xs < v.rows && y < v.cols) {
+      const double* p = static_cast<const double*>(v.p);
+      e = v.trans ? p[static_cast<int64_t>(y) * v.ld + xs] : p[static_cast<int64_t>(xs) * v.ld + y];
+    }
+    return static_cast<T>(e * pow2_scale_of(*v.src64_max));
+  }
   if (xs < v.rows && y < v.cols) {
     const T* p = static_cast<const T*>(v.p);
     return v.trans ? p[static_cast<int64_t>(y) * v.ld + xs] : p[static_cast<int64_t>(xs) * v.ld + y];
@@ -61,6 +77,7 @@ __device__ __forceinline__ DView dense_view(const void* base, int64_t ld, int64_
   v.diag = INT_MIN / 2;
   v.trans = 0;
   v.tri = static_cast<int16_t>(tri);
+  v.src64_max = nullptr;
   return v;
 }
 
@@ -84,6 +101,18 @@ struct MF<float> {
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+// Records a wavefront's largest magnitude m (non-negative, or NaN) into the
+// float-bit maximum at *w.  All lanes of the wavefront take part.
+__device__ __forceinline__ void note_umax(int32_t* w, float m) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const float x = __shfl_xor(m, o, 64);
+    m = (x > m || x != x) ? x : m;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int*>(w), __float_as_uint(m));
+}
+__device__ __forceinline__ float nan_fmax(float m, float v) { return (v > m || v != v) ? v : m; }
+
 // ---------------------------------------------------------------------------
 // GEMM work items
 // ---------------------------------------------------------------------------
@@ -94,6 +123,7 @@ __device__ bool gemm_item(const GemmLaunch& L, int idx, GemmItem& it) {
     it = static_cast<const GemmItem*>(L.items)[idx];
     return true;
   }
+  it.umax = nullptr;
   if (MODE == GEMM_LU_TRAILING) {
     const LuItem lu = static_cast<const LuItem*>(L.items)[idx];
     const int b = lu.b, j = L.j, w = L.w, m = b - j - w;
@@ -142,10 +172,11 @@ __device__ bool gemm_item(const GemmLaunch& L, int idx, GemmItem& it) {
     };
     const int64_t o1 = o, o2 = o + h;
     if (MODE == GEMM_RLU_A) {
-      if (part == 0) {  // U12 = L11^{-1} (P1 A12)
+      if (part == 0) {  // U12 = L11^{-1} (P1 A12): the block (1,2) of U, its growth recorded
         it.A = dense_view(a, b, o1, o1, h, h, E, 1);
         it.B = permuted(a, o2, o1);
         it.out = sh + (o1 * b + o2) * E;
+        it.umax = lu.swaps + kUmaxWord;
       } else {          // L21 = A21 U11^{-1}
         it.A = dense_view(a, b, o2, o1, h, h, E);
         it.B = dense_view(a, b, o1, o1, h, h, E, 2);
@@ -543,14 +574,19 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
           if (it.has_cin) val[j][v] += beta * cv[j][v];
           if (it.has_sub) val[j][v] -= sv[j][v];
         }
+      float um = 0.f;
 #pragma unroll
       for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = m0 + wm * WM + i * 16 + MF<T>::row(lane, v);
           const int c = n0 + wn * WN + j * 16 + (lane & 15);
-          if (r < it.M && c < it.N) gstore(out + static_cast<int64_t>(r) * it.ldo + c, val[j][v]);
+          if (r < it.M && c < it.N) {
+            gstore(out + static_cast<int64_t>(r) * it.ldo + c, val[j][v]);
+            um = nan_fmax(um, static_cast<float>(fabs(val[j][v])));
+          }
         }
+      if (it.umax) note_umax(it.umax, um);
     }
   }
 }
@@ -793,14 +829,19 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmLaun
         if (it.has_cin) val[j][v] += beta * cv[j][v];
         if (it.has_sub) val[j][v] -= sv[j][v];
       }
+    float um = 0.f;
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = m0 + wm * WM + i * 16 + MF<double>::row(lane, v);
         const int c = n0 + wn * WN + j * 16 + (lane & 15);
-        if (r < it.M && c < it.N) gstore(out + static_cast<int64_t>(r) * it.ldo + c, val[j][v]);
+        if (r < it.M && c < it.N) {
+          gstore(out + static_cast<int64_t>(r) * it.ldo + c, val[j][v]);
+          um = nan_fmax(um, static_cast<float>(fabs(val[j][v])));
+        }
       }
+    if (MODE != GEMM_EXPLICIT && it.umax) note_umax(it.umax, um);
   }
 }
 
@@ -923,18 +964,26 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lp(GemmLaun
       opb.issue(k0, n0);
     }
   };
+  // FP16 parts hold magnitudes below 65504 only: values outside that range
+  // (or not finite) are recorded in L.range_flag, so the caller can redo the
+  // products in BF16.
+  bool out_of_range = false;
   auto store = [&](int buf, int k0) {
 #pragma unroll
     for (int t = 0; t < AE; ++t) {
       E pa[NP];
-      P::split(GEN ? opa.raw[t] : opa.finalize(t, m0, k0), pa);
+      const float x = GEN ? opa.raw[t] : opa.finalize(t, m0, k0);
+      if (LP == 1) out_of_range = out_of_range || !(fabsf(x) < 65504.0f);
+      P::split(x, pa);
 #pragma unroll
       for (int q = 0; q < NP; ++q) As[buf][q][opa.r0 + t * opa.dr][opa.c0 + t * opa.dc] = pa[q];
     }
 #pragma unroll
     for (int t = 0; t < BE; ++t) {
       E pb[NP];
-      P::split(GEN ? opb.raw[t] : opb.finalize(t, k0, n0), pb);
+      const float y = GEN ? opb.raw[t] : opb.finalize(t, k0, n0);
+      if (LP == 1) out_of_range = out_of_range || !(fabsf(y) < 65504.0f);
+      P::split(y, pb);
 #pragma unroll
       for (int q = 0; q < NP; ++q) Bs[buf][q][opb.c0 + t * opb.dc][opb.r0 + t * opb.dr] = pb[q];
     }
@@ -982,6 +1031,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lp(GemmLaun
     }
   }
 
+  if (LP == 1 && L.range_flag && __any(out_of_range) && lane == 0) atomicOr(L.range_flag, 1);
   float* out = static_cast<float*>(it.out);
   const float alpha = static_cast<float>(it.alpha), beta = static_cast<float>(it.beta);
   const float xs = (LP == 1) ? (1.0f / 2048.0f) : 1.0f;
@@ -1374,32 +1424,32 @@ constexpr int kLuLdsElems = 4 * kTile * kLuLd + kTile;
 // only within the wavefront) factors diagonal tile t0 / kTile.  The tile is
 // read from the matrix, or from LDS (sT, leading dimension ldt) when the
 // caller has just formed it there; lds is kLuLdsElems elements of scratch.
-template <typename T>
-__device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T* sT, int ldt, T* lds) {
+template <typename T, typename TC = T>
+__device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T* sT, int ldt, TC* lds) {
   constexpr int LD = kLuLd;
   const LuItem it = item;  // every field read up front, ahead of the stores
   if (t0 >= it.b) return;  // a smaller matrix of a merged batch
   T* A = static_cast<T*>(it.a);
   const int b = it.b, ts = min(kTile, b - t0), s = t0 / kTile;
   const int l = threadIdx.x & 63, r = l & 31, half = l >> 5;
-  T (*sR)[LD] = reinterpret_cast<T (*)[LD]>(lds);                       // current rows, by original tile row
-  T (*sL)[LD] = reinterpret_cast<T (*)[LD]>(lds + kTile * LD);          // multipliers: sL[r][C]
-  T (*sF)[LD] = reinterpret_cast<T (*)[LD]>(lds + 2 * kTile * LD);      // factored tile in pivot order
-  T (*sFT)[LD] = reinterpret_cast<T (*)[LD]>(lds + 3 * kTile * LD);     // its transpose
-  T* sD = lds + 4 * kTile * LD;                                         // reciprocals of U's diagonal
+  TC (*sR)[LD] = reinterpret_cast<TC (*)[LD]>(lds);                       // current rows, by original tile row
+  TC (*sL)[LD] = reinterpret_cast<TC (*)[LD]>(lds + kTile * LD);          // multipliers: sL[r][C]
+  TC (*sF)[LD] = reinterpret_cast<TC (*)[LD]>(lds + 2 * kTile * LD);      // factored tile in pivot order
+  TC (*sFT)[LD] = reinterpret_cast<TC (*)[LD]>(lds + 3 * kTile * LD);     // its transpose
+  TC* sD = lds + 4 * kTile * LD;                                         // reciprocals of U's diagonal
   // The tile (rows and columns past the matrix become identity rows): all
   // loads first, from the whole LDS tile or clamped matrix addresses, so
   // that no load waits under a per-element branch.
-  T a[16];
+  TC a[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int c = 16 * half + t;
-    a[t] = sT ? sT[r * ldt + c] : gload(A + static_cast<int64_t>(t0 + min(r, ts - 1)) * b + t0 + min(c, ts - 1));
+    a[t] = static_cast<TC>(sT ? sT[r * ldt + c] : gload(A + static_cast<int64_t>(t0 + min(r, ts - 1)) * b + t0 + min(c, ts - 1)));
   }
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int c = 16 * half + t;
-    if (!(r < ts && c < ts)) a[t] = r == c ? T(1) : T(0);
+    if (!(r < ts && c < ts)) a[t] = r == c ? TC(1) : TC(0);
   }
   bool done = false;
   int pos = r;  // position of this row in the factored tile (rows >= ts keep theirs)
@@ -1418,18 +1468,18 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
   // LDS accesses are off the critical path.  The pivot search of column
   // C + 1 ranks the rows by |piv yc - xc u1| = |piv| |yn| (the same order as
   // |yn|), so it does not wait for the reciprocal of the pivot.
-  T xc = sR[r][0], yc = sR[r][1];
+  TC xc = sR[r][0], yc = sR[r][1];
   int p = half_argmax(pivot_key(xc, half == 0 && r < ts, r), 0);
   bool bad = false;
   for (int C = 0; C < ts; ++C) {
     // Reads of the pivot row first: their latency overlaps the search.
     const int c2 = min(C + 2, kTile + 1);
-    const T y2 = sR[r][c2], u2 = sR[p][c2];
-    T prow[16];
+    const TC y2 = sR[r][c2], u2 = sR[p][c2];
+    TC prow[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) prow[t] = sR[p][16 * half + t];
-    const T piv = read_lane(xc, p);
-    const T u1 = read_lane(yc, p);
+    const TC piv = read_lane(xc, p);
+    const TC u1 = read_lane(yc, p);
     const bool act = !done && r < ts && r != p;
     if (r == p) {
       done = true;
@@ -1439,13 +1489,13 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
     // basic block; unused after the last column), then the multiplier and
     // columns C + 1 and C + 2 of every row; the scheduling barriers keep
     // this chain ahead of the bulk row update.
-    const T ys = fma(piv, yc, -(xc * u1));
+    const TC ys = fma(piv, yc, -(xc * u1));
     const int pn = half_argmax(pivot_key(ys, half == 0 && !done && r < ts, r), 0);
-    bad = bad || !(piv != T(0) && isfinite(piv));
-    const T rinv = piv != T(0) ? tile_rcp(piv) : T(0);
-    const T lm = act ? xc * rinv : T(0);
-    const T yn = fma(-lm, u1, yc);  // column C + 1 after this step
-    const T z = fma(-lm, u2, y2);   // column C + 2 after this step
+    bad = bad || !(piv != TC(0) && isfinite(piv));
+    const TC rinv = piv != TC(0) ? tile_rcp(piv) : TC(0);
+    const TC lm = act ? xc * rinv : TC(0);
+    const TC yn = fma(-lm, u1, yc);  // column C + 1 after this step
+    const TC z = fma(-lm, u2, y2);   // column C + 2 after this step
     __builtin_amdgcn_sched_barrier(0);
     sL[r][C] = lm;  // every lane (both halves store the same value); read only for rows chosen later
 #pragma unroll
@@ -1463,7 +1513,7 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
   wave_lds_order();
   // Factored row in pivot order: multipliers left of its pivot column, U
   // from there on (rows past the tile edge are identity rows).
-  T fv[16];
+  TC fv[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) fv[t] = sL[r][16 * half + t];  // read in full, used left of pos
 #pragma unroll
@@ -1477,6 +1527,16 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
     sF[pos][c] = fv[t];
     sFT[c][pos] = fv[t];
   }
+  {
+    // Growth: the tile's entries of U (the row from its pivot column on).
+    float um = 0.f;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int c = 16 * half + t;
+      if (r < ts && c >= pos && c < ts) um = nan_fmax(um, static_cast<float>(fabs(a[t])));
+    }
+    note_umax(it.swaps + kUmaxWord, um);
+  }
   // Row movement of the tile: position pos holds original tile row r.  Rows
   // never leave their band, so the band's permutation entries are t0 + r.
   if (half == 0 && r < ts) {
@@ -1484,7 +1544,7 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
     gstore(it.perm + t0 + pos, t0 + r);
   }
   wave_lds_order();
-  if (l < kTile) sD[l] = T(1) / sF[l][l];
+  if (l < kTile) sD[l] = TC(1) / sF[l][l];
   wave_lds_order();
   // Inverses of the tile's triangular factors by forward substitution in
   // column (axpy) form, every update of a step independent:
@@ -1494,17 +1554,17 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
   // Element i of operand row q + 1 is read from LDS as soon as step q has
   // used element i of row q (scheduling barriers keep every step's reads
   // next to it), so one row of registers holds the operand.
-  const T* Mq = half ? &sF[0][0] : &sFT[0][0];
-  T xs[kTile];
+  const TC* Mq = half ? &sF[0][0] : &sFT[0][0];
+  TC xs[kTile];
 #pragma unroll
-  for (int q = 0; q < kTile; ++q) xs[q] = (q == r) ? T(1) : T(0);
-  T mrow[kTile];
+  for (int q = 0; q < kTile; ++q) xs[q] = (q == r) ? TC(1) : TC(0);
+  TC mrow[kTile];
 #pragma unroll
   for (int i = 1; i < kTile; ++i) mrow[i] = Mq[i];
-  T dq = sD[0];
+  TC dq = sD[0];
 #pragma unroll
   for (int q = 0; q < kTile; ++q) {
-    const T xq = half ? xs[q] * dq : xs[q];
+    const TC xq = half ? xs[q] * dq : xs[q];
     xs[q] = xq;
     if (q + 1 < kTile) dq = sD[q + 1];
 #pragma unroll
@@ -1517,10 +1577,10 @@ __device__ __forceinline__ void tile_lu_wave(const LuItem& item, int t0, const T
   T* aux = step_inv<T>(it, s);
   if (half == 0) {
 #pragma unroll
-    for (int i = 0; i < kTile; ++i) gstore(aux + i * kTile + r, xs[i]);  // L^{-1}[i][r]
+    for (int i = 0; i < kTile; ++i) gstore(aux + i * kTile + r, static_cast<T>(xs[i]));  // L^{-1}[i][r]
   } else {
 #pragma unroll
-    for (int i = 0; i < kTile; ++i) gstore(aux + kTile * kTile + r * kTile + i, xs[i]);  // U^{-1}[r][i]
+    for (int i = 0; i < kTile; ++i) gstore(aux + kTile * kTile + r * kTile + i, static_cast<T>(xs[i]));  // U^{-1}[r][i]
   }
 }
 
@@ -1543,23 +1603,62 @@ __device__ __forceinline__ void step_diag_inverse(const LuItem& it, int q) {
   }
 }
 
-template <typename T>
+// C: the arithmetic of the tile factorisation (double for the mixed paths'
+// float matrices: their pivot selection and smallest-block LU run in FP64).
+template <typename T, typename C>
 __global__ __launch_bounds__(64) void k_tile_lu(const LuItem* items, int t0) {
-  __shared__ __attribute__((aligned(16))) T lds[kLuLdsElems];
-  tile_lu_wave<T>(items[blockIdx.x], t0, nullptr, 0, lds);
+  __shared__ __attribute__((aligned(16))) C lds[kLuLdsElems];
+  tile_lu_wave<T, C>(items[blockIdx.x], t0, nullptr, 0, lds);
   if (t0 == 0 && items[blockIdx.x].b <= kTile) {
     __threadfence();  // the inverses this wavefront stored to aux
     step_diag_inverse<T>(items[blockIdx.x], 0);
   }
 }
 
+// Element growth of the tile-pivoting LUs (words kAmaxWord.. and kUmaxWord of
+// LuItem::swaps).  Before the factorisation workgroup g records the largest
+// magnitude of rows [b g / P, b (g + 1) / P) (P = kAmaxParts) and workgroup 0
+// clears the |U| maximum that the factorisation then raises.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_amax(const LuItem* items) {
+  const LuItem it = items[blockIdx.y];
+  const int b = it.b, g = blockIdx.x;
+  const int64_t r0 = static_cast<int64_t>(b) * g / kAmaxParts, r1 = static_cast<int64_t>(b) * (g + 1) / kAmaxParts;
+  const T* A = static_cast<const T*>(it.a);
+  float m = 0.f;
+  for (int64_t e = r0 * b + threadIdx.x; e < r1 * b; e += 256) m = nan_fmax(m, static_cast<float>(fabs(gload(A + e))));
+  __shared__ float part[4];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = nan_fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = nan_fmax(nan_fmax(part[0], part[1]), nan_fmax(part[2], part[3]));
+    it.swaps[kAmaxWord + g] = __float_as_int(m);
+    if (g == 0) it.swaps[kUmaxWord] = 0;
+  }
+}
+
+// After the factorisation: growth above kGrowthLimit (or a non-finite |U|)
+// is reported like a failed pivot of this Schur operation.  One wavefront
+// per matrix.
+__global__ __launch_bounds__(64) void k_lu_check(const LuItem* items) {
+  const LuItem it = items[blockIdx.x];
+  const int l = threadIdx.x;
+  float a = l < kAmaxParts ? __int_as_float(it.swaps[kAmaxWord + l]) : 0.f;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) a = nan_fmax(a, __shfl_xor(a, o, 64));
+  const float u = __int_as_float(it.swaps[kUmaxWord]);
+  if (l == 0 && it.info && !(u <= kGrowthLimit * a)) atomicCAS(it.info, 0, it.node + 1);
+}
+
 // Base case of the recursive LU (launch_getrf_rec): diagonal tile t0 / kTile
 // is factored and replaced by its packed inverses (L^{-1} strictly below the
 // diagonal, U^{-1} on and above it), its permutation composed into perm.
-template <typename T>
+template <typename T, typename C>
 __global__ __launch_bounds__(64) void k_tile_lu_inv(const LuItem* items, int t0) {
-  __shared__ __attribute__((aligned(16))) T lds[kLuLdsElems];
-  tile_lu_wave<T>(items[blockIdx.x], t0, nullptr, 0, lds);
+  __shared__ __attribute__((aligned(16))) C lds[kLuLdsElems];
+  tile_lu_wave<T, C>(items[blockIdx.x], t0, nullptr, 0, lds);
   __threadfence();  // the inverses this wavefront stored to aux
   step_diag_inverse<T>(items[blockIdx.x], t0 / kTile);
 }
@@ -1647,7 +1746,7 @@ __device__ __forceinline__ void stage_linv_perm(const LuItem& it, int s, T* sLi)
   }
 }
 
-template <typename T>
+template <typename T, typename C>
 __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem) {
   T* A = static_cast<T*>(it.a);
   const int b = it.b, s = t0 / kTile, t1 = t0 + kTile, ts1 = min(kTile, b - t1);
@@ -1709,7 +1808,9 @@ __device__ __forceinline__ void step_lookahead(const LuItem& it, int t0, T* smem
     sT[x * kStepLd + y] = acc[v];
   }
   __syncthreads();
-  if (wave == 0) tile_lu_wave<T>(it, t1, sT, kStepLd, sA);
+  // (sA sits 8-byte aligned, and the workgroup's LDS holds kStepLdsElems
+  // doubles, room for the factorisation's scratch in C after it)
+  if (wave == 0) tile_lu_wave<T, C>(it, t1, sT, kStepLd, reinterpret_cast<C*>(sA));
 }
 
 template <typename T>
@@ -1899,11 +2000,16 @@ __device__ __forceinline__ void step_strip_cols(const LuItem& it, int t0, int j,
     typename MF<T>::acc acc;
     zero_acc<T>(acc);
     frag_mma<T, false>(sLi + 16 * gi * kStepLd, kStepLd, sB + 16 * gj, kStepLdw, acc);
+    float um = 0.f;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int y = C0 + 16 * gj + (lane & 15);
-      if (y < b) gstore(A + static_cast<int64_t>(tp + 16 * gi + MF<T>::row(lane, v)) * b + y, acc[v]);
+      if (y < b) {
+        gstore(A + static_cast<int64_t>(tp + 16 * gi + MF<T>::row(lane, v)) * b + y, acc[v]);
+        um = nan_fmax(um, static_cast<float>(fabs(acc[v])));
+      }
     }
+    note_umax(it.swaps + kUmaxWord, um);  // U12 of tile s - 1
   }
 }
 
@@ -1946,9 +2052,12 @@ struct StepShape {
   __host__ __device__ int total() const { return look + trail_n * trail_n + 2 * strip + band; }
 };
 
-template <typename T>
+template <typename T, typename C>
 __global__ __launch_bounds__(256) void k_lu_step(const LuItem* items, int t0) {
-  __shared__ __attribute__((aligned(16))) T smem[kStepLdsElems];
+  // kStepLdsElems doubles whatever T is: the look-ahead factorisation may
+  // compute a float matrix's tile in double.
+  __shared__ __attribute__((aligned(16))) double smem_raw[kStepLdsElems];
+  T* smem = reinterpret_cast<T*>(smem_raw);
   // Workgroups are numbered matrix-fastest: the look-ahead workgroups of all
   // matrices come first, and consecutive workgroups (which the dispatcher
   // spreads over the XCDs in turn) of one matrix land on the same XCDs, so
@@ -1961,7 +2070,7 @@ __global__ __launch_bounds__(256) void k_lu_step(const LuItem* items, int t0) {
   const StepShape sh(it.b, t0);
   int bx = role;
   if (bx < sh.look) {
-    step_lookahead<T>(it, t0, smem);
+    step_lookahead<T, C>(it, t0, smem);
     return;
   }
   bx -= sh.look;
@@ -2281,16 +2390,26 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
   }
 }
 
-template <typename T>
-hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, hipStream_t st) {
+template <typename T, typename C>
+hipError_t launch_getrf_tile_c(const LuItem* d_items, int count, int b, hipStream_t st) {
+  hipLaunchKernelGGL((k_lu_amax<T>), dim3(kAmaxParts, count), dim3(256), 0, st, d_items);
   // Tile 0, then one launch per diagonal tile (k_lu_step): the launch of tile
   // s factors tile s + 1, so consecutive launches form the critical path.
-  hipLaunchKernelGGL((k_tile_lu<T>), dim3(count), dim3(64), 0, st, d_items, 0);
+  hipLaunchKernelGGL((k_tile_lu<T, C>), dim3(count), dim3(64), 0, st, d_items, 0);
   for (int t0 = 0; t0 < b; t0 += kTile) {
     const int grid = StepShape(b, t0).total();
-    if (grid > 0) hipLaunchKernelGGL((k_lu_step<T>), dim3(grid, count), dim3(256), 0, st, d_items, t0);
+    if (grid > 0) hipLaunchKernelGGL((k_lu_step<T, C>), dim3(grid, count), dim3(256), 0, st, d_items, t0);
   }
+  hipLaunchKernelGGL(k_lu_check, dim3(count), dim3(64), 0, st, d_items);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, bool wide, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    if (wide) return launch_getrf_tile_c<float, double>(d_items, count, b, st);
+  }
+  return launch_getrf_tile_c<T, T>(d_items, count, b, st);
 }
 
 // Recursive LU with inverted factors.  For a node of order 2h at origin o,
@@ -2305,14 +2424,14 @@ hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, hipStream_
 // inversion would leave (L^{-1} below the diagonal, U^{-1} on and above it)
 // together with perm, so no triangular inversion follows.  Needs b =
 // kTile * 2^m and a b x b shadow in LuItem::tmp.
-template <typename T>
+template <typename T, typename C>
 hipError_t getrf_rec_node(const LuItem* d_items, int count, int o, int n, hipStream_t st) {
   if (n <= kTile) {
-    hipLaunchKernelGGL((k_tile_lu_inv<T>), dim3(count), dim3(64), 0, st, d_items, o);
+    hipLaunchKernelGGL((k_tile_lu_inv<T, C>), dim3(count), dim3(64), 0, st, d_items, o);
     return hipGetLastError();
   }
   const int h = n / 2;
-  hipError_t e = getrf_rec_node<T>(d_items, count, o, h, st);
+  hipError_t e = getrf_rec_node<T, C>(d_items, count, o, h, st);
   if (e != hipSuccess) return e;
   GemmLaunch L{};
   L.elem = sizeof(T);
@@ -2325,7 +2444,7 @@ hipError_t getrf_rec_node(const LuItem* d_items, int count, int o, int n, hipStr
   if ((e = launch_gemm<T>(L, h, h, st)) != hipSuccess) return e;
   L.mode = GEMM_RLU_B;
   if ((e = launch_gemm<T>(L, h, h, st)) != hipSuccess) return e;
-  if ((e = getrf_rec_node<T>(d_items, count, o + h, h, st)) != hipSuccess) return e;
+  if ((e = getrf_rec_node<T, C>(d_items, count, o + h, h, st)) != hipSuccess) return e;
   L.mode = GEMM_RLU_C;
   if ((e = launch_gemm<T>(L, h, h, st)) != hipSuccess) return e;
   L.mode = GEMM_RLU_D;
@@ -2334,8 +2453,16 @@ hipError_t getrf_rec_node(const LuItem* d_items, int count, int o, int n, hipStr
 }
 
 template <typename T>
-hipError_t launch_getrf_rec(const LuItem* d_items, int count, int b, hipStream_t st) {
-  return getrf_rec_node<T>(d_items, count, 0, b, st);
+hipError_t launch_getrf_rec(const LuItem* d_items, int count, int b, bool wide, hipStream_t st) {
+  hipLaunchKernelGGL((k_lu_amax<T>), dim3(kAmaxParts, count), dim3(256), 0, st, d_items);
+  hipError_t e;
+  if (sizeof(T) == 4 && wide)
+    e = getrf_rec_node<T, double>(d_items, count, 0, b, st);
+  else
+    e = getrf_rec_node<T, T>(d_items, count, 0, b, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lu_check, dim3(count), dim3(64), 0, st, d_items);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -2419,10 +2546,10 @@ hipError_t launch_fill_int(int32_t* p, int n, int v, hipStream_t st) {
 template hipError_t launch_gemm<double>(const GemmLaunch&, int, int, hipStream_t);
 template hipError_t launch_gemm<float>(const GemmLaunch&, int, int, hipStream_t);
 template hipError_t launch_getrf<double>(const LuItem*, int, int, hipStream_t);
-template hipError_t launch_getrf_tile<double>(const LuItem*, int, int, hipStream_t);
-template hipError_t launch_getrf_rec<double>(const LuItem*, int, int, hipStream_t);
-template hipError_t launch_getrf_rec<float>(const LuItem*, int, int, hipStream_t);
-template hipError_t launch_getrf_tile<float>(const LuItem*, int, int, hipStream_t);
+template hipError_t launch_getrf_tile<double>(const LuItem*, int, int, bool, hipStream_t);
+template hipError_t launch_getrf_rec<double>(const LuItem*, int, int, bool, hipStream_t);
+template hipError_t launch_getrf_rec<float>(const LuItem*, int, int, bool, hipStream_t);
+template hipError_t launch_getrf_tile<float>(const LuItem*, int, int, bool, hipStream_t);
 template hipError_t launch_getrf<float>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_trtri<double>(const LuItem*, int, int, bool, hipStream_t);
 template hipError_t launch_trtri<float>(const LuItem*, int, int, bool, hipStream_t);

@@ -466,10 +466,11 @@ void account(Plan& p) {
 }  // namespace
 
 int64_t getrf_launches(int b, LuKind kind) {
+  // tile pivoting: two more launches record the element growth
   // recursive: one launch per diagonal tile, four per inner node
-  if (kind == LU_RECURSIVE) return b / kTile + 4 * (b / kTile - 1);
+  if (kind == LU_RECURSIVE) return 2 + b / kTile + 4 * (b / kTile - 1);
   const bool tile_pivoting = kind == LU_TILE;
-  if (tile_pivoting) return 1 + (b > kTile ? (b + kTile - 1) / kTile : 0);  // first tile, one launch per tile
+  if (tile_pivoting) return 3 + (b > kTile ? (b + kTile - 1) / kTile : 0);  // first tile, one launch per tile
   int64_t n = 0;
   for (int j = 0; j < b;) {
     const int w = std::min(panel_width(b - j), b - j);
@@ -789,6 +790,55 @@ Plan make_column_plan(int64_t n, int k, int j, int width) {
   return plan;
 }
 
+namespace {
+
+// Blocks of Gamma read by the products of a step are first converted into
+// slots by a load step (numbered from `base`, live for that step only), so
+// that the products of a float recursion only read float slots while M
+// stays in its own precision; returns the most slots one step needed.
+int stage_matrix_blocks(Plan& p, int base) {
+  std::vector<Step> out;
+  out.reserve(p.steps.size() * 2);
+  int most = 0;
+  for (Step& st : p.steps) {
+    if (st.kind == ST_LOAD || st.kind == ST_GETRF || st.kind == ST_TRTRI) {
+      out.push_back(std::move(st));
+      continue;
+    }
+    std::vector<std::pair<int, int>> blocks;  // unique (r, c) in first-use order
+    auto slot_of = [&](Opnd& o) {
+      if (o.kind != OPND_MBLK) return;
+      const std::pair<int, int> rc(o.a, o.b);
+      size_t u = 0;
+      while (u < blocks.size() && blocks[u] != rc) ++u;
+      if (u == blocks.size()) blocks.push_back(rc);
+      o = Opnd::slot(base + static_cast<int>(u));
+    };
+    for (StepItem& it : st.items) {
+      slot_of(it.x);
+      slot_of(it.y);
+      slot_of(it.cin);
+      slot_of(it.sub);
+    }
+    if (!blocks.empty()) {
+      Step ld{ST_LOAD, {}};
+      for (size_t u = 0; u < blocks.size(); ++u) {
+        StepItem it;
+        it.dst = Opnd::slot(base + static_cast<int>(u));
+        it.x = Opnd::mblk(blocks[u].first, blocks[u].second);
+        ld.items.push_back(it);
+      }
+      out.push_back(std::move(ld));
+      most = std::max(most, static_cast<int>(blocks.size()));
+    }
+    out.push_back(std::move(st));
+  }
+  p.steps = std::move(out);
+  return most;
+}
+
+}  // namespace
+
 RefinePlans make_refine_plans(int64_t n, int k, int j, int width, bool reuse) {
   RefinePlans rp;
   init_column_plan(rp.column, n, k, j, width);
@@ -841,6 +891,11 @@ RefinePlans make_refine_plans(int64_t n, int k, int j, int width, bool reuse) {
     pool.release(acc);
   }
   rp.column.nslots = rp.solve.nslots = std::max(B.pool().peak, pool.peak);
+  // The float recursion reads M only through staged loads (converted to
+  // float, scaled, identity padding synthesised) into slots past the plans'.
+  const int base = rp.column.nslots;
+  const int staged = std::max(stage_matrix_blocks(rp.column, base), stage_matrix_blocks(rp.solve, base));
+  rp.column.nslots = rp.solve.nslots = base + staged;
   rp.column.algorithmic_flops = rp.solve.algorithmic_flops = 0;
   account(rp.column);
   account(rp.solve);

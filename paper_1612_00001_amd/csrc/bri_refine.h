@@ -16,7 +16,6 @@ struct RefItem {
   const double* M;  // n x n, leading dimension ldm
   int64_t n, ldm, kb;
   int32_t b, j;     // block order, target block column
-  float* G;         // sigma Gamma, kb x kb
   double* X;        // iterate, kb x b
   double* R;        // residual, kb x b
   float* R32;       // s R
@@ -27,8 +26,6 @@ struct RefItem {
 // All launchers take a device array of count items; largest sizes bound the grid.
 // atomicMax of |M| (which = 0) or |R| (which = 1) into scal[which] (cleared first).
 hipError_t launch_absmax(const RefItem* items, int count, int which, int64_t max_elems, hipStream_t st);
-// G = sigma Gamma, sigma = 2^-e from max |M|.
-hipError_t launch_gamma_f32(const RefItem* items, int count, int64_t max_elems, hipStream_t st);
 // Completes R = E_j - Gamma X after R[0:n) = -M X[0:n).
 hipError_t launch_resid_fix(const RefItem* items, int count, int64_t max_elems, hipStream_t st);
 // R32 = s R, s = 2^-e from max |R|.

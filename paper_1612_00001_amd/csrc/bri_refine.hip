@@ -85,17 +85,6 @@ __global__ __launch_bounds__(256) void k_absmax(const RefItem* items, int which)
               static_cast<unsigned long long>(__double_as_longlong(m)));
 }
 
-// G = sigma * Gamma (kb x kb, leading dimension kb) in float, sigma from scal[0].
-__global__ __launch_bounds__(256) void k_gamma_f32(const RefItem* items) {
-  const RefItem it = items[blockIdx.y];
-  const double sigma = pow2_scale(bits_to_double(it.scal));
-  for (int64_t e = first_elem(); e < it.kb * it.kb; e += elem_stride()) {
-    const int64_t r = e / it.kb, c = e - r * it.kb;
-    const double v = (r < it.n && c < it.n) ? it.M[r * it.ldm + c] : (r == c ? 1.0 : 0.0);
-    it.G[e] = static_cast<float>(sigma * v);
-  }
-}
-
 // R = E_j - Gamma X given R[0:n) = -M X[0:n): adds the unit entries of E_j in
 // rows < n and forms the identity-padding rows n <= r < kb.
 __global__ __launch_bounds__(256) void k_resid_fix(const RefItem* items) {
@@ -187,12 +176,6 @@ inline dim3 grid_for(int64_t max_elems, int count) {
 hipError_t launch_absmax(const RefItem* items, int count, int which, int64_t max_elems, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_absmax, grid_reduce(max_elems, count), dim3(256), 0, st, items, which);
-  return hipGetLastError();
-}
-
-hipError_t launch_gamma_f32(const RefItem* items, int count, int64_t max_elems, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gamma_f32, grid_for(max_elems, count), dim3(256), 0, st, items);
   return hipGetLastError();
 }
 

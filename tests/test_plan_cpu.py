@@ -338,3 +338,44 @@ def test_reuse_refine_plans(n, k, j, W):
     r = np.random.default_rng(n).standard_normal((k * b, b))
     y = run_plan(m, k, solve, rhs=r, state=state)
     assert np.abs(np.vstack([y[t] for t in range(k)]) - inv @ r).max() < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed_f16"])
+def test_workspace_budget_narrows_the_width(precision):
+    # The memory / time trade-off of Theorem "MC_BRI": with a budget the
+    # automatic width shrinks (by factors of 4) until the workspace fits;
+    # below the width-1 workspace nothing fits.
+    n, k = 16384, 8
+    m_bytes = 8 * n * n
+    free = bri.workspace_size(n, k, 0, 0, precision)
+    w_free = bri.plan_describe(n, k, 0, 0, precision)["batch_width"]
+    last_w = w_free
+    for frac in (2.0, 1.0, 0.5, 0.25):
+        budget = int(frac * m_bytes)
+        need = bri.workspace_size(n, k, 0, 0, precision, workspace_budget=budget)
+        if need == 0:
+            continue
+        assert need <= budget
+        w = bri.plan_describe(n, k, 0, 0, precision, workspace_budget=budget)["batch_width"]
+        assert w <= last_w
+        last_w = w
+        if free <= budget:
+            assert need == free
+    w1 = bri.workspace_size(n, k, 0, 0, precision, concurrency=1)
+    assert bri.workspace_size(n, k, 0, 0, precision, workspace_budget=w1) == w1
+    assert bri.workspace_size(n, k, 0, 0, precision, workspace_budget=w1 - 1) == 0
+    # the FP64 path fits a quarter of M at width 1
+    if precision == "f64":
+        assert w1 <= m_bytes // 4
+
+
+def test_mixed_workspace_below_the_matrix_at_width_one():
+    # The mixed paths read M in place (block loads convert and scale it), so
+    # at the precision workload's shape (k = 8) their workspace at width 1
+    # stays below the size of M itself (about 0.67 of it: the FP64 block
+    # column and residual of the refinement, 2 k b^2 doubles = 2 / k of M,
+    # their float images, and the float slots with the k kept pivots).  At
+    # k = 4 the column buffers alone are half of M's size.
+    n, k = 16384, 8
+    need = bri.workspace_size(n, k, 0, 0, "mixed_f16", concurrency=1)
+    assert 0 < need < 0.75 * 8 * n * n

@@ -76,13 +76,15 @@ def haar_spd(n: int, seed, lo_exp: float = 0.0, hi_exp: float = 2.0,
 
 
 def haar_spd_device(n: int, seed, lo_exp: float = 0.0, hi_exp: float = 2.0, pin_endpoints: bool = False,
-                    device="cuda:0"):
+                    device="cuda:0", return_factors: bool = False):
     """The ``haar_spd`` recipe with the O(n^3) steps (QR, Q Lam Q^T) done by
     torch on ``device`` in float64, for sizes where the host would take
     minutes.  Same draws as ``haar_spd`` (the Gaussian and the eigenvalues
     come from the same seeded generator, in the same order); Q differs from
     the host one only by rounding (the QR is unique once the sign of
-    diag(R) is fixed).  Returns a float64 device tensor."""
+    diag(R) is fixed).  Returns a float64 device tensor, or with
+    ``return_factors`` the tuple (M, Q, lam) with Q on the device and lam a
+    host array."""
     import torch
 
     rng = rng_for(seed)
@@ -96,8 +98,11 @@ def haar_spd_device(n: int, seed, lo_exp: float = 0.0, hi_exp: float = 2.0, pin_
     q *= torch.sign(torch.diagonal(r))[None, :]
     del r
     m = (q * torch.from_numpy(lam).to(device)[None, :]) @ q.T.contiguous()
+    m = 0.5 * (m + m.T)
+    if return_factors:
+        return m, q, lam
     del q
-    return 0.5 * (m + m.T)
+    return m
 
 
 def tridiag_toeplitz(n: int, diag: float = 4.0, off: float = -1.0) -> np.ndarray:

@@ -169,6 +169,35 @@ int invert_block_batched(int count, const void* const* M, const int64_t* n, cons
                          const int* k, const int* i, const int* j, void* const* out,
                          const int64_t* ldo, const bri_opts* o);
 
+/* Several blocks of one matrix: blocks (i[t], j[t]) of M^{-1}, t < count, to
+ * out[t] (b x b, leading dimension ldo[t]).  i, j, out and ldo are HOST
+ * arrays.  All k^2 blocks, or any selection (such as the band of blocks near
+ * the diagonal), follow the paper's remark that the blocks can be computed
+ * independently and in parallel (Section "Conclusion"; Section
+ * "Implementation" obtains every block by its own run): the targets are the
+ * problems of one merged batch over the same M (invert_block_batched with
+ * M[t] = M), sharing its launches.  Workspace:
+ * bri_blocks_workspace_size().  d_info, if not NULL, holds count statuses.
+ * Argument codes: -p for argument p of this signature. */
+size_t bri_blocks_workspace_size(int64_t n, int k, int count, const int* i, const int* j, const bri_opts* o);
+int invert_blocks(const void* M, int64_t n, int64_t ldm, int k, int count, const int* i, const int* j,
+                  void* const* out, const int64_t* ldo, const bri_opts* o);
+
+/* Matrix-free M: block N_ij of A_gamma^{-1} for the LS-SVM cross-validation
+ * matrix of Section "Experimental results" (eq. A), of order m = npts + 1,
+ *   A_gamma = [[0, 1^T], [1, K + I / gamma]],  K_rc = exp(-||x_r - x_c||^2 / (2 sigma^2)),
+ * never stored: every block of it the recursion reads is evaluated from the
+ * data points by the block loads (the paper's remark that such a matrix can
+ * be computed element by element from the much smaller input data, Section
+ * "Implementation").
+ *   X   : npts x d data points, row-major, leading dimension ldx >= d; double
+ *         for BRI_F64, float for BRI_F32 (the other precisions: unsupported).
+ *   sigma, gamma > 0; k, i, j, out, ldo as for invert_block with n = npts + 1.
+ * Workspace: bri_rbf_workspace_size(); argument codes -p as usual. */
+size_t bri_rbf_workspace_size(int64_t npts, int d, int k, int i, int j, const bri_opts* o);
+int invert_block_rbf(const void* X, int64_t npts, int64_t ldx, int d, double sigma, double gamma,
+                     int k, int i, int j, void* out, int64_t ldo, const bri_opts* o);
+
 /* Adjoint of invert_block: for L = sum(G .* N_ij), writes
  *   grad_M = dL/dM = -(N_{i,:})^T G (N_{:,j})^T            (n x n, ld ldgm)
  * where N_{i,:} and N_{:,j} are block row i and block column j of M^{-1},

@@ -106,12 +106,25 @@ _SIGNATURES = [
     ("bri_refine_plan_dump", ctypes.c_int64,
      [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BriOpts),
       ctypes.POINTER(ctypes.c_int64), ctypes.c_int64]),
+    ("bri_blocks_workspace_size", ctypes.c_size_t,
+     [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+      ctypes.POINTER(BriOpts)]),
+    ("invert_blocks", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+      ctypes.POINTER(BriOpts)]),
+    ("bri_rbf_workspace_size", ctypes.c_size_t,
+     [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BriOpts)]),
+    ("invert_block_rbf", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(BriOpts)]),
     ("bri_gemm_workspace_size", ctypes.c_size_t, [ctypes.c_int]),
     ("bri_gemm", ctypes.c_int,
      [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
       ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64,
       ctypes.c_double, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.POINTER(BriOpts)]),
     ("bri_profile_enable", ctypes.c_int, [ctypes.c_int]),
+    ("bri_profile_read", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("bri_refine_last", ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int)]),
     ("bri_status_string", ctypes.c_char_p, [ctypes.c_int]),
@@ -276,6 +289,39 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
     return out
 
 
+def rbf_workspace_size(npts: int, d: int, k: int, i: int, j: int, precision: str = "f64",
+                       concurrency: int = 0, workspace_budget: int = 0) -> int:
+    o = make_opts(precision, concurrency, workspace_budget=workspace_budget)
+    return int(lib().bri_rbf_workspace_size(npts, d, k, i, j, ctypes.byref(o)))
+
+
+def invert_block_rbf(X: torch.Tensor, k: int, i: int, j: int, sigma: float, gamma: float,
+                     precision: str = "f64", info: Optional[torch.Tensor] = None, pivoting: str = "auto",
+                     concurrency: int = 0, workspace_budget: int = 0) -> torch.Tensor:
+    """Block (i, j) of A_gamma^{-1}, A_gamma the LS-SVM matrix of the points X
+    (npts x d, rows), order npts + 1, evaluated element by element on the
+    device (never stored)."""
+    dtype = _DTYPE_OF[precision]
+    _require_gpu(X, "X", dtype)
+    npts, d = X.shape
+    m = npts + 1
+    b = block_size(m, k)
+    o = make_opts(precision, concurrency, pivoting=pivoting, workspace_budget=workspace_budget)
+    need = lib().bri_rbf_workspace_size(npts, d, k, i, j, ctypes.byref(o))
+    out = torch.empty(b, b, dtype=dtype, device=X.device)
+    if need == 0:
+        _check(lib().invert_block_rbf(X.data_ptr(), npts, X.stride(0), d, sigma, gamma, k, i, j, out.data_ptr(),
+                                      out.stride(0), ctypes.byref(o)) or BRI_ERR_UNSUPPORTED)
+    ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = need
+    o.d_info = info.data_ptr() if info is not None else None
+    o.stream = _stream_ptr(X.device)
+    _check(lib().invert_block_rbf(X.data_ptr(), npts, X.stride(0), d, sigma, gamma, k, i, j, out.data_ptr(),
+                                  out.stride(0), ctypes.byref(o)))
+    return out
+
+
 def block_column(M: torch.Tensor, k: int, j: int, transpose: bool = False, precision: str = "f64",
                  concurrency: int = 0, factorization: str = "auto") -> torch.Tensor:
     """Block column j of Gamma^{-1} ((k*b) x b); with ``transpose`` the block
@@ -353,6 +399,43 @@ def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Seq
     return outs
 
 
+def band_blocks(k: int, width: int = 0) -> List[tuple]:
+    """The blocks (i, j) with |i - j| <= width (width 0: the diagonal blocks)."""
+    return [(i, j) for i in range(k) for j in range(k) if abs(i - j) <= width]
+
+
+def invert_blocks(M: torch.Tensor, k: int, blocks: Optional[Sequence[tuple]] = None, precision: str = "f64",
+                  info: Optional[torch.Tensor] = None, pivoting: str = "auto") -> List[torch.Tensor]:
+    """Several blocks of M^{-1} (all k^2 when ``blocks`` is None), computed as
+    one merged batch over the same M; returns them in the order of ``blocks``."""
+    dtype = _DTYPE_OF[precision]
+    _require_gpu(M, "M", dtype)
+    n = M.shape[0]
+    if M.shape[1] != n:
+        raise ValueError("M must be square")
+    if blocks is None:
+        blocks = [(i, j) for i in range(k) for j in range(k)]
+    count = len(blocks)
+    b = block_size(n, k)
+    ii = (ctypes.c_int * count)(*[int(x[0]) for x in blocks])
+    jj = (ctypes.c_int * count)(*[int(x[1]) for x in blocks])
+    outs = [torch.empty(b, b, dtype=dtype, device=M.device) for _ in range(count)]
+    op = (ctypes.c_void_p * count)(*[o_.data_ptr() for o_ in outs])
+    ldo = (ctypes.c_int64 * count)(*[o_.stride(0) for o_ in outs])
+    o = make_opts(precision, pivoting=pivoting)
+    need = lib().bri_blocks_workspace_size(n, k, count, ii, jj, ctypes.byref(o))
+    if need == 0 and count > 0:
+        _check(lib().invert_blocks(M.data_ptr(), n, M.stride(0), k, count, ii, jj, op, ldo, ctypes.byref(o))
+               or BRI_ERR_UNSUPPORTED)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=M.device)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = need
+    o.d_info = info.data_ptr() if info is not None else None
+    o.stream = _stream_ptr(M.device)
+    _check(lib().invert_blocks(M.data_ptr(), n, M.stride(0), k, count, ii, jj, op, ldo, ctypes.byref(o)))
+    return outs
+
+
 def gemm(A: Sequence[torch.Tensor], B: Sequence[torch.Tensor], C: Sequence[torch.Tensor],
          alpha: float = 1.0, beta: float = 0.0, workspace: Optional[torch.Tensor] = None,
          products: Optional[str] = None) -> None:
@@ -403,6 +486,17 @@ class InvertBlock(torch.autograd.Function):
         (M,) = ctx.saved_tensors
         g = invert_block_backward(M, ctx.k, ctx.i, ctx.j, grad_out, precision=ctx.precision)
         return g, None, None, None, None
+
+
+class _ProfEntry(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+
+def profile_read_clear() -> None:
+    """Reads (and so clears) the step-timing record of bri_profile_*."""
+    arr = (_ProfEntry * 9)()
+    lib().bri_profile_read(ctypes.cast(arr, ctypes.c_void_p), 9)
 
 
 def refine_last() -> tuple:

@@ -84,14 +84,21 @@ struct CachedPlan {
   void* host = nullptr;  // pinned descriptor staging buffer
   hipEvent_t uploaded = nullptr;
   std::mutex mu;
+  // The last call's work captured as a HIP graph (upload, status clear and
+  // every kernel), replayed while a call's descriptors and launch settings
+  // are byte for byte those of the captured one.
+  hipGraphExec_t graph = nullptr;
+  std::vector<char> graph_desc;  // descriptors (and settings) the graph was captured with
   ~CachedPlan() {
+    if (graph) (void)hipGraphExecDestroy(graph);
     if (uploaded) (void)hipEventDestroy(uploaded);
     if (host) (void)hipHostFree(host);
   }
 };
 
 typedef std::tuple<int, int64_t, int, int, int, int, int, int> PlanKey;  // kind,n,k,i,j,width,elem,transpose
-// kind: 0 block plan, 1 block column plan, 2 block plan with kept pivots
+// kind: 0 block plan, 1 block column plan, 2 block plan with kept pivots,
+// 3 block plan reading M through staged block loads only
 
 std::mutex g_cache_mu;
 std::map<PlanKey, std::shared_ptr<CachedPlan>>& cache() {
@@ -164,6 +171,7 @@ std::shared_ptr<CachedPlan> get_plan(int kind, int64_t n, int k, int i, int j, i
   auto cp = std::make_shared<CachedPlan>();
   cp->plan = kind == 0   ? make_block_plan(n, k, i, j, width)
              : kind == 2 ? make_block_plan_reuse(n, k, i, j, width)
+             : kind == 3 ? make_block_plan_staged(n, k, i, j, width)
                          : make_column_plan(n, k, j, width);
   cp->plan.transpose = transpose;
   cp->layout = make_layout(cp->plan, elem);
@@ -194,6 +202,7 @@ struct Ctx {
   bool wide = false;    // float recursion whose tile factorisations compute in double
   int m_elem = 0;       // element size of M when it differs from elem (mixed: double M, float plan)
   const double* m_max = nullptr;  // mixed: max |M| on the device (blocks of M read scaled)
+  const RbfSource* rbf = nullptr;  // matrix-free M: its description on the device
 };
 
 // How the kernels of a plan are launched.
@@ -217,6 +226,8 @@ DView zero_view() {
   v.trans = 0;
   v.tri = 0;
   v.src64_max = nullptr;
+  v.rbf = nullptr;
+  v.r0 = v.c0 = 0;
   return v;
 }
 
@@ -262,6 +273,12 @@ DView resolve(const Ctx& c, const Opnd& o) {
       }
       v.trans = static_cast<int16_t>(c.transpose ? 1 : 0);
       v.src64_max = c.m_max;
+      if (c.rbf) {
+        v.rbf = c.rbf;
+        v.p = c.rbf;  // not read: the elements are evaluated
+        v.r0 = static_cast<int32_t>(r * b);
+        v.c0 = static_cast<int32_t>(col * b);
+      }
       return v;
     }
     case OPND_IDENT:
@@ -370,8 +387,8 @@ void describe_step(const Ctx& c, const Step& s, StepItems& out) {
       }
       default: {
         // A matrix in another precision is read through load steps only.
-        if (c.m_max && (it.x.kind == OPND_MBLK || it.y.kind == OPND_MBLK || it.cin.kind == OPND_MBLK ||
-                        it.sub.kind == OPND_MBLK))
+        if ((c.m_max || c.rbf) && (it.x.kind == OPND_MBLK || it.y.kind == OPND_MBLK || it.cin.kind == OPND_MBLK ||
+                                   it.sub.kind == OPND_MBLK))
           throw std::logic_error("unstaged block of M in a product");
         GemmItem g = gemm_base(c);
         g.out = dst_ptr(c, it.dst, g.ldo);
@@ -577,6 +594,81 @@ int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
   return run_exec<T>(ex, c.b, cfg_of(c), st);
 }
 
+// Enqueues the status clear, the descriptor upload (from cp.host) and the
+// kernels of plan cp on st.
+int enqueue_call(CachedPlan& cp, Ctx& c, bool clear_info, hipStream_t st) {
+  if (clear_info && launch_fill_int(c.info, 1, 0, st) != hipSuccess) return BRI_ERR_HIP;
+  if (cp.layout.desc_bytes > 0) {
+    if (hipMemcpyAsync(c.ws + cp.layout.desc_off, cp.host, cp.layout.desc_bytes, hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return BRI_ERR_HIP;
+  }
+  if (hipEventRecord(cp.uploaded, st) != hipSuccess) return BRI_ERR_HIP;
+  return c.elem == 8 ? run_steps<double>(c, cp.plan, st) : run_steps<float>(c, cp.plan, st);
+}
+
+// Graph capture of whole calls: for plans with few launches (where the
+// launch overhead counts), never while step timing is on.
+constexpr int64_t kGraphMaxLaunches = 4096;
+bool graph_eligible(const CachedPlan& cp) {
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (g_prof_on) return false;
+  }
+  return cp.plan.launches <= kGraphMaxLaunches && cp.layout.desc_bytes > 0;
+}
+
+// Everything a captured call depends on: its descriptors (which hold every
+// operand, output and status address) and the launch settings.
+std::vector<char> graph_key(const CachedPlan& cp, const Ctx& c, bool clear_info) {
+  std::vector<char> key(static_cast<const char*>(cp.host), static_cast<const char*>(cp.host) + cp.layout.desc_bytes);
+  struct Settings {
+    const void* ws;
+    const void* info;
+    int pivoting, lu, lp, elem, b, clear;
+  } st_{c.ws, c.info, c.pivoting, c.lu, c.lp, c.elem, c.b, clear_info ? 1 : 0};
+  const char* p = reinterpret_cast<const char*>(&st_);
+  key.insert(key.end(), p, p + sizeof(st_));
+  for (size_t s = 0; s < cp.layout.nfast.size(); ++s) {
+    const int32_t v[2] = {cp.layout.nfast[s], cp.layout.ndirect[s]};
+    key.insert(key.end(), reinterpret_cast<const char*>(v), reinterpret_cast<const char*>(v) + sizeof(v));
+  }
+  return key;
+}
+
+// A library-owned stream of the current device to capture on (the caller's
+// stream may be the legacy default stream, which cannot be captured).
+hipStream_t capture_stream() {
+  static std::mutex mu;
+  static hipStream_t per_device[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  if (!per_device[dev] && hipStreamCreateWithFlags(&per_device[dev], hipStreamNonBlocking) != hipSuccess)
+    per_device[dev] = nullptr;
+  return per_device[dev];
+}
+
+// The call's work captured into an executable graph (not run), or null.
+hipGraphExec_t capture_call(CachedPlan& cp, Ctx& c, bool clear_info) {
+  hipStream_t cs = capture_stream();
+  if (!cs) return nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+  bool ok = true;
+  if (clear_info) ok = launch_fill_int(c.info, 1, 0, cs) == hipSuccess;
+  if (ok && cp.layout.desc_bytes > 0)
+    ok = hipMemcpyAsync(c.ws + cp.layout.desc_off, cp.host, cp.layout.desc_bytes, hipMemcpyHostToDevice, cs) ==
+         hipSuccess;
+  if (ok) ok = (c.elem == 8 ? run_steps<double>(c, cp.plan, cs) : run_steps<float>(c, cp.plan, cs)) == BRI_OK;
+  hipGraph_t graph = nullptr;
+  const bool ended = hipStreamEndCapture(cs, &graph) == hipSuccess && graph;
+  hipGraphExec_t exec = nullptr;
+  if (ok && ended && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipGetLastError();  // a failed capture leaves no error behind for later calls
+  return ok ? exec : nullptr;
+}
+
 // Uploads the descriptors of plan cp for context c and enqueues its kernels.
 int execute(CachedPlan& cp, Ctx& c, hipStream_t st, bool clear_info) {
   c.lay = &cp.layout;
@@ -593,14 +685,24 @@ int execute(CachedPlan& cp, Ctx& c, hipStream_t st, bool clear_info) {
   } catch (const std::exception&) {
     return BRI_ERR_UNSUPPORTED;
   }
-  if (clear_info && launch_fill_int(c.info, 1, 0, st) != hipSuccess) return BRI_ERR_HIP;
-  if (cp.layout.desc_bytes > 0) {
-    if (hipMemcpyAsync(c.ws + cp.layout.desc_off, cp.host, cp.layout.desc_bytes, hipMemcpyHostToDevice, st) !=
-        hipSuccess)
-      return BRI_ERR_HIP;
+  // The whole call as one graph launch when it repeats the captured one.
+  if (graph_eligible(cp)) {
+    const std::vector<char> key = graph_key(cp, c, clear_info);
+    if (cp.graph && key == cp.graph_desc) {
+      if (hipGraphLaunch(cp.graph, st) != hipSuccess) return BRI_ERR_HIP;
+      return hipEventRecord(cp.uploaded, st) == hipSuccess ? BRI_OK : BRI_ERR_HIP;
+    }
+    hipGraphExec_t g = capture_call(cp, c, clear_info);
+    if (g) {
+      if (cp.graph) (void)hipGraphExecDestroy(cp.graph);
+      cp.graph = g;
+      cp.graph_desc = key;
+      if (hipGraphLaunch(cp.graph, st) != hipSuccess) return BRI_ERR_HIP;
+      return hipEventRecord(cp.uploaded, st) == hipSuccess ? BRI_OK : BRI_ERR_HIP;
+    }
+    // capture failed: run the call directly
   }
-  if (hipEventRecord(cp.uploaded, st) != hipSuccess) return BRI_ERR_HIP;
-  return c.elem == 8 ? run_steps<double>(c, cp.plan, st) : run_steps<float>(c, cp.plan, st);
+  return enqueue_call(cp, c, clear_info, st);
 }
 
 bool plain_precision(int p) { return p == BRI_F64 || p == BRI_F32; }
@@ -682,6 +784,33 @@ MergedLayout merge_layout(const std::vector<const Plan*>& plans) {
   return m;
 }
 
+// Helper streams of the current device on which the structure groups of a
+// merged batch run side by side (created once per device, default priority).
+struct GroupStreams {
+  static constexpr int kStreams = 4;  // the hardware queues a process gets by default
+  std::mutex mu;
+  hipStream_t stream[kStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kStreams] = {};
+};
+GroupStreams* group_streams() {
+  static std::mutex mu;
+  static GroupStreams* per_device[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  if (!per_device[dev]) {
+    auto* gs = new GroupStreams();
+    bool ok = hipEventCreateWithFlags(&gs->fork, hipEventDisableTiming) == hipSuccess;
+    for (int q = 0; ok && q < GroupStreams::kStreams; ++q)
+      ok = hipStreamCreateWithFlags(&gs->stream[q], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&gs->join[q], hipEventDisableTiming) == hipSuccess;
+    if (!ok) return nullptr;  // the merged batch then runs on the caller's stream alone
+    per_device[dev] = gs;
+  }
+  return per_device[dev];
+}
+
 struct MergedExec {
   std::vector<std::vector<ExecStep>> groups;
   std::vector<int> bmax;
@@ -720,9 +849,34 @@ MergedExec merge_write(const std::vector<const Plan*>& plans, const std::vector<
 
 template <typename T>
 int run_merged(const MergedExec& ex, const ExecCfg& cfg, hipStream_t st) {
+  bool prof;
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    prof = g_prof_on;
+  }
+  GroupStreams* gs = ex.groups.size() > 1 && !prof ? group_streams() : nullptr;
+  if (!gs) {
+    for (size_t g = 0; g < ex.groups.size(); ++g) {
+      const int rc = run_exec<T>(ex.groups[g], ex.bmax[g], cfg, st);
+      if (rc != BRI_OK) return rc;
+    }
+    return BRI_OK;
+  }
+  // The groups touch disjoint parts of the workspace (each problem its own
+  // region and status word, each group its own descriptors): they run side
+  // by side on the helper streams, forked from and joined into st.
+  std::lock_guard<std::mutex> lk(gs->mu);
+  if (hipEventRecord(gs->fork, st) != hipSuccess) return BRI_ERR_HIP;
+  const size_t ns = std::min<size_t>(GroupStreams::kStreams, ex.groups.size());
+  for (size_t q = 0; q < ns; ++q)
+    if (hipStreamWaitEvent(gs->stream[q], gs->fork, 0) != hipSuccess) return BRI_ERR_HIP;
   for (size_t g = 0; g < ex.groups.size(); ++g) {
-    const int rc = run_exec<T>(ex.groups[g], ex.bmax[g], cfg, st);
+    const int rc = run_exec<T>(ex.groups[g], ex.bmax[g], cfg, gs->stream[g % ns]);
     if (rc != BRI_OK) return rc;
+  }
+  for (size_t q = 0; q < ns; ++q) {
+    if (hipEventRecord(gs->join[q], gs->stream[q]) != hipSuccess) return BRI_ERR_HIP;
+    if (hipStreamWaitEvent(st, gs->join[q], 0) != hipSuccess) return BRI_ERR_HIP;
   }
   return BRI_OK;
 }
@@ -805,6 +959,15 @@ int run_batch(const BatchPlan& bp, const void* const* M, const int64_t* n, const
 bool batch_mergeable(const bri_opts* o) {
   return (o->pivoting == BRI_PIVOT_TILE || o->pivoting == BRI_PIVOT_AUTO) &&
          (plain_precision(o->precision) || mixed_precision(o->precision));
+}
+
+// Status word of a finished call (waits for the stream).
+int read_info1(const int32_t* d, int32_t& h, hipStream_t st) {
+  h = 0;
+  if (hipMemcpyAsync(&h, d, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return BRI_ERR_HIP;
+  return BRI_OK;
 }
 
 // Status words of a finished call (waits for the stream).
@@ -1392,8 +1555,10 @@ int64_t bri_refine_plan_dump(int64_t n, int k, int j, int which, const bri_opts*
   return dump_steps(which == 0 ? r->col->plan : r->sol->plan, words, cap);
 }
 
-int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, void* out, int64_t ldo,
-                 const bri_opts* o) {
+}  // extern "C"
+
+static int invert_block_impl(const void* M, int64_t n, int64_t ldm, int k, int i, int j, void* out, int64_t ldo,
+                             const bri_opts* o) {
   if (!M) return -1;
   if (!out) return -7;
   if (!o) return -9;
@@ -1412,12 +1577,12 @@ int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, voi
       t.d_info = block_info_word(n, k, i, j, o);
       if (!t.d_info) return BRI_ERR_WORKSPACE;
     }
-    int rc2 = invert_block(M, n, ldm, k, i, j, out, ldo, &t);
-    std::vector<int32_t> h;
-    if (rc2 == BRI_OK) rc2 = read_info(t.d_info, 1, h, o->stream);
-    if (rc2 != BRI_OK || h[0] <= 0) return rc2;
+    int rc2 = invert_block_impl(M, n, ldm, k, i, j, out, ldo, &t);
+    int32_t h = 0;
+    if (rc2 == BRI_OK) rc2 = read_info1(t.d_info, h, o->stream);
+    if (rc2 != BRI_OK || h <= 0) return rc2;
     t.pivoting = BRI_PIVOT_PANEL;
-    return invert_block(M, n, ldm, k, i, j, out, ldo, &t);
+    return invert_block_impl(M, n, ldm, k, i, j, out, ldo, &t);
   }
   if (mixed_precision(o->precision)) return invert_block_mixed(M, n, ldm, k, i, j, out, ldo, o);
   if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
@@ -1443,6 +1608,13 @@ int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, voi
   c.ldo = ldo;
   c.info = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(c.ws + cp->layout.info_off);
   return execute(*cp, c, o->stream, true);
+}
+
+extern "C" {
+
+int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, void* out, int64_t ldo,
+                 const bri_opts* o) {
+  return invert_block_impl(M, n, ldm, k, i, j, out, ldo, o);
 }
 
 static size_t column_size_of(int64_t n, int k, int j, const bri_opts* o) {
@@ -1641,6 +1813,145 @@ int invert_block_batched(int count, const void* const* M, const int64_t* n, cons
     if (rc != BRI_OK) return rc;
   }
   return BRI_OK;
+}
+
+size_t bri_blocks_workspace_size(int64_t n, int k, int count, const int* i, const int* j, const bri_opts* o) {
+  if (count <= 0 || !i || !j || !o) return 0;
+  std::vector<int64_t> nn(count, n);
+  std::vector<int> kk(count, k);
+  return bri_batched_workspace_size(count, nn.data(), kk.data(), i, j, o);
+}
+
+int invert_blocks(const void* M, int64_t n, int64_t ldm, int k, int count, const int* i, const int* j,
+                  void* const* out, const int64_t* ldo, const bri_opts* o) {
+  if (!M) return -1;
+  if (count < 0) return -5;
+  if (!i) return -6;
+  if (!j) return -7;
+  if (!out) return -8;
+  if (!ldo) return -9;
+  if (!o) return -10;
+  if (count == 0) return BRI_OK;
+  for (int t = 0; t < count; ++t) {
+    const int rc = check_block_args(n, ldm, k, i[t], j[t], ldo[t]);
+    if (rc == -5 || rc == -6) return rc - 1;  // i, j are arguments 6 and 7 here
+    if (rc == -8) return -9;
+    if (rc) return rc;
+    if (!out[t]) return -8;
+  }
+  std::vector<const void*> mm(count, M);
+  std::vector<int64_t> nn(count, n), ll(count, ldm);
+  std::vector<int> kk(count, k);
+  return invert_block_batched(count, mm.data(), nn.data(), ll.data(), kk.data(), i, j, out, ldo, o);
+}
+
+}  // extern "C"
+
+// The RbfSource of a matrix-free call sits in the workspace, past the
+// status word (the first kAlign bytes of the info region hold both).
+constexpr size_t kRbfOffset = 64;
+static_assert(kRbfOffset + sizeof(RbfSource) <= kAlign, "RbfSource in the status block");
+
+static size_t rbf_size_of(int64_t m, int k, int i, int j, const bri_opts* o) {
+  try {
+    return get_plan(3, m, k, i, j, resolve_width(m, k, o), elem_size(o->precision), 0)->layout.total;
+  } catch (const std::exception&) {
+    return 0;
+  }
+}
+
+static int check_rbf_args(int64_t npts, int64_t ldx, int d, double sigma, double gamma, int k, int i, int j,
+                          int64_t ldo, const bri_opts* o) {
+  if (npts < 1) return -2;
+  if (d < 1 || ldx < d) return -3;
+  if (!(sigma > 0.0)) return -5;
+  if (!(gamma > 0.0)) return -6;
+  const int64_t m = npts + 1;
+  const int rc = check_block_args(m, m, k, i, j, ldo);
+  if (rc == -4) return -7;
+  if (rc == -5) return -8;
+  if (rc == -6) return -9;
+  if (rc == -8) return -11;
+  if (rc) return rc;
+  if (!o) return -12;
+  if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
+  return 0;
+}
+
+static int invert_block_rbf_impl(const void* X, int64_t npts, int64_t ldx, int d, double sigma, double gamma, int k,
+                                 int i, int j, void* out, int64_t ldo, const bri_opts* o) {
+  const int64_t m = npts + 1;
+  if (o->pivoting == BRI_PIVOT_AUTO) {
+    bri_opts t = *o;
+    t.pivoting = BRI_PIVOT_TILE;
+    if (!t.d_info) {
+      const size_t need = rbf_size_of(m, k, i, j, o);
+      if (need == 0 || !o->workspace || o->workspace_bytes < need) return BRI_ERR_WORKSPACE;
+      auto cp = get_plan(3, m, k, i, j, resolve_width(m, k, o), elem_size(o->precision), 0);
+      t.d_info = reinterpret_cast<int32_t*>(static_cast<char*>(o->workspace) + cp->layout.info_off);
+    }
+    int rc2 = invert_block_rbf_impl(X, npts, ldx, d, sigma, gamma, k, i, j, out, ldo, &t);
+    int32_t h = 0;
+    if (rc2 == BRI_OK) rc2 = read_info1(t.d_info, h, o->stream);
+    if (rc2 != BRI_OK || h <= 0) return rc2;
+    t.pivoting = BRI_PIVOT_PANEL;
+    return invert_block_rbf_impl(X, npts, ldx, d, sigma, gamma, k, i, j, out, ldo, &t);
+  }
+  const int elem = elem_size(o->precision);
+  std::shared_ptr<CachedPlan> cp;
+  try {
+    cp = get_plan(3, m, k, i, j, resolve_width(m, k, o), elem, 0);
+  } catch (const std::exception&) {
+    return BRI_ERR_UNSUPPORTED;
+  }
+  if (!o->workspace || o->workspace_bytes < cp->layout.total) return BRI_ERR_WORKSPACE;
+  char* ws = static_cast<char*>(o->workspace);
+  RbfSource src;
+  src.X = X;
+  src.ldx = ldx;
+  src.npts = static_cast<int32_t>(npts);
+  src.d = d;
+  src.inv_two_sigma2 = 1.0 / (2.0 * sigma * sigma);
+  src.inv_gamma = 1.0 / gamma;
+  RbfSource* dsrc = reinterpret_cast<RbfSource*>(ws + cp->layout.info_off + kRbfOffset);
+  if (launch_store_rbf(dsrc, src, o->stream) != hipSuccess) return BRI_ERR_HIP;
+  Ctx c;
+  c.pivoting = o->pivoting;
+  c.lu = o->factorization;
+  c.M = static_cast<const char*>(X);
+  c.n = m;
+  c.ldm = m;
+  c.b = cp->plan.b;
+  c.elem = elem;
+  c.rbf = dsrc;
+  c.ws = ws;
+  c.out = static_cast<char*>(out);
+  c.ldo = ldo;
+  c.info = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(ws + cp->layout.info_off);
+  return execute(*cp, c, o->stream, true);
+}
+
+extern "C" {
+
+size_t bri_rbf_workspace_size(int64_t npts, int d, int k, int i, int j, const bri_opts* o) {
+  if (!o || check_rbf_args(npts, d, d, 1.0, 1.0, k, i, j, (npts + k) / k, o) != 0) return 0;
+  const int64_t m = npts + 1;
+  bool fits;
+  const bri_opts ob = with_budget(o, m, k, [&](const bri_opts& r) { return rbf_size_of(m, k, i, j, &r); }, fits);
+  return fits ? rbf_size_of(m, k, i, j, &ob) : 0;
+}
+
+int invert_block_rbf(const void* X, int64_t npts, int64_t ldx, int d, double sigma, double gamma, int k, int i,
+                     int j, void* out, int64_t ldo, const bri_opts* o) {
+  if (!X) return -1;
+  if (!out) return -10;
+  const int rc = check_rbf_args(npts, ldx, d, sigma, gamma, k, i, j, ldo, o);
+  if (rc) return rc;
+  const int64_t m = npts + 1;
+  bool fits;
+  const bri_opts ob = with_budget(o, m, k, [&](const bri_opts& r) { return rbf_size_of(m, k, i, j, &r); }, fits);
+  if (!fits) return BRI_ERR_WORKSPACE;
+  return invert_block_rbf_impl(X, npts, ldx, d, sigma, gamma, k, i, j, out, ldo, &ob);
 }
 
 size_t bri_gemm_workspace_size(int count) {

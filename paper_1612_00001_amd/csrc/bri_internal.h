@@ -21,7 +21,12 @@ namespace bri {
 //     with max |M| 2^-e in [0.5, 1), max |M| being the double at src64_max
 //     (the scaled matrix the mixed paths' float recursion works on).  Only
 //     the block loads (k_load) read such views.
+//   - rbf: when set, the elements inside the stored extent are not stored
+//     but evaluated: element (x, y) is element (r0 + x, c0 + y) of the
+//     matrix rbf describes (RbfSource), with (r0, c0) the view's origin.
+//     Only the block loads read such views.
 // ---------------------------------------------------------------------------
+struct RbfSource;
 struct DView {
   const void* p;
   int64_t ld;
@@ -30,6 +35,21 @@ struct DView {
   int32_t diag;
   int16_t trans, tri;
   const double* src64_max;
+  const RbfSource* rbf;
+  int32_t r0, c0;
+};
+
+// The matrix A_gamma of the LS-SVM cross-validation (Section "Experimental
+// results", eq. A), of order m = npts + 1, evaluated element by element from
+// the data points x_1..x_npts (rows of X, npts x d, leading dimension ldx):
+//   A(0, 0) = 0,  A(0, c) = A(c, 0) = 1,
+//   A(r, c) = exp(-||x_r - x_c||^2 / (2 sigma^2)) + [r == c] / gamma   (r, c >= 1).
+struct RbfSource {
+  const void* X;        // double (or float for BRI_F32) data points
+  int64_t ldx;
+  int32_t npts, d;
+  double inv_two_sigma2;  // 1 / (2 sigma^2)
+  double inv_gamma;       // 1 / gamma
 };
 
 // out[x, y] = beta * Cin[x, y] + alpha * sum_t A[x, t] B[t, y] - Sub[x, y]
@@ -239,6 +259,14 @@ struct RefinePlans {
   bool column_gives_x0 = true;   // false: the column plan only factors the pivots (reuse)
 };
 RefinePlans make_refine_plans(int64_t n, int k, int j, int width, bool reuse);
+
+// Blocks of Gamma read by the products of a step are first converted into
+// slots by a load step (slot numbers from base, live for that step only);
+// returns the most slots one step needed.  Used where M is read through
+// converting or evaluating loads only (mixed precisions, matrix-free M).
+int stage_matrix_blocks(Plan& p, int base);
+// make_block_plan with every block of M staged that way.
+Plan make_block_plan_staged(int64_t n, int k, int i, int j, int width);
 
 // The plan of invert_block with the k - 1 elimination pivots kept and reused
 // (each Schur node then has three children; the paper's suggested reuse

@@ -42,6 +42,21 @@ __device__ __forceinline__ double pow2_scale_of(double x) {
   return ldexp(1.0, -e);
 }
 
+// Element (r, c) of the matrix an RbfSource describes (see its definition);
+// T is the element type of the data points.
+template <typename T>
+__device__ __forceinline__ double rbf_element(const RbfSource& s, int64_t r, int64_t c) {
+  if (r == 0 || c == 0) return (r == 0 && c == 0) ? 0.0 : 1.0;
+  const T* xr = static_cast<const T*>(s.X) + (r - 1) * s.ldx;
+  const T* xc = static_cast<const T*>(s.X) + (c - 1) * s.ldx;
+  double d2 = 0.0;
+  for (int t = 0; t < s.d; ++t) {
+    const double u = static_cast<double>(xr[t]) - static_cast<double>(xc[t]);
+    d2 = fma(u, u, d2);
+  }
+  return exp(-d2 * s.inv_two_sigma2) + (r == c ? s.inv_gamma : 0.0);
+}
+
 template <typename T>
 __device__ __forceinline__ T vget(const DView& v, int x, int y) {
   if (v.tri == 1) {
@@ -51,6 +66,11 @@ __device__ __forceinline__ T vget(const DView& v, int x, int y) {
     if (x > y) return T(0);
   }
   const int xs = v.rowperm ? v.rowperm[x] : x;
+  if (v.rbf) {
+    if (xs < v.rows && y < v.cols)
+      return static_cast<T>(rbf_element<T>(*v.rbf, static_cast<int64_t>(v.r0) + xs, static_cast<int64_t>(v.c0) + y));
+    return (xs - y == v.diag) ? T(1) : T(0);
+  }
   if (v.src64_max) {
     double e = (xs - y == v.diag) ? 1.0 : 0.0;
     if (xs < v.rows && y < v.cols) {
@@ -78,6 +98,8 @@ __device__ __forceinline__ DView dense_view(const void* base, int64_t ld, int64_
   v.trans = 0;
   v.tri = static_cast<int16_t>(tri);
   v.src64_max = nullptr;
+  v.rbf = nullptr;
+  v.r0 = v.c0 = 0;
   return v;
 }
 
@@ -2535,6 +2557,15 @@ hipError_t launch_load(const LoadItem* d_items, int count, int rows, int cols, h
   int gx = cdiv(total, 256);
   if (gx > 4096) gx = 4096;
   hipLaunchKernelGGL((k_load<T>), dim3(gx, count), dim3(256), 0, st, d_items);
+  return hipGetLastError();
+}
+
+__global__ void k_store_rbf(RbfSource* dst, RbfSource src) {
+  if (threadIdx.x == 0) *dst = src;
+}
+
+hipError_t launch_store_rbf(RbfSource* dst, const RbfSource& src, hipStream_t st) {
+  hipLaunchKernelGGL(k_store_rbf, dim3(1), dim3(64), 0, st, dst, src);
   return hipGetLastError();
 }
 

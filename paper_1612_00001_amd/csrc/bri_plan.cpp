@@ -790,8 +790,6 @@ Plan make_column_plan(int64_t n, int k, int j, int width) {
   return plan;
 }
 
-namespace {
-
 // Blocks of Gamma read by the products of a step are first converted into
 // slots by a load step (numbered from `base`, live for that step only), so
 // that the products of a float recursion only read float slots while M
@@ -837,7 +835,12 @@ int stage_matrix_blocks(Plan& p, int base) {
   return most;
 }
 
-}  // namespace
+Plan make_block_plan_staged(int64_t n, int k, int i, int j, int width) {
+  Plan p = make_block_plan(n, k, i, j, width);
+  p.nslots += stage_matrix_blocks(p, p.nslots);
+  account(p);
+  return p;
+}
 
 RefinePlans make_refine_plans(int64_t n, int k, int j, int width, bool reuse) {
   RefinePlans rp;

@@ -156,3 +156,36 @@ def test_mixed_with_reused_pivots(precision):
         torch.cuda.synchronize()
         assert int(info.item()) == 0
         assert rel(got.cpu().numpy(), oracle.invert_block(m, k, i, j)) < 1e-10
+
+
+def test_mixed_f16_cond_1e6_stays_in_range():
+    # cond 1e6: after the power-of-two scaling of M (largest entry in
+    # [0.5, 1)) the largest magnitude the products meet is about 1e4, inside
+    # the FP16 range: FP16 split products and refinement reach the target.
+    n, k = 512, 4
+    m = workloads.haar_spd(n, 61, 0.0, 6.0, pin_endpoints=True).m
+    got, info = run_mixed(m, k, 0, 0, "mixed_f16", iters=30)
+    err = rel(got, oracle.invert_block(m, k, 0, 0))
+    print(f"mixed_f16 cond 1e6: rel err {err:.2e}, info {info}", flush=True)
+    assert info == 0 and not bri.refine_last_bf16_fallback()
+    assert err < 1e-10
+
+
+def test_mixed_f16_out_of_range_falls_back_to_bf16():
+    # A badly scaled matrix D A D (A diagonally dominant, the last 64 rows and
+    # columns scaled by 1e-4): its inverse D^-1 A^-1 D^-1 has entries around
+    # 1e8 times the scaled matrix's, far outside the FP16 range (65504).  The
+    # split FP16 products flag it and the call is computed again with BF16
+    # split products (FP32's exponent range), which reach the target.
+    n, k = 512, 4
+    d = np.ones(n)
+    d[-64:] = 1e-4
+    m = d[:, None] * workloads.gaussian_dd(n, 63) * d[None, :]
+    for (i, j) in [(3, 3), (0, 3)]:
+        got, info = run_mixed(m, k, i, j, "mixed_f16", iters=30)
+        err = rel(got, oracle.invert_block(m, k, i, j))
+        fell_back = bri.refine_last_bf16_fallback()
+        print(f"mixed_f16 scaled ({i},{j}): rel err {err:.2e}, info {info}, bf16 fallback {fell_back}", flush=True)
+        assert fell_back
+        assert info == 0
+        assert err < 1e-10

@@ -418,3 +418,69 @@ def test_tile_lu_edges_merged_batch(precision):
     assert int(info.abs().sum().item()) == 0
     for m, k, i, j, o in zip(mats, ks, iis, jjs, outs):
         assert rel(o.double().cpu().numpy(), oracle.invert_block(m, k, i, j)) < tol, (m.shape[0], k, i, j)
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed_f16"])
+def test_workspace_budget_same_block(precision):
+    # A workspace budget narrows the width (more, smaller lock-step batches);
+    # the block is the same.
+    n, k = 1024, 4
+    m = workloads.haar_spd(n, 81, 0.0, 2.0).m
+    want = oracle.invert_block(m, k, 1, 1)
+    free = bri.workspace_size(n, k, 1, 1, precision)
+    budget = bri.workspace_size(n, k, 1, 1, precision, concurrency=1)
+    assert budget < free
+    assert bri.plan_describe(n, k, 1, 1, precision, workspace_budget=budget)["batch_width"] == 1
+    for wb in (0, budget):
+        info = torch.zeros(1, dtype=torch.int32, device=DEV)
+        ws = torch.empty(bri.workspace_size(n, k, 1, 1, precision, workspace_budget=wb), dtype=torch.uint8,
+                         device=DEV)
+        got = bri.invert_block(gpu(m), k, 1, 1, precision=precision, info=info, workspace=ws,
+                               workspace_budget=wb).cpu().numpy()
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        assert rel(got, want) < (1e-12 if precision == "f64" else 1e-10), wb
+
+
+def test_repeated_calls_replay_a_captured_graph():
+    # Repeated calls with the same arguments replay the graph captured by the
+    # first one (status clear, descriptor upload, every kernel).  Each replay
+    # is checked against an eager call (step timing on: no graph), with other
+    # work of the program and synchronisations between the replays, and the
+    # matrix changed in place between two replays (a replay reads the current
+    # values).
+    n, k = 256, 2
+    m1 = workloads.gaussian_dd(n, 301)
+    m2 = workloads.gaussian_dd(n, 302)
+    M = gpu(m1)
+    b = 128
+    out = torch.empty(b, b, dtype=torch.float64, device=DEV)
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = torch.empty(bri.workspace_size(n, k, 0, 1), dtype=torch.uint8, device=DEV)
+
+    def eager(mat):
+        lib = bri.lib()
+        lib.bri_profile_enable(1)
+        try:
+            ref = bri.invert_block(gpu(mat), k, 0, 1, pivoting="tile")
+            torch.cuda.synchronize()
+        finally:
+            lib.bri_profile_enable(0)
+            bri.profile_read_clear()
+        return ref.cpu().numpy()
+
+    want1, want2 = eager(m1), eager(m2)
+    other = gpu(workloads.gaussian_dd(300, 303))
+    for rep in range(5):
+        if rep == 3:
+            M.copy_(gpu(m2))
+        bri.invert_block(M, k, 0, 1, out=out, info=info, workspace=ws, pivoting="tile")
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        want = want2 if rep >= 3 else want1
+        assert int(info.item()) == 0
+        assert np.array_equal(got, want), rep
+        # other work of the program between replays
+        bri.invert_block(other, 3, 1, 1)
+        _ = (other @ other).sum().item()
+        torch.cuda.synchronize()

@@ -105,6 +105,29 @@ def haar_spd_device(n: int, seed, lo_exp: float = 0.0, hi_exp: float = 2.0, pin_
     return m
 
 
+def lssvm_points(n: int, d: int, seed) -> np.ndarray:
+    """n x d input points with i.i.d. N(0, 1) entries (the paper's LS-SVM
+    experiment draws its inputs with randn)."""
+    return rng_for(seed).standard_normal((n, d))
+
+
+def lssvm_matrix(x: np.ndarray, sigma: float, gamma: float) -> np.ndarray:
+    """The dense (n + 1) x (n + 1) LS-SVM cross-validation matrix
+    A_gamma = [[0, 1^T], [1, K + I/gamma]], K_ij = exp(-|x_i - x_j|^2 / (2 sigma^2))
+    of the points x (rows), for checking the matrix-free path."""
+    n = x.shape[0]
+    d2 = np.empty((n, n))
+    for r0 in range(0, n, 256):  # squared distances from differences, by row chunks
+        diff = x[r0:r0 + 256, None, :] - x[None, :, :]
+        d2[r0:r0 + 256] = np.sum(diff * diff, axis=2)
+    a = np.empty((n + 1, n + 1))
+    a[0, 0] = 0.0
+    a[0, 1:] = 1.0
+    a[1:, 0] = 1.0
+    a[1:, 1:] = np.exp(-d2 / (2.0 * sigma * sigma)) + np.eye(n) / gamma
+    return a
+
+
 def tridiag_toeplitz(n: int, diag: float = 4.0, off: float = -1.0) -> np.ndarray:
     """Constant tridiagonal matrix with ``diag`` on the diagonal and ``off`` beside it."""
     t = np.zeros((n, n))

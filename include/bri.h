@@ -169,6 +169,24 @@ int invert_block_batched(int count, const void* const* M, const int64_t* n, cons
                          const int* k, const int* i, const int* j, void* const* out,
                          const int64_t* ldo, const bri_opts* o);
 
+/* invert_block for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it).  Same
+ * arguments and result as invert_block (BRI_F64 and BRI_F32; o->workspace
+ * and o->workspace_bytes are ignored), but the workspace is a static device
+ * array of BRI_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it
+ * runs on until the process ends, and the step descriptors are staged
+ * through a static host buffer: no device or pinned host memory is
+ * allocated (the host plan of a new shape is built and cached in ordinary
+ * host memory on its first call).  With automatic concurrency the width is
+ * the widest whose workspace fits the array; problems that do not fit even
+ * at width 1 return BRI_ERR_WORKSPACE (and mixed precisions
+ * BRI_ERR_UNSUPPORTED).  All calls on one GPU share the array, which keeps
+ * the last call's contents: calls that overlap in time on one GPU race. */
+#define BRI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+size_t bri_noalloc_scratch_bytes(void);
+int invert_block_noalloc(const void* M, int64_t n, int64_t ldm, int k, int i, int j,
+                         void* out, int64_t ldo, const bri_opts* o);
+
 /* Several blocks of one matrix: blocks (i[t], j[t]) of M^{-1}, t < count, to
  * out[t] (b x b, leading dimension ldo[t]).  i, j, out and ldo are HOST
  * arrays.  All k^2 blocks, or any selection (such as the band of blocks near

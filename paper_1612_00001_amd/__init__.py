@@ -118,6 +118,10 @@ _SIGNATURES = [
     ("invert_block_rbf", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(BriOpts)]),
+    ("bri_noalloc_scratch_bytes", ctypes.c_size_t, []),
+    ("invert_block_noalloc", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+      ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(BriOpts)]),
     ("bri_gemm_workspace_size", ctypes.c_size_t, [ctypes.c_int]),
     ("bri_gemm", ctypes.c_int,
      [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
@@ -319,6 +323,22 @@ def invert_block_rbf(X: torch.Tensor, k: int, i: int, j: int, sigma: float, gamm
     o.stream = _stream_ptr(X.device)
     _check(lib().invert_block_rbf(X.data_ptr(), npts, X.stride(0), d, sigma, gamma, k, i, j, out.data_ptr(),
                                   out.stride(0), ctypes.byref(o)))
+    return out
+
+
+def invert_block_noalloc(M: torch.Tensor, k: int, i: int, j: int, out: torch.Tensor,
+                         precision: str = "f64", info: Optional[torch.Tensor] = None,
+                         pivoting: str = "auto") -> torch.Tensor:
+    """invert_block into a caller-provided ``out`` with the library's static
+    device scratch as workspace: allocates no device memory."""
+    dtype = _DTYPE_OF[precision]
+    _require_gpu(M, "M", dtype)
+    _require_gpu(out, "out", dtype)
+    o = make_opts(precision, pivoting=pivoting)
+    o.d_info = info.data_ptr() if info is not None else None
+    o.stream = _stream_ptr(M.device)
+    _check(lib().invert_block_noalloc(M.data_ptr(), M.shape[0], M.stride(0), k, i, j, out.data_ptr(),
+                                      out.stride(0), ctypes.byref(o)))
     return out
 
 

@@ -594,6 +594,14 @@ int run_steps(const Ctx& c, const Plan& p, hipStream_t st) {
   return run_exec<T>(ex, c.b, cfg_of(c), st);
 }
 
+// Descriptor staging of the calls that allocate nothing (invert_block_noalloc):
+// one static, pageable host buffer.  hipMemcpyAsync returns once a pageable
+// source has been taken (staged for the transfer), so the next call may
+// overwrite it; the mutex keeps host threads apart.
+constexpr size_t kNoallocDescBytes = size_t(8) << 20;
+alignas(64) char g_noalloc_desc[kNoallocDescBytes];
+std::mutex g_noalloc_mu;
+
 // Enqueues the status clear, the descriptor upload (from cp.host) and the
 // kernels of plan cp on st.
 int enqueue_call(CachedPlan& cp, Ctx& c, bool clear_info, hipStream_t st) {
@@ -670,9 +678,24 @@ hipGraphExec_t capture_call(CachedPlan& cp, Ctx& c, bool clear_info) {
 }
 
 // Uploads the descriptors of plan cp for context c and enqueues its kernels.
-int execute(CachedPlan& cp, Ctx& c, hipStream_t st, bool clear_info) {
+// noalloc: stage through the static buffer above (no pinned buffer, no event).
+int execute(CachedPlan& cp, Ctx& c, hipStream_t st, bool clear_info, bool noalloc = false) {
   c.lay = &cp.layout;
   std::lock_guard<std::mutex> g(cp.mu);
+  if (noalloc) {
+    if (cp.layout.desc_bytes > kNoallocDescBytes) return BRI_ERR_WORKSPACE;
+    std::lock_guard<std::mutex> gn(g_noalloc_mu);
+    try {
+      build_descriptors(c, cp.plan, g_noalloc_desc, cp.layout.nfast, cp.layout.ndirect);
+    } catch (const std::exception&) {
+      return BRI_ERR_UNSUPPORTED;
+    }
+    if (clear_info && launch_fill_int(c.info, 1, 0, st) != hipSuccess) return BRI_ERR_HIP;
+    if (cp.layout.desc_bytes > 0 && hipMemcpyAsync(c.ws + cp.layout.desc_off, g_noalloc_desc, cp.layout.desc_bytes,
+                                                   hipMemcpyHostToDevice, st) != hipSuccess)
+      return BRI_ERR_HIP;
+    return c.elem == 8 ? run_steps<double>(c, cp.plan, st) : run_steps<float>(c, cp.plan, st);
+  }
   if (!cp.host) {
     if (hipHostMalloc(&cp.host, std::max<size_t>(cp.layout.desc_bytes, 64)) != hipSuccess) return BRI_ERR_HIP;
     if (hipEventCreateWithFlags(&cp.uploaded, hipEventDisableTiming) != hipSuccess) return BRI_ERR_HIP;
@@ -1557,8 +1580,10 @@ int64_t bri_refine_plan_dump(int64_t n, int k, int j, int which, const bri_opts*
 
 }  // extern "C"
 
+// invert_block; noalloc: the workspace is the caller's scratch and the
+// descriptors are staged without allocating (invert_block_noalloc).
 static int invert_block_impl(const void* M, int64_t n, int64_t ldm, int k, int i, int j, void* out, int64_t ldo,
-                             const bri_opts* o) {
+                             const bri_opts* o, bool noalloc) {
   if (!M) return -1;
   if (!out) return -7;
   if (!o) return -9;
@@ -1577,14 +1602,17 @@ static int invert_block_impl(const void* M, int64_t n, int64_t ldm, int k, int i
       t.d_info = block_info_word(n, k, i, j, o);
       if (!t.d_info) return BRI_ERR_WORKSPACE;
     }
-    int rc2 = invert_block_impl(M, n, ldm, k, i, j, out, ldo, &t);
+    int rc2 = invert_block_impl(M, n, ldm, k, i, j, out, ldo, &t, noalloc);
     int32_t h = 0;
     if (rc2 == BRI_OK) rc2 = read_info1(t.d_info, h, o->stream);
     if (rc2 != BRI_OK || h <= 0) return rc2;
     t.pivoting = BRI_PIVOT_PANEL;
-    return invert_block_impl(M, n, ldm, k, i, j, out, ldo, &t);
+    return invert_block_impl(M, n, ldm, k, i, j, out, ldo, &t, noalloc);
   }
-  if (mixed_precision(o->precision)) return invert_block_mixed(M, n, ldm, k, i, j, out, ldo, o);
+  if (mixed_precision(o->precision)) {
+    if (noalloc) return BRI_ERR_UNSUPPORTED;
+    return invert_block_mixed(M, n, ldm, k, i, j, out, ldo, o);
+  }
   if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
   const int elem = elem_size(o->precision);
   const int w = resolve_width(n, k, o);
@@ -1607,14 +1635,26 @@ static int invert_block_impl(const void* M, int64_t n, int64_t ldm, int k, int i
   c.out = static_cast<char*>(out);
   c.ldo = ldo;
   c.info = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(c.ws + cp->layout.info_off);
-  return execute(*cp, c, o->stream, true);
+  return execute(*cp, c, o->stream, true, noalloc);
 }
+
+namespace bri {
+int invert_block_scratch(const void* M, int64_t n, int64_t ldm, int k, int i, int j, void* out, int64_t ldo,
+                         const bri_opts* o, void* scratch, size_t scratch_bytes) {
+  if (!o) return -9;
+  bri_opts t = *o;
+  t.workspace = scratch;
+  t.workspace_bytes = scratch_bytes;
+  if (t.concurrency <= 0) t.workspace_budget = scratch_bytes;  // the widest width that fits
+  return invert_block_impl(M, n, ldm, k, i, j, out, ldo, &t, true);
+}
+}  // namespace bri
 
 extern "C" {
 
 int invert_block(const void* M, int64_t n, int64_t ldm, int k, int i, int j, void* out, int64_t ldo,
                  const bri_opts* o) {
-  return invert_block_impl(M, n, ldm, k, i, j, out, ldo, o);
+  return invert_block_impl(M, n, ldm, k, i, j, out, ldo, o, false);
 }
 
 static size_t column_size_of(int64_t n, int k, int j, const bri_opts* o) {

@@ -138,8 +138,13 @@ def main() -> int:
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-budget", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the FP64 headline calls (no profiled pass, no reference, no other workloads)")
+    ap.add_argument("--input", choices=("spd", "dd"), default="spd",
+                    help="headline matrix: spd (Q Lam Q^T, cond 1e4; default) or dd (Gaussian + n I made on the "
+                         "device without a QR: for counter runs, where the profiler does not survive the QR "
+                         "library; only with --headline-only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -169,15 +174,22 @@ def main() -> int:
     dev = torch.device("cuda:0")
     lib = bri.lib()
 
-    def setup(M, n, k, i, j, precision, reuse=False):
-        need = bri.workspace_size(n, k, i, j, precision, reuse=reuse)
+    # Every workload here is SPD or diagonally dominant, where tile pivoting
+    # is stable; its element-growth check still runs (a flagged
+    # factorisation would show as info != 0, asserted below), but the calls
+    # do not wait for it as the default automatic pivoting does.
+    PIV = "tile"
+
+    def setup(M, n, k, i, j, precision, reuse=False, workspace_budget=0):
+        need = bri.workspace_size(n, k, i, j, precision, reuse=reuse, workspace_budget=workspace_budget)
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
         b = bri.block_size(n, k)
         out = torch.empty(b, b, dtype=M.dtype, device=dev)
         info = torch.zeros(1, dtype=torch.int32, device=dev)
 
         def call():
-            bri.invert_block(M, k, i, j, precision=precision, out=out, info=info, workspace=ws, reuse=reuse)
+            bri.invert_block(M, k, i, j, precision=precision, out=out, info=info, workspace=ws, reuse=reuse,
+                             pivoting=PIV, workspace_budget=workspace_budget)
         return call, out, info, ws
 
     # ---- headline: spd_n16384_k8, FP64, block (0, 0) -------------------------
@@ -185,15 +197,28 @@ def main() -> int:
     n, k = wl.n, wl.k
     i, j = wl.targets[0]
     b = bri.block_size(n, k)
-    print("generating spd_n16384_k8 on the device", file=sys.stderr, flush=True)
-    M3, q, lam = workloads.haar_spd_device(n, wl.seed, 0.0, 4.0, pin_endpoints=True, device=dev,
-                                           return_factors=True)
-    # Reference block from the matrix's known inverse Q Lam^{-1} Q^T (torch,
-    # FP64; not this library): N_00 = Q[0:b] Lam^{-1} Q[0:b]^T.
-    qb = q[i * b:(i + 1) * b].contiguous()
-    del q
-    ref = ((qb * torch.from_numpy(1.0 / lam).to(dev)[None, :]) @ qb.T.contiguous()).cpu().numpy()
-    del qb
+    if args.input == "dd":
+        if not args.headline_only:
+            print("--input dd needs --headline-only", file=sys.stderr)
+            return 2
+        # Same size and plan, N(0, 1) entries + n on the diagonal; the
+        # product kernels move the same bytes on any input of this shape.
+        print("generating dd_n16384_k8 on the device", file=sys.stderr, flush=True)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(wl.seed)
+        M3 = torch.randn(n, n, dtype=torch.float64, device=dev, generator=gen)
+        M3.diagonal().add_(float(n))
+        ref = None
+    else:
+        print("generating spd_n16384_k8 on the device", file=sys.stderr, flush=True)
+        M3, q, lam = workloads.haar_spd_device(n, wl.seed, 0.0, 4.0, pin_endpoints=True, device=dev,
+                                               return_factors=True)
+        # Reference block from the matrix's known inverse Q Lam^{-1} Q^T
+        # (torch, FP64; not this library): N_00 = Q[0:b] Lam^{-1} Q[0:b]^T.
+        qb = q[i * b:(i + 1) * b].contiguous()
+        del q
+        ref = ((qb * torch.from_numpy(1.0 / lam).to(dev)[None, :]) @ qb.T.contiguous()).cpu().numpy()
+        del qb
     torch.cuda.synchronize()
     stats = bri.plan_describe(n, k, i, j, "f64")
     flops = stats["algorithmic_flops"]
@@ -206,7 +231,9 @@ def main() -> int:
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "spd_n16384_k8: n=16384 k=8 b=2048, block (0,0), Q Lam Q^T, cond 1e4",
+        "config": {"workload": ("spd_n16384_k8: n=16384 k=8 b=2048, block (0,0), Q Lam Q^T, cond 1e4"
+                                if args.input == "spd" else
+                                "dd_n16384_k8: n=16384 k=8 b=2048, block (0,0), Gaussian + n I (counter runs)"),
                    "n": n, "k": k, "b": b, "block": [i, j], "precision": "f64",
                    "concurrency": stats["batch_width"]},
         "pct_fp64_mfma_peak": 100.0 * value / PEAK_TFLOPS["f64"],
@@ -275,6 +302,23 @@ def main() -> int:
                              "workspace_bytes": st2["workspace_bytes"],
                              "workspace_over_M": st2["workspace_bytes"] / (8.0 * n * n)})
             del ws2, o2
+
+    # ---- memory budget: the same call within a quarter of M's size ----------
+    if not args.no_budget:
+        budget = (8 * n * n) // 4
+        stb = bri.plan_describe(n, k, i, j, "f64", workspace_budget=budget)
+        print(f"memory budget: FP64 n={n} k={k} within {budget} bytes (width {stb['batch_width']})", file=sys.stderr,
+              flush=True)
+        cb, ob, ib, wsb = setup(M3, n, k, i, j, "f64", workspace_budget=budget)
+        bms, _ = time_calls(cb, 1, 0, torch)
+        line["memory_budget"] = {
+            "workload": "spd_n16384_k8, FP64, workspace budget M/4 (Theorem MC_BRI trade-off)",
+            "budget_bytes": budget, "workspace_bytes": stb["workspace_bytes"],
+            "workspace_over_M": stb["workspace_bytes"] / (8.0 * n * n), "batch_width": stb["batch_width"],
+            "kernel_launches_per_step": stb["kernel_launches"], "ms_per_step": bms,
+            "tflops": flops / (bms * 1e-3) / 1e12, "speed_vs_default": ms / bms,
+            "rel_error": rel_err(ob.cpu().numpy(), ref), "info": int(ib.item())}
+        del wsb, ob
 
     # ---- CPU baseline: the FP64 oracle on a sample of the same workload -------
     if not args.no_cpu_baseline:
@@ -355,13 +399,53 @@ def main() -> int:
         st1 = bri.plan_describe(256, 2, 0, 0, "f64")
         o1 = torch.empty(128, 128, dtype=torch.float64, device=dev)
         w1 = torch.empty(bri.workspace_size(256, 2, 0, 0), dtype=torch.uint8, device=dev)
-        c1 = lambda: bri.invert_block(M1, 2, 0, 0, out=o1, workspace=w1)  # noqa: E731
+        c1 = lambda: bri.invert_block(M1, 2, 0, 0, out=o1, workspace=w1, pivoting=PIV)  # noqa: E731
         ms1, wall1 = time_calls(c1, 50, 5, torch)
         e1 = {"workload": "dd_n256_k2: n=256 k=2 b=128 block (0,0), Gaussian + nI", "precision": "f64",
               "us_per_call": ms1 * 1e3, "wall_us_per_call": wall1 * 1e3,
               "tflops": st1["algorithmic_flops"] / (ms1 * 1e-3) / 1e12}
         e1["rel_error"] = rel_err(o1.cpu().numpy(), np.linalg.inv(m1)[:128, :128])
         variants.append(e1)
+        # every block of the n = 4096 matrix (invert_blocks: one merged batch)
+        binfo = torch.zeros(k2 * k2, dtype=torch.int32, device=dev)
+        allb = lambda: bri.invert_blocks(M64, k2, info=binfo, pivoting=PIV)  # noqa: E731
+        outs = allb()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = allb()
+        torch.cuda.synchronize()
+        abms = (time.perf_counter() - t0) * 1e3
+        aflops = sum(bri.plan_describe(n2, k2, bi, bj, "f64")["algorithmic_flops"]
+                     for bi in range(k2) for bj in range(k2))
+        worst = 0.0
+        for t, o_ in enumerate(outs):
+            bi, bj = divmod(t, k2)
+            want = (spd2.q[bi * b2:(bi + 1) * b2] / spd2.lam[None, :]) @ spd2.q[bj * b2:(bj + 1) * b2].T
+            worst = max(worst, rel_err(o_.cpu().numpy(), want))
+        variants.append({"workload": "spd_n4096_k4: all 16 blocks (invert_blocks)", "precision": "f64",
+                         "ms_per_call": abms, "tflops": aflops / (abms * 1e-3) / 1e12, "max_rel_error": worst,
+                         "info_nonzero": int((binfo != 0).sum().item())})
+        del outs
+        # matrix-free A_gamma (eq. A): npts = 4095 points in R^16, k = 4
+        npts, dd, kr = 4095, 16, 4
+        xh = workloads.lssvm_points(npts, dd, 7)
+        X = torch.from_numpy(xh).to(dev)
+        rinfo = torch.zeros(1, dtype=torch.int32, device=dev)
+        rb = lambda: bri.invert_block_rbf(X, kr, 0, 0, 2.0, 10.0, info=rinfo, pivoting="auto")  # noqa: E731
+        ro = rb()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ro = rb()
+        torch.cuda.synchronize()
+        rms = (time.perf_counter() - t0) * 1e3
+        ah = workloads.lssvm_matrix(xh, 2.0, 10.0)
+        rwant = np.linalg.inv(ah)[:1024, :1024]
+        rflops = bri.plan_describe(npts + 1, kr, 0, 0, "f64")["algorithmic_flops"]
+        variants.append({"workload": "matrix-free LS-SVM A_gamma (eq. A): 4095 points in R^16, sigma 2, gamma 10, "
+                                     "m = 4096, k = 4, block (0,0), never stored", "precision": "f64",
+                         "ms_per_call": rms, "tflops": rflops / (rms * 1e-3) / 1e12,
+                         "rel_error_vs_dense_inverse": rel_err(ro.cpu().numpy(), rwant), "info": int(rinfo.item()),
+                         "workspace_bytes": bri.rbf_workspace_size(npts, dd, kr, 0, 0)})
         del M64, M32
     line["variants"] = variants
 
@@ -384,12 +468,12 @@ def main() -> int:
             dt_ = torch.float32 if prec == "f32" else torch.float64
             Ms = [torch.from_numpy(m).to(dev, dt_) for m in mats]
             binfo = torch.zeros(len(probs), dtype=torch.int32, device=dev)
-            outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo)
+            outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo, pivoting=PIV)
             torch.cuda.synchronize()
             reps = 3
             t0 = time.perf_counter()
             for _ in range(reps):
-                outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo)
+                outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo, pivoting=PIV)
             torch.cuda.synchronize()
             bms = (time.perf_counter() - t0) * 1e3 / reps
             err = max(rel_err(outs[t].double().cpu().numpy(), dense[t]) for t in sample)

@@ -301,6 +301,23 @@ int bri_profile_read(bri_profile_entry* entries, int cap);
  * pointer may be NULL. */
 int bri_refine_last(int* sweeps, double* last_update, int* bf16_fallback);
 
+/* Autotuner.  bri_autotune() measures on this GPU, with synthetic inputs in
+ * o->workspace (at least 64 MiB; larger workspaces cover larger cases, up to
+ * about 4 GiB for all of them) on o->stream, (1) which tile shape the FP64
+ * products of a plan step run fastest in, for 1..64 items of order
+ * 256..2048, plain and triangular, and (2) which LU variant (tile steps or
+ * recursive halving) factors 1..64 matrices of order 256..2048 fastest.  It
+ * writes the decisions to the text cache at path (NULL: $BRI_TUNE_CACHE, else
+ * $HOME/.cache/bri-mi355x/tune.txt), loads them, and returns the number of
+ * decisions (< 0: an error code).  Later calls of this process, and every
+ * process that finds the cache, take these decisions where the automatic
+ * choices apply (bri_opts.factorization = 0); the built-in rules cover the
+ * cases the cache lacks.  bri_tune_load() (re)loads a cache (NULL: the
+ * default path) and returns its number of decisions, or BRI_ERR_UNSUPPORTED
+ * when it cannot be read.  Synchronous. */
+int bri_autotune(const bri_opts* o, const char* path);
+int bri_tune_load(const char* path);
+
 /* Human-readable text for a status code returned by any entry point. */
 const char* bri_status_string(int status);
 

@@ -131,6 +131,8 @@ _SIGNATURES = [
     ("bri_profile_read", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("bri_refine_last", ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int)]),
+    ("bri_autotune", ctypes.c_int, [ctypes.POINTER(BriOpts), ctypes.c_char_p]),
+    ("bri_tune_load", ctypes.c_int, [ctypes.c_char_p]),
     ("bri_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("bri_version", ctypes.c_char_p, []),
 ]
@@ -389,7 +391,7 @@ def invert_block_backward(M: torch.Tensor, k: int, i: int, j: int, G: torch.Tens
 def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Sequence[int],
                          jjs: Sequence[int], precision: str = "f64", concurrency: int = 0,
                          info: Optional[torch.Tensor] = None, reuse: bool = False,
-                         factorization: str = "auto") -> List[torch.Tensor]:
+                         factorization: str = "auto", pivoting: str = "auto") -> List[torch.Tensor]:
     """One block per problem; all problems share one workspace and one call."""
     count = len(Ms)
     dtype = _DTYPE_OF[precision]
@@ -406,7 +408,7 @@ def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Seq
     ldo = (ctypes.c_int64 * count)(*[o_.stride(0) for o_ in outs])
     mp = (ctypes.c_void_p * count)(*[m.data_ptr() for m in Ms])
     op = (ctypes.c_void_p * count)(*[o_.data_ptr() for o_ in outs])
-    o = make_opts(precision, concurrency, reuse=reuse, factorization=factorization)
+    o = make_opts(precision, concurrency, reuse=reuse, factorization=factorization, pivoting=pivoting)
     need = lib().bri_batched_workspace_size(count, n, kk, ii, jj, ctypes.byref(o))
     if need == 0 and count > 0:
         raise BriError(BRI_ERR_UNSUPPORTED, "invalid arguments")
@@ -517,6 +519,29 @@ def profile_read_clear() -> None:
     """Reads (and so clears) the step-timing record of bri_profile_*."""
     arr = (_ProfEntry * 9)()
     lib().bri_profile_read(ctypes.cast(arr, ctypes.c_void_p), 9)
+
+
+def autotune(path: Optional[str] = None, workspace_bytes: int = 4 << 30, device: str = "cuda:0") -> int:
+    """Measures the product tile shapes and LU variants on this GPU (see
+    bri_autotune in include/bri.h), writes the tuning cache and loads it;
+    returns the number of decisions."""
+    ws = torch.empty(workspace_bytes, dtype=torch.uint8, device=device)
+    o = make_opts("f64")
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = workspace_bytes
+    o.stream = _stream_ptr(torch.device(device))
+    rc = lib().bri_autotune(ctypes.byref(o), path.encode() if path else None)
+    if rc < 0:
+        raise BriError(rc, status_string(rc))
+    return rc
+
+
+def tune_load(path: Optional[str] = None) -> int:
+    """(Re)loads a tuning cache; returns its number of decisions."""
+    rc = lib().bri_tune_load(path.encode() if path else None)
+    if rc < 0:
+        raise BriError(rc, status_string(rc))
+    return rc
 
 
 def refine_last() -> tuple:

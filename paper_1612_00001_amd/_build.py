@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbri.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["bri_kernels.hip", "bri_refine.hip", "bri_noalloc.hip", "bri_api.cpp", "bri_plan.cpp"]
+SOURCES = ["bri_kernels.hip", "bri_refine.hip", "bri_noalloc.hip", "bri_api.cpp", "bri_plan.cpp", "bri_tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device compilation.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

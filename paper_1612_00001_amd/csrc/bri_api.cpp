@@ -533,7 +533,8 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, const ExecCfg& cfg, h
       std::lock_guard<std::mutex> g(g_prof_mu);
       rec.kind = s.kind;
       rec.launches = step_launches(s.kind, s.count, bmax, pivoting, s.uniform, lu);
-      rec.flops = s.flops;
+      // a triangular inversion skipped after the recursive LU counts no work
+      rec.flops = s.kind == ST_TRTRI && step_recursive(s, bmax, pivoting, lu) ? 0.0 : s.flops;
       rec.e0 = prof_event();
       rec.e1 = prof_event();
       if (!rec.e0 || !rec.e1 || hipEventRecord(rec.e0, st) != hipSuccess) return BRI_ERR_HIP;

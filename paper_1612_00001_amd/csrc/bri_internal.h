@@ -287,10 +287,23 @@ inline bool getrf_rec_possible(int b) { return b >= 2 * kTile && b <= kMaxBlock 
 // possible.  Automatic: the recursion's products keep the MFMA pipes busy
 // when there are many or large matrices; for few small ones the tile-step
 // LU's shorter chain of launches wins.
+// Autotuned choices (bri_tune.cpp), loaded from the tuning cache on first
+// use: -1 when the table holds nothing for the case.
+int tuned_lu_kind(int count, int b);
+int tuned_product_shape(int elem, int tri, int count, int m, int n);
+// Overrides for the autotuner's timing runs (-1: none), per host thread.
+extern thread_local int g_force_shape;
+extern thread_local int g_force_lu;
+// Tile shapes of the FP64 explicit products that the autotuner chooses from.
+constexpr int kShapeDl128 = 1, kShapeDl64 = 2, kShapeDl256 = 3;
+
 inline LuKind lu_kind(int count, int b, bool panel_pivoting, bool uniform, int choice) {
   if (panel_pivoting) return LU_PANEL;
   if (!uniform || !getrf_rec_possible(b) || choice == 1) return LU_TILE;
   if (choice == 2) return LU_RECURSIVE;
+  if (g_force_lu == LU_TILE || g_force_lu == LU_RECURSIVE) return static_cast<LuKind>(g_force_lu);
+  const int tuned = tuned_lu_kind(count, b);
+  if (tuned == LU_TILE || tuned == LU_RECURSIVE) return static_cast<LuKind>(tuned);
   const double work = static_cast<double>(count) * b * b * b;
   return work >= 64.0 * 1024.0 * 1024.0 * 1024.0 ? LU_RECURSIVE : LU_TILE;
 }

@@ -2376,9 +2376,16 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
           // thread of a 1024-thread workgroup has, and spill); 64 x 64 tiles
           // of 4 wavefronts of 32 x 32 for the small one.
           ndl = nfast;
-          if (tier == kTierSmall) {
+          int shape = tier == kTierSmall ? kShapeDl64 : kShapeDl128;
+          const int tuned = tuned_product_shape(8, L.tri, ndl, max_m, max_n);
+          if (tuned == kShapeDl64 || tuned == kShapeDl128 || tuned == kShapeDl256) shape = tuned;
+          if (g_force_shape >= kShapeDl128 && g_force_shape <= kShapeDl256) shape = g_force_shape;
+          if (shape == kShapeDl64) {
             dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), ndl);
             hipLaunchKernelGGL((k_gemm_dl<GEMM_EXPLICIT, 64, 64, 32, 32>), grid, dim3(256), 0, st, L);
+          } else if (shape == kShapeDl256) {
+            dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), ndl);
+            hipLaunchKernelGGL((k_gemm_dl<GEMM_EXPLICIT, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
           } else {
             dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
             hipLaunchKernelGGL((k_gemm_dl<GEMM_EXPLICIT, 128, 128, 32, 32>), grid, dim3(1024), 0, st, L);
@@ -2557,6 +2564,30 @@ hipError_t launch_load(const LoadItem* d_items, int count, int rows, int cols, h
   int gx = cdiv(total, 256);
   if (gx > 4096) gx = 4096;
   hipLaunchKernelGGL((k_load<T>), dim3(gx, count), dim3(256), 0, st, d_items);
+  return hipGetLastError();
+}
+
+// Fills every matrix of the LU items with a diagonally dominant pattern
+// (entries in [-0.5, 0.5) from an integer hash, b added on the diagonal):
+// inputs for the autotuner's factorisation timings.
+__global__ __launch_bounds__(256) void k_fill_diag_dominant(const LuItem* items) {
+  const LuItem it = items[blockIdx.y];
+  double* a = static_cast<double*>(it.a);
+  const int64_t n = static_cast<int64_t>(it.b) * it.b;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < n; e += static_cast<int64_t>(gridDim.x) * 256) {
+    uint32_t h = static_cast<uint32_t>(e) * 2654435761u ^ (blockIdx.y * 40503u + 0x9e3779b9u);
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    const int64_t r = e / it.b, c = e % it.b;
+    a[e] = static_cast<double>(h) * (1.0 / 4294967296.0) - 0.5 + (r == c ? static_cast<double>(it.b) : 0.0);
+  }
+}
+
+hipError_t launch_fill_diag_dominant(const LuItem* d_items, int count, int b, hipStream_t st) {
+  int gx = cdiv(static_cast<int64_t>(b) * b, 256);
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(k_fill_diag_dominant, dim3(gx, count), dim3(256), 0, st, d_items);
   return hipGetLastError();
 }
 

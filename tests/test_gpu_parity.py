@@ -484,3 +484,22 @@ def test_repeated_calls_replay_a_captured_graph():
         bri.invert_block(other, 3, 1, 1)
         _ = (other @ other).sum().item()
         torch.cuda.synchronize()
+
+
+def test_autotune_writes_and_applies_a_cache(tmp_path):
+    # The autotuner measures on this GPU (within a 1 GiB workspace: the
+    # cases that fit), writes its decisions and loads them; a block computed
+    # afterwards is still the oracle's.
+    path = str(tmp_path / "tune.txt")
+    print("autotune", flush=True)
+    n_dec = bri.autotune(path=path, workspace_bytes=1 << 30)
+    text = open(path).read()
+    print(text, flush=True)
+    assert n_dec > 0
+    assert text.count("\nlu ") + text.count("\nproduct ") == n_dec
+    m = workloads.haar_spd(1024, 17, 0.0, 2.0).m
+    got = run(m, 4, 0, 0)
+    assert rel(got, oracle.invert_block(m, 4, 0, 0)) < 1e-12
+    empty = tmp_path / "empty.txt"
+    empty.write_text("")
+    bri.tune_load(str(empty))

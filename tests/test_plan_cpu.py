@@ -379,3 +379,26 @@ def test_mixed_workspace_below_the_matrix_at_width_one():
     n, k = 16384, 8
     need = bri.workspace_size(n, k, 0, 0, "mixed_f16", concurrency=1)
     assert 0 < need < 0.75 * 8 * n * n
+
+
+def test_tuning_cache_drives_the_lu_choice(tmp_path):
+    # A tuning cache entry for factorisation launches of 64 matrices of order
+    # 2048 overrides the built-in rule (which takes the recursive LU there):
+    # the plan's launch count changes accordingly; an empty cache restores it.
+    n, k = 16384, 8
+    auto = bri.plan_describe(n, k, 0, 0, "f64")["kernel_launches"]
+    cache = tmp_path / "tune.txt"
+    lines = [f"lu {c} 2048 0" for c in (1, 2, 4, 8, 16, 32, 64)] + ["product 8 0 64 2048 2048 3"]
+    cache.write_text("# test\n" + "\n".join(lines) + "\n")
+    try:
+        assert bri.tune_load(str(cache)) == 8
+        tiled = bri.plan_describe(n, k, 0, 0, "f64")["kernel_launches"]
+        forced = bri.plan_describe(n, k, 0, 0, "f64", factorization="tile")["kernel_launches"]
+        assert tiled == forced and tiled != auto
+    finally:
+        empty = tmp_path / "empty.txt"
+        empty.write_text("")
+        assert bri.tune_load(str(empty)) == 0
+    assert bri.plan_describe(n, k, 0, 0, "f64")["kernel_launches"] == auto
+    with pytest.raises(bri.BriError):
+        bri.tune_load(str(tmp_path / "missing.txt"))

@@ -145,6 +145,8 @@ def main() -> int:
                     help="headline matrix: spd (Q Lam Q^T, cond 1e4; default) or dd (Gaussian + n I made on the "
                          "device without a QR: for counter runs, where the profiler does not survive the QR "
                          "library; only with --headline-only)")
+    ap.add_argument("--factorization", choices=("auto", "tile", "recursive"), default="auto",
+                    help="LU variant of the headline calls (default: the library's choice)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -180,7 +182,7 @@ def main() -> int:
     # do not wait for it as the default automatic pivoting does.
     PIV = "tile"
 
-    def setup(M, n, k, i, j, precision, reuse=False, workspace_budget=0):
+    def setup(M, n, k, i, j, precision, reuse=False, workspace_budget=0, factorization="auto"):
         need = bri.workspace_size(n, k, i, j, precision, reuse=reuse, workspace_budget=workspace_budget)
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
         b = bri.block_size(n, k)
@@ -189,7 +191,7 @@ def main() -> int:
 
         def call():
             bri.invert_block(M, k, i, j, precision=precision, out=out, info=info, workspace=ws, reuse=reuse,
-                             pivoting=PIV, workspace_budget=workspace_budget)
+                             pivoting=PIV, workspace_budget=workspace_budget, factorization=factorization)
         return call, out, info, ws
 
     # ---- headline: spd_n16384_k8, FP64, block (0, 0) -------------------------
@@ -222,7 +224,7 @@ def main() -> int:
     torch.cuda.synchronize()
     stats = bri.plan_describe(n, k, i, j, "f64")
     flops = stats["algorithmic_flops"]
-    call, out, info, ws = setup(M3, n, k, i, j, "f64")
+    call, out, info, ws = setup(M3, n, k, i, j, "f64", factorization=args.factorization)
     print(f"headline: FP64 n={n} k={k}, {args.warmup} warm-up + {args.steps} timed calls", file=sys.stderr,
           flush=True)
     ms, wall_ms = time_calls(call, args.steps, args.warmup, torch)
@@ -270,8 +272,9 @@ def main() -> int:
     # multiplies and Schur products; one launch per plan step) or the
     # factorisation of the pivot blocks, whichever takes longer.
     prods = family_roofline(prof, PRODUCT_KINDS, 1,
-                            "k_gemm_dl<GEMM_EXPLICIT, 128, 128, 32, 32> (direct-to-LDS FP64 products: "
-                            "triangular multiplies and Schur products of a plan step)",
+                            "k_gemm_dl<GEMM_EXPLICIT, 256, 128, 64, 64> (direct-to-LDS FP64 products: "
+                            "triangular multiplies and Schur products of a plan step; 128 x 128 tiles for "
+                            "the launches of fewer than 512 tiles)",
                             "b^3 per triangular multiply, 2 b^3 per Schur product")
     prods["traffic"] = counted_traffic()
     facts = family_roofline(prof, FACTOR_KINDS, 1,
@@ -295,12 +298,25 @@ def main() -> int:
             vms, _ = time_calls(c2, 1, 1, torch)
             sweeps, last = bri.refine_last()
             st2 = bri.plan_describe(n, k, i, j, prec)
-            variants.append({"workload": "spd_n16384_k8", "block": [i, j], "precision": prec, "ms_per_step": vms,
-                             "tflops": flops / (vms * 1e-3) / 1e12, "speed_vs_f64": ms / vms,
-                             "rel_error": rel_err(o2.cpu().numpy(), ref), "refine_sweeps": sweeps,
-                             "last_rel_correction": last, "info": int(inf2.item()),
-                             "workspace_bytes": st2["workspace_bytes"],
-                             "workspace_over_M": st2["workspace_bytes"] / (8.0 * n * n)})
+            entry = {"workload": "spd_n16384_k8", "block": [i, j], "precision": prec, "ms_per_step": vms,
+                     "tflops": flops / (vms * 1e-3) / 1e12, "speed_vs_f64": ms / vms,
+                     "rel_error": rel_err(o2.cpu().numpy(), ref), "refine_sweeps": sweeps,
+                     "last_rel_correction": last, "info": int(inf2.item()),
+                     "workspace_bytes": st2["workspace_bytes"],
+                     "workspace_over_M": st2["workspace_bytes"] / (8.0 * n * n)}
+            if prec == "mixed_f16":
+                # Plan steps of the float recursion and of the correction
+                # solves by kind (HIP events); the rest of the call is the
+                # FP64 residuals, the refinement kernels and the loads.
+                lib.bri_profile_enable(1)
+                profile_read(lib)
+                pms, _ = time_calls(c2, 1, 0, torch)
+                mprof = profile_read(lib)
+                lib.bri_profile_enable(0)
+                entry["profiled_ms_per_step"] = pms
+                entry["breakdown"] = {KIND_NAMES[t]: {"ms_per_step": v[2], "launches_per_step": v[1]}
+                                      for t, v in mprof.items() if v[0]}
+            variants.append(entry)
             del ws2, o2
 
     # ---- memory budget: the same call within a quarter of M's size ----------
@@ -447,6 +463,43 @@ def main() -> int:
                          "rel_error_vs_dense_inverse": rel_err(ro.cpu().numpy(), rwant), "info": int(rinfo.item()),
                          "workspace_bytes": bri.rbf_workspace_size(npts, dd, kr, 0, 0)})
         del M64, M32
+        # Elimination order study: the paper's literal frame order against
+        # the principal order (every pivot a principal Schur complement, the
+        # reformulation with respect to (M/A) of eq. SchurofA), k = 8 on
+        # Q Lam Q^T with cond 1e4 (automatic pivoting: a factorisation whose
+        # element growth trips the check is redone with panel pivoting), and
+        # k = 5 on a tridiagonal matrix.
+        ns, ks_ = 4096, 8
+        Ms_, qs, lams = workloads.haar_spd_device(ns, 33, 0.0, 4.0, pin_endpoints=True, device=dev,
+                                                  return_factors=True)
+        bs = bri.block_size(ns, ks_)
+        qs0 = qs[:bs].contiguous()
+        want_s = ((qs0 * torch.from_numpy(1.0 / lams).to(dev)[None, :]) @ qs0.T.contiguous()).cpu().numpy()
+        del qs, qs0
+        study = []
+        sflops = bri.plan_describe(ns, ks_, 0, 0, "f64")["algorithmic_flops"]
+        for order in ("principal", "paper"):
+            sinfo = torch.zeros(1, dtype=torch.int32, device=dev)
+            so = torch.empty(bs, bs, dtype=torch.float64, device=dev)
+            cs = lambda: bri.invert_block(Ms_, ks_, 0, 0, out=so, info=sinfo, order=order)  # noqa: E731
+            sms, _ = time_calls(cs, 2, 1, torch)
+            study.append({"order": order, "matrix": "spd_n4096_k8: Q Lam Q^T, cond 1e4 (endpoints pinned), block (0,0)",
+                          "ms_per_call": sms, "tflops": sflops / (sms * 1e-3) / 1e12,
+                          "rel_error": rel_err(so.cpu().numpy(), want_s), "info": int(sinfo.item())})
+        del Ms_
+        mt = workloads.tridiag_toeplitz(4000)
+        Mt = torch.from_numpy(mt).to(dev)
+        bt = bri.block_size(4000, 5)
+        want_t = np.linalg.inv(mt)[:bt, :bt]
+        for order in ("principal", "paper"):
+            tinfo = torch.zeros(1, dtype=torch.int32, device=dev)
+            to_ = bri.invert_block(Mt, 5, 0, 0, info=tinfo, pivoting="panel", order=order)
+            torch.cuda.synchronize()
+            ti = int(tinfo.item())
+            study.append({"order": order, "matrix": "tridiagonal (4, -1), n = 4000, k = 5, block (0,0)",
+                          "info": ti, "rel_error": rel_err(to_.cpu().numpy(), want_t) if ti == 0 else None})
+        del Mt
+        line["order_study"] = study
     line["variants"] = variants
 
     # ---- batched workload: 512 problems, n in [64, 1024], k in {2,3,4} ---------

@@ -87,6 +87,26 @@ typedef enum {
                            same workspace).  Synchronous.                            */
 } bri_pivoting;
 
+/* Elimination order of the recursion. */
+typedef enum {
+  BRI_ORDER_PRINCIPAL = 0, /* default: every Schur complement is taken with respect to a
+                              principal pivot block v(p, p, I) (eq. SchurofA with the
+                              pivot moved to the leading position); for a target
+                              (i, j) the other blocks are eliminated in ascending
+                              order, then j (i != j) or the largest other index, and an
+                              off-diagonal block is assembled by eq. invSchur          */
+  BRI_ORDER_PAPER = 1      /* the literal frame procedure of Sections "Forward recursive
+                              procedure" and "Backward recursive procedure": block rows
+                              0 <-> j and columns 0 <-> i exchanged, typed frames
+                              reduced by (M/D), (M/C), (M/B) or (M/A), the root's (M/D)
+                              inverted.  For k >= 5 some pivots are non-principal
+                              blocks, which may be singular or ill-conditioned where
+                              the principal order's are not.  invert_block and its
+                              size / describe / dump queries only, BRI_F64 and BRI_F32,
+                              without reuse; elsewhere BRI_ERR_UNSUPPORTED (size
+                              queries: 0)                                              */
+} bri_order;
+
 typedef struct {
   int precision;           /* a bri_precision value                                   */
   int concurrency;         /* W: Schur operations evaluated side by side; <= 0: auto  */
@@ -117,6 +137,7 @@ typedef struct {
                               Theorem "MC_BRI").  Size queries return 0 and calls
                               BRI_ERR_WORKSPACE when even width 1 does not fit.
                               Batched calls ignore it.                            */
+  int order;               /* a bri_order value (default BRI_ORDER_PRINCIPAL)         */
 } bri_opts;
 
 /* Fills *o with defaults: BRI_F64, automatic concurrency, automatic pivoting

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libbri.so")
 PRECISIONS = {"f64": 0, "f32": 1, "mixed_f32": 2, "mixed_f16": 3, "mixed_bf16": 4}
 PIVOTING = {"tile": 0, "panel": 1, "auto": 2}
 FACTORIZATIONS = {"auto": 0, "tile": 1, "recursive": 2}
+ORDERS = {"principal": 0, "paper": 1}
 _DTYPE_OF = {"f64": torch.float64, "f32": torch.float32, "mixed_f32": torch.float64,
              "mixed_f16": torch.float64, "mixed_bf16": torch.float64}
 
@@ -45,6 +46,7 @@ class BriOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("factorization", ctypes.c_int),
         ("workspace_budget", ctypes.c_size_t),
+        ("order", ctypes.c_int),
     ]
 
 
@@ -164,7 +166,7 @@ def _check(status: int) -> None:
 
 def make_opts(precision: str = "f64", concurrency: int = 0, refine_max_iters: int = 10,
               refine_tol: float = 1e-12, pivoting: str = "auto", reuse: bool = False,
-              factorization: str = "auto", workspace_budget: int = 0) -> BriOpts:
+              factorization: str = "auto", workspace_budget: int = 0, order: str = "principal") -> BriOpts:
     o = BriOpts()
     lib().bri_default_opts(ctypes.byref(o))
     if precision not in PRECISIONS:
@@ -181,6 +183,9 @@ def make_opts(precision: str = "f64", concurrency: int = 0, refine_max_iters: in
         raise ValueError(f"unknown factorization {factorization!r}")
     o.factorization = FACTORIZATIONS[factorization]
     o.workspace_budget = int(workspace_budget)
+    if order not in ORDERS:
+        raise ValueError(f"unknown order {order!r}")
+    o.order = ORDERS[order]
     return o
 
 
@@ -202,10 +207,11 @@ def block_size(n: int, k: int) -> int:
 
 
 def plan_describe(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
-                  reuse: bool = False, factorization: str = "auto", workspace_budget: int = 0) -> dict:
+                  reuse: bool = False, factorization: str = "auto", workspace_budget: int = 0,
+                  order: str = "principal") -> dict:
     """Host-only structure of the plan (no GPU needed)."""
     o = make_opts(precision, concurrency, reuse=reuse, factorization=factorization,
-                  workspace_budget=workspace_budget)
+                  workspace_budget=workspace_budget, order=order)
     s = BriPlanStats()
     _check(lib().bri_plan_describe(n, k, i, j, ctypes.byref(o), ctypes.byref(s)))
     return {f: getattr(s, f) for f, _ in BriPlanStats._fields_}
@@ -226,9 +232,9 @@ def _decode_steps(words: List[int]) -> List[tuple]:
 
 
 def plan_dump(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
-              reuse: bool = False) -> List[tuple]:
+              reuse: bool = False, order: str = "principal") -> List[tuple]:
     """Host-only list of plan steps: [(kind, [items...])], item = (dst, x, y, cin, sub, node)."""
-    o = make_opts(precision, concurrency, reuse=reuse)
+    o = make_opts(precision, concurrency, reuse=reuse, order=order)
     need = lib().bri_plan_dump(n, k, i, j, ctypes.byref(o), None, 0)
     if need < 0:
         raise BriError(int(need), status_string(int(need)))
@@ -252,8 +258,8 @@ def refine_plan_dump(n: int, k: int, j: int, which: str, concurrency: int = 0, r
 
 
 def workspace_size(n: int, k: int, i: int, j: int, precision: str = "f64", concurrency: int = 0,
-                   reuse: bool = False, workspace_budget: int = 0) -> int:
-    o = make_opts(precision, concurrency, reuse=reuse, workspace_budget=workspace_budget)
+                   reuse: bool = False, workspace_budget: int = 0, order: str = "principal") -> int:
+    o = make_opts(precision, concurrency, reuse=reuse, workspace_budget=workspace_budget, order=order)
     return int(lib().bri_workspace_size(n, k, i, j, ctypes.byref(o)))
 
 
@@ -261,8 +267,12 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
                  out: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
                  workspace: Optional[torch.Tensor] = None, refine_max_iters: int = 10,
                  refine_tol: float = 1e-12, pivoting: str = "auto", reuse: bool = False,
-                 factorization: str = "auto", workspace_budget: int = 0) -> torch.Tensor:
+                 factorization: str = "auto", workspace_budget: int = 0,
+                 order: str = "principal") -> torch.Tensor:
     """Block N_ij (b x b, b = ceil(n/k)) of M^{-1} (of Gamma^{-1} when k does not divide n).
+
+    ``order="paper"`` runs the paper's literal frame procedure instead of the
+    principal elimination order (f64 / f32, no reuse).
 
     ``info`` (optional int32 GPU tensor of one element) receives the device
     status of include/bri.h; it is not checked here (no synchronisation).
@@ -274,7 +284,7 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
         raise ValueError("M must be square")
     b = block_size(n, k)
     o = make_opts(precision, concurrency, refine_max_iters, refine_tol, pivoting, reuse, factorization,
-                  workspace_budget)
+                  workspace_budget, order)
     need = lib().bri_workspace_size(n, k, i, j, ctypes.byref(o))
     if need == 0:
         # Invalid arguments: let the library name the offending one (it

@@ -98,7 +98,8 @@ struct CachedPlan {
 
 typedef std::tuple<int, int64_t, int, int, int, int, int, int> PlanKey;  // kind,n,k,i,j,width,elem,transpose
 // kind: 0 block plan, 1 block column plan, 2 block plan with kept pivots,
-// 3 block plan reading M through staged block loads only
+// 3 block plan reading M through staged block loads only, 4 block plan in
+// the literal frame order
 
 std::mutex g_cache_mu;
 std::map<PlanKey, std::shared_ptr<CachedPlan>>& cache() {
@@ -128,6 +129,14 @@ int auto_width(int64_t n, int k, int precision) {
   while (wmem * 4 * per <= 32.0 * (1ull << 30)) wmem *= 4;
   w = std::min(w, wmem);
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(w, leaves_of(k))));
+}
+
+// Plan kind of a single-block call (see get_plan); the literal frame order
+// exists for the plain precisions without kept pivots only (order_ok).
+int block_kind(const bri_opts* o) { return o->order == BRI_ORDER_PAPER ? 4 : (o->reuse ? 2 : 0); }
+bool order_ok(const bri_opts* o) {
+  if (o->order == BRI_ORDER_PRINCIPAL) return true;
+  return o->order == BRI_ORDER_PAPER && !o->reuse && (o->precision == BRI_F64 || o->precision == BRI_F32);
 }
 
 int resolve_width(int64_t n, int k, const bri_opts* o) {
@@ -172,6 +181,7 @@ std::shared_ptr<CachedPlan> get_plan(int kind, int64_t n, int k, int i, int j, i
   cp->plan = kind == 0   ? make_block_plan(n, k, i, j, width)
              : kind == 2 ? make_block_plan_reuse(n, k, i, j, width)
              : kind == 3 ? make_block_plan_staged(n, k, i, j, width)
+             : kind == 4 ? make_block_plan_literal(n, k, i, j, width)
                          : make_column_plan(n, k, j, width);
   cp->plan.transpose = transpose;
   cp->layout = make_layout(cp->plan, elem);
@@ -506,12 +516,14 @@ struct ExecStep {
   bool uniform;  // every item has the block order bmax
 };
 
-// The factorisation of a step (and the triangular inversion after it) takes
-// the recursive LU with inverted factors when all its matrices have one
-// block order that the recursion halves down to tiles and the launch is
-// large enough (getrf_rec_applies); otherwise the tile-step LU.
-bool step_recursive(const ExecStep& s, int bmax, int pivoting, int lu) {
-  return lu_kind(s.count, bmax, pivoting == BRI_PIVOT_PANEL, s.uniform, lu) == LU_RECURSIVE;
+// The LU variant of a step's factorisation (lu_kind); the triangular
+// inversion after it runs only after the tile-step and panel LUs (the
+// recursive LU leaves the factors inverted).
+LuKind step_lu(const ExecStep& s, int bmax, int pivoting, int lu) {
+  return lu_kind(s.count, bmax, pivoting == BRI_PIVOT_PANEL, s.uniform, lu);
+}
+bool step_inverts_factors(const ExecStep& s, int bmax, int pivoting, int lu) {
+  return step_lu(s, bmax, pivoting, lu) == LU_RECURSIVE;
 }
 
 // Enqueues the kernels of the steps; bmax is the largest block order among
@@ -534,7 +546,7 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, const ExecCfg& cfg, h
       rec.kind = s.kind;
       rec.launches = step_launches(s.kind, s.count, bmax, pivoting, s.uniform, lu);
       // a triangular inversion skipped after the recursive LU counts no work
-      rec.flops = s.kind == ST_TRTRI && step_recursive(s, bmax, pivoting, lu) ? 0.0 : s.flops;
+      rec.flops = s.kind == ST_TRTRI && step_inverts_factors(s, bmax, pivoting, lu) ? 0.0 : s.flops;
       rec.e0 = prof_event();
       rec.e1 = prof_event();
       if (!rec.e0 || !rec.e1 || hipEventRecord(rec.e0, st) != hipSuccess) return BRI_ERR_HIP;
@@ -543,17 +555,18 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, const ExecCfg& cfg, h
       case ST_LOAD:
         e = launch_load<T>(static_cast<const LoadItem*>(s.desc), s.count, bmax, bmax, st);
         break;
-      case ST_GETRF:
-        if (pivoting == BRI_PIVOT_PANEL)
-          e = launch_getrf<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, st);
-        else if (step_recursive(s, bmax, pivoting, lu))
-          e = launch_getrf_rec<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, cfg.wide, st);
-        else
-          e = launch_getrf_tile<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, cfg.wide, st);
+      case ST_GETRF: {
+        const LuItem* d = static_cast<const LuItem*>(s.desc);
+        switch (step_lu(s, bmax, pivoting, lu)) {
+          case LU_PANEL: e = launch_getrf<T>(d, s.count, bmax, st); break;
+          case LU_RECURSIVE: e = launch_getrf_rec<T>(d, s.count, bmax, cfg.wide, st); break;
+          default: e = launch_getrf_tile<T>(d, s.count, bmax, cfg.wide, st); break;
+        }
         break;
+      }
       case ST_TRTRI:
         // after the recursive LU the factors are already inverted
-        if (!step_recursive(s, bmax, pivoting, lu))
+        if (!step_inverts_factors(s, bmax, pivoting, lu))
           e = launch_trtri<T>(static_cast<const LuItem*>(s.desc), s.count, bmax, pivoting != BRI_PIVOT_PANEL, st);
         break;
       default: {
@@ -1446,6 +1459,7 @@ int bri_profile_read(bri_profile_entry* entries, int cap) {
 }
 
 static size_t workspace_size_of(int64_t n, int k, int i, int j, const bri_opts* o) {
+  if (!order_ok(o)) return 0;
   const int w = resolve_width(n, k, o);
   if (mixed_precision(o->precision)) {
     try {
@@ -1456,7 +1470,7 @@ static size_t workspace_size_of(int64_t n, int k, int i, int j, const bri_opts* 
   }
   if (!plain_precision(o->precision)) return 0;
   try {
-    auto cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, w, elem_size(o->precision), 0);
+    auto cp = get_plan(block_kind(o), n, k, i, j, w, elem_size(o->precision), 0);
     return cp->layout.total;
   } catch (const std::exception&) {
     return 0;
@@ -1473,7 +1487,7 @@ static int32_t* block_info_word(int64_t n, int k, int i, int j, const bri_opts* 
       off = mb.info_off;
       need = mb.total;
     } else {
-      auto cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, resolve_width(n, k, o), elem_size(o->precision), 0);
+      auto cp = get_plan(block_kind(o), n, k, i, j, resolve_width(n, k, o), elem_size(o->precision), 0);
       off = cp->layout.info_off;
       need = cp->layout.total;
     }
@@ -1504,8 +1518,9 @@ int bri_plan_describe(int64_t n, int k, int i, int j, const bri_opts* o, bri_pla
   const bri_opts ob = block_budget(o, n, k, i, j, fits);
   if (!fits) return BRI_ERR_WORKSPACE;
   o = &ob;
+  if (!order_ok(o)) return BRI_ERR_UNSUPPORTED;
   const int w = resolve_width(n, k, o);
-  auto cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, w, elem_size(o->precision), 0);
+  auto cp = get_plan(block_kind(o), n, k, i, j, w, elem_size(o->precision), 0);
   const Plan& p = cp->plan;
   s->schur_ops = p.schur_ops;
   s->final_inversions = p.final_inversions;
@@ -1559,8 +1574,9 @@ int64_t bri_plan_dump(int64_t n, int k, int i, int j, const bri_opts* o, int64_t
   if (!o) return -5;
   const int rc = check_block_args(n, n, k, i, j, (n + k - 1) / k);
   if (rc) return rc;
+  if (!order_ok(o)) return BRI_ERR_UNSUPPORTED;
   const int w = resolve_width(n, k, o);
-  auto cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, w, elem_size(o->precision), 0);
+  auto cp = get_plan(block_kind(o), n, k, i, j, w, elem_size(o->precision), 0);
   return dump_steps(cp->plan, words, cap);
 }
 
@@ -1594,6 +1610,7 @@ static int invert_block_impl(const void* M, int64_t n, int64_t ldm, int k, int i
   const bri_opts ob = block_budget(o, n, k, i, j, fits);
   if (!fits) return BRI_ERR_WORKSPACE;
   o = &ob;
+  if (!order_ok(o)) return BRI_ERR_UNSUPPORTED;
   if (o->pivoting == BRI_PIVOT_AUTO) {
     // Tile pivoting first; if a factorisation reported a failed pivot or
     // element growth, the block again with panel pivoting.
@@ -1619,7 +1636,7 @@ static int invert_block_impl(const void* M, int64_t n, int64_t ldm, int k, int i
   const int w = resolve_width(n, k, o);
   std::shared_ptr<CachedPlan> cp;
   try {
-    cp = get_plan(o->reuse ? 2 : 0, n, k, i, j, w, elem, 0);
+    cp = get_plan(block_kind(o), n, k, i, j, w, elem, 0);
   } catch (const std::exception&) {
     return BRI_ERR_UNSUPPORTED;
   }
@@ -1685,6 +1702,7 @@ int bri_block_column(const void* M, int64_t n, int64_t ldm, int k, int j, int tr
   if (!M) return -1;
   if (!X) return -7;
   if (!o) return -9;
+  if (o->order != BRI_ORDER_PRINCIPAL) return BRI_ERR_UNSUPPORTED;  // the column plan is principal
   const int rc = check_block_args(n, ldm, k, 0, j, ldx);
   if (rc) return rc == -8 ? -8 : (rc == -6 ? -5 : rc);
   if (!plain_precision(o->precision)) return BRI_ERR_UNSUPPORTED;
@@ -1748,6 +1766,7 @@ static int check_batch_args(int count, const int64_t* n, const int* k, const int
 size_t bri_batched_workspace_size(int count, const int64_t* n, const int* k, const int* i, const int* j,
                                   const bri_opts* o) {
   if (count < 0 || !n || !k || !i || !j || !o) return 0;
+  if (o->order != BRI_ORDER_PRINCIPAL) return 0;
   if (check_batch_args(count, n, k, i, j) != 0) return 0;
   if (count == 0) return kAlign;
   if (batch_mergeable(o)) {
@@ -1779,6 +1798,7 @@ int invert_block_batched(int count, const void* const* M, const int64_t* n, cons
   if (!out) return -8;
   if (!ldo) return -9;
   if (!o) return -10;
+  if (o->order != BRI_ORDER_PRINCIPAL) return BRI_ERR_UNSUPPORTED;
   if (count == 0) return BRI_OK;
   for (int t = 0; t < count; ++t) {
     if (!M[t]) return -2;
@@ -1975,7 +1995,7 @@ static int invert_block_rbf_impl(const void* X, int64_t npts, int64_t ldx, int d
 extern "C" {
 
 size_t bri_rbf_workspace_size(int64_t npts, int d, int k, int i, int j, const bri_opts* o) {
-  if (!o || check_rbf_args(npts, d, d, 1.0, 1.0, k, i, j, (npts + k) / k, o) != 0) return 0;
+  if (!o || o->order != BRI_ORDER_PRINCIPAL || check_rbf_args(npts, d, d, 1.0, 1.0, k, i, j, (npts + k) / k, o) != 0) return 0;
   const int64_t m = npts + 1;
   bool fits;
   const bri_opts ob = with_budget(o, m, k, [&](const bri_opts& r) { return rbf_size_of(m, k, i, j, &r); }, fits);
@@ -1988,6 +2008,7 @@ int invert_block_rbf(const void* X, int64_t npts, int64_t ldx, int d, double sig
   if (!out) return -10;
   const int rc = check_rbf_args(npts, ldx, d, sigma, gamma, k, i, j, ldo, o);
   if (rc) return rc;
+  if (o->order != BRI_ORDER_PRINCIPAL) return BRI_ERR_UNSUPPORTED;
   const int64_t m = npts + 1;
   bool fits;
   const bri_opts ob = with_budget(o, m, k, [&](const bri_opts& r) { return rbf_size_of(m, k, i, j, &r); }, fits);
@@ -2080,7 +2101,7 @@ static bri_opts backward_budget(const bri_opts* o, int64_t n, int k, int i, int 
 
 size_t bri_backward_workspace_size(int64_t n, int k, int i, int j, const bri_opts* o) {
   if (!o || check_block_args(n, n, k, i, j, (n + k - 1) / k) != 0) return 0;
-  if (!plain_precision(o->precision)) return 0;
+  if (!plain_precision(o->precision) || o->order != BRI_ORDER_PRINCIPAL) return 0;
   bool fits;
   const bri_opts ob = backward_budget(o, n, k, i, j, fits);
   return fits ? backward_size_of(n, k, i, j, &ob) : 0;
@@ -2106,6 +2127,7 @@ int invert_block_backward(const void* M, int64_t n, int64_t ldm, int k, int i, i
   if (!G) return -7;
   if (!grad_M) return -9;
   if (!o) return -11;
+  if (o->order != BRI_ORDER_PRINCIPAL) return BRI_ERR_UNSUPPORTED;
   if (n < 1) return -2;
   if (ldm < n) return -3;
   if (k < 2 || k > n) return -4;

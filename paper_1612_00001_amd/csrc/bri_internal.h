@@ -268,6 +268,12 @@ int stage_matrix_blocks(Plan& p, int base);
 // make_block_plan with every block of M staged that way.
 Plan make_block_plan_staged(int64_t n, int k, int i, int j, int width);
 
+// The plan of invert_block in the paper's literal frame order (Sections
+// "Forward recursive procedure" and "Backward recursive procedure"): typed
+// frames whose Schur complements may pivot on non-principal blocks, block
+// rows 0 <-> j and columns 0 <-> i exchanged, the root's (M/D) inverted.
+Plan make_block_plan_literal(int64_t n, int k, int i, int j, int width);
+
 // The plan of invert_block with the k - 1 elimination pivots kept and reused
 // (each Schur node then has three children; the paper's suggested reuse
 // across branches).  Same result, fewer operations, k - 1 kept b x b blocks.

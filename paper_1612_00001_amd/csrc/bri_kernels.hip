@@ -391,17 +391,41 @@ struct TileOp {
   }
 };
 
-// Work item and output tile of a workgroup.  Workgroups are numbered item
-// fastest (tile t of every item before tile t + 1 of any), so that
-// workgroups dispatched together spread over all items.  With a triangular
-// operand the K range of a tile depends on its position; the heaviest tiles
-// take the lowest numbers (dispatched first) so that a launch does not end
-// on a tail of long tiles.
+// Work item and role of a workgroup of the LU step kernel: numbered item
+// fastest (role t of every item before role t + 1 of any).
 __device__ __forceinline__ void gemm_workgroup(int& item, int& tile) {
   const int flat = blockIdx.y * gridDim.x + blockIdx.x;
   item = flat % gridDim.y;
   tile = flat / gridDim.y;
 }
+
+// Work item and output tile of a product workgroup (grid: tiles x items).
+// The dispatcher hands consecutive workgroups to the eight XCDs in turn
+// (workgroup w runs on XCD w mod 8), and each XCD has its own L2.  In large
+// launches the workgroups are renumbered so that every XCD takes one
+// contiguous range of the item-major order (item by item, the tiles of an
+// item together): the tiles an XCD runs at one time belong to one or two
+// items and share their operand panels in that XCD's L2 (n = 16384, k = 8:
+// -4% per call).  Small launches keep the item-fastest order (tile t of
+// every item before tile t + 1 of any), which spreads them over the XCDs.
+// Any numbering is correct.
+__device__ __forceinline__ void product_workgroup(int& item, int& tile) {
+  const int g = gridDim.x * gridDim.y;
+  const int w = blockIdx.y * gridDim.x + blockIdx.x;
+  if (g < 2048) {
+    item = w % gridDim.y;
+    tile = w / gridDim.y;
+    return;
+  }
+  const int q = g >> 3, r = g & 7, x = w & 7, l = w >> 3;
+  const int f = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+  item = f / gridDim.x;
+  tile = f % gridDim.x;
+}
+// Output tile (tm, tn) of tile number bid of an item, row by row (column by
+// column for a triangular B).  With a triangular operand the K range of a
+// tile depends on its position; the heaviest tiles take the lowest numbers
+// (dispatched first) so that a launch does not end on a tail of long tiles.
 __device__ __forceinline__ void heavy_first(const GemmItem& it, int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
   if (it.B.tri != 0 && it.A.tri == 0) {
     tn = bid / tiles_m;
@@ -464,7 +488,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm(GemmLaunch 
 
   GemmItem it;
   int item, tile;
-  gemm_workgroup(item, tile);
+  product_workgroup(item, tile);
   // Explicit items: this launch takes items [L.j, L.j + gridDim.y).
   if (!gemm_item<T, MODE>(L, item + (MODE == GEMM_EXPLICIT ? L.j : 0), it)) return;
   const int tiles_n = (it.N + BN - 1) / BN;
@@ -669,7 +693,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmLaun
 
   GemmItem it;
   int item, tile;
-  gemm_workgroup(item, tile);
+  product_workgroup(item, tile);
   if (!gemm_item<double, MODE>(L, item, it)) return;
   const int tiles_n = (it.N + BN - 1) / BN;
   const int tiles_m = (it.M + BM - 1) / BM;
@@ -806,16 +830,16 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmLaun
     // and issue (their loads repeat the last step), so that every step of the
     // unrolled body has the same loads in flight.
     auto step = [&](int t, double* ra, double* rb, double* wa, double* wb) {
-      // vmcnt(0): the wait covers steps t and t + 1 (a partial wait, for
-      // all but the last step's loads, gave wrong blocks with two
-      // workgroups per compute unit before the lgkmcnt(0) below was added,
-      // which may have been the cause; the full wait costs nothing
-      // measurable).  lgkmcnt(0): this wavefront's
-      // reads of step t - 1's buffer are complete before the barrier (the
-      // compiler places the MFMAs that consume them, and their waits, after
-      // it), since once past it other wavefronts load step t + 2 into that
-      // buffer.
-      lds_barrier<0x0070>();
+      // vmcnt(AI + BI): this thread's loads of step t have landed, those of
+      // step t + 1 (the AI + BI issued last) may still be in flight.  Vector
+      // memory loads return in issue order, so the counter reaching AI + BI
+      // means every older load (and its LDS write) is done; step t + 1's
+      // pieces go to a buffer that nobody reads before the next barrier.
+      // lgkmcnt(0): this wavefront's reads of step t - 1's buffer are
+      // complete before the barrier (the compiler places the MFMAs that
+      // consume them, and their waits, after it), since once past it other
+      // wavefronts load step t + 2 into that buffer.
+      lds_barrier<0x0070 | (AI + BI)>();
       issue(t + 2, wa, wb);
       if (t < nk) {
         const int k0 = kb + t * BK;
@@ -926,7 +950,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lp(GemmLaun
 
   GemmItem it;
   int item, tile;
-  gemm_workgroup(item, tile);
+  product_workgroup(item, tile);
   if (!gemm_item<float, MODE>(L, item + (GEN ? L.j : 0), it)) return;
   const int tiles_n = (it.N + BN - 1) / BN;
   const int tiles_m = (it.M + BM - 1) / BM;
@@ -2372,11 +2396,16 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
         const int tier = gemm_tier(L, GEMM_EXPLICIT, nfast, max_m, max_n);
         if (nfast > 0 && L.ndl == nfast && tier != kTierTiny) {
           // 128 x 128 tiles of 16 wavefronts of 32 x 32 for the two larger
-          // shapes (a 128 x 256 tile would need more than the 128 registers a
-          // thread of a 1024-thread workgroup has, and spill); 64 x 64 tiles
-          // of 4 wavefronts of 32 x 32 for the small one.
+          // shapes, 64 x 64 tiles of 4 wavefronts of 32 x 32 for the small
+          // one; launches of at least 512 tiles of 256 x 128 (full products,
+          // or triangular ones with K >= 2048) take 256 x 128 tiles of 8
+          // wavefronts of 64 x 64, which read a quarter fewer operand bytes per
+          // flop (the shape the autotuner picks on the MI355X in every such
+          // case it measures).
           ndl = nfast;
           int shape = tier == kTierSmall ? kShapeDl64 : kShapeDl128;
+          const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * ndl;
+          if (tier != kTierSmall && tiles256 >= 512 && (L.tri == 0 || min(max_m, max_n) >= 2048)) shape = kShapeDl256;
           const int tuned = tuned_product_shape(8, L.tri, ndl, max_m, max_n);
           if (tuned == kShapeDl64 || tuned == kShapeDl128 || tuned == kShapeDl256) shape = tuned;
           if (g_force_shape >= kShapeDl128 && g_force_shape <= kShapeDl256) shape = g_force_shape;

@@ -55,13 +55,131 @@ struct SlotPool {
   }
 };
 
+// A node of the recursion: (r, c) at depth d in the principal order, or
+// frame f (depth = its size - 1) of the paper's literal frame procedure.
 struct Node {
   int r, c, depth;
+  int f = -1;
+};
+
+// The frames of the paper's forward procedure (Section "Forward recursive
+// procedure"), for the literal elimination order.  A frame is a list of
+// block rows and one of block columns with a type (R for the root, else the
+// child position A, B, C or D it came from).  A frame of at least three
+// blocks a side first exchanges its two leading block columns (types B, D)
+// and / or rows (types C, D), so that the block its parent regarded as M_22
+// is back at position (2, 2); then its children drop the last row and
+// column (A), the last row and first column (B), the first row and last
+// column (C), or the first row and column (D).  Frames of two blocks a side
+// are the leaves: their four blocks are blocks of M.
+struct LitFrame {
+  std::vector<int> rows, cols;
+  char type;
+  int kid[4];  // child frames A, B, C, D (-1 for a leaf frame)
+};
+
+class LitTree {
+ public:
+  // Root frame of block (i, j): block rows 0 and j and block columns 0 and
+  // i exchanged, so that N_ij is the (1, 1) block of the permuted inverse.
+  LitTree(int k, int i, int j) {
+    std::vector<int> rows(k), cols(k);
+    for (int t = 0; t < k; ++t) rows[t] = cols[t] = t;
+    std::swap(rows[0], rows[j]);
+    std::swap(cols[0], cols[i]);
+    root_ = visit(rows, cols, 'R');
+  }
+  int root() const { return root_; }
+  const LitFrame& at(int f) const { return frames_[f]; }
+  // Positions (A, B, C, D = 0..3) of the operands X, Y, Z, W of the frame's
+  // Schur complement X - Y Z^{-1} W for its type: the root and A frames
+  // take (M/D) = A - B D^{-1} C, B frames (M/C) = B - A C^{-1} D, C frames
+  // (M/B) = C - D B^{-1} A and D frames (M/A) = D - C A^{-1} B (eqs.
+  // SchurofD, SchurofC, SchurofB, SchurofA).
+  static void roles(char type, int& x, int& y, int& z, int& w) {
+    switch (type) {
+      case 'B': x = 1; y = 0; z = 2; w = 3; break;
+      case 'C': x = 2; y = 3; z = 1; w = 0; break;
+      case 'D': x = 3; y = 2; z = 0; w = 1; break;
+      default:  x = 0; y = 1; z = 3; w = 2; break;
+    }
+  }
+
+ private:
+  int visit(std::vector<int> rows, std::vector<int> cols, char type) {
+    const size_t m = rows.size();
+    if (m >= 3) {
+      if (type == 'B' || type == 'D') std::swap(cols[0], cols[1]);
+      if (type == 'C' || type == 'D') std::swap(rows[0], rows[1]);
+    }
+    const int id = static_cast<int>(frames_.size());
+    frames_.push_back(LitFrame{rows, cols, type, {-1, -1, -1, -1}});
+    if (m >= 3) {
+      const std::vector<int> r_head(rows.begin(), rows.end() - 1), r_tail(rows.begin() + 1, rows.end());
+      const std::vector<int> c_head(cols.begin(), cols.end() - 1), c_tail(cols.begin() + 1, cols.end());
+      const int a = visit(r_head, c_head, 'A');
+      const int b = visit(r_head, c_tail, 'B');
+      const int c = visit(r_tail, c_head, 'C');
+      const int d = visit(r_tail, c_tail, 'D');
+      frames_[id].kid[0] = a;
+      frames_[id].kid[1] = b;
+      frames_[id].kid[2] = c;
+      frames_[id].kid[3] = d;
+    }
+    return id;
+  }
+  std::vector<LitFrame> frames_;
+  int root_ = -1;
 };
 
 class Builder {
  public:
   Builder(Plan& p, std::vector<int> elim, int width) : plan_(p), elim_(std::move(elim)), width_(width) {}
+  // Literal frame order: nodes are frames of tree t (which must outlive the
+  // builder) and carry their own operand roles.
+  void set_literal(const LitTree* t) { lit_ = t; }
+
+  // The children of node u in the roles of its Schur complement
+  // X - Y Z^{-1} W (principal order: X = (r, c), Y = (r, p), Z = (p, p),
+  // W = (p, c) at depth d - 1, p the pivot of depth d).
+  void kids_of(const Node& u, Node& x, Node& y, Node& z, Node& w) const {
+    if (lit_) {
+      const LitFrame& F = lit_->at(u.f);
+      int rx, ry, rz, rw;
+      LitTree::roles(F.type, rx, ry, rz, rw);
+      x = Node{-1, -1, u.depth - 1, F.kid[rx]};
+      y = Node{-1, -1, u.depth - 1, F.kid[ry]};
+      z = Node{-1, -1, u.depth - 1, F.kid[rz]};
+      w = Node{-1, -1, u.depth - 1, F.kid[rw]};
+      return;
+    }
+    const int p = pivot_of(u.depth);
+    x = Node{u.r, u.c, u.depth - 1};
+    y = Node{u.r, p, u.depth - 1};
+    z = Node{p, p, u.depth - 1};
+    w = Node{p, u.c, u.depth - 1};
+  }
+  // The blocks of a depth-1 node in the same roles (W and X may stand for
+  // the right-hand side column of a solve plan).
+  void leaf_blocks(const Node& u, Opnd& x, Opnd& y, Opnd& z, Opnd& w) const {
+    if (lit_) {
+      const LitFrame& F = lit_->at(u.f);
+      const Opnd q[4] = {Opnd::mblk(F.rows[0], F.cols[0]), Opnd::mblk(F.rows[0], F.cols[1]),
+                         Opnd::mblk(F.rows[1], F.cols[0]), Opnd::mblk(F.rows[1], F.cols[1])};
+      int rx, ry, rz, rw;
+      LitTree::roles(F.type, rx, ry, rz, rw);
+      x = q[rx];
+      y = q[ry];
+      z = q[rz];
+      w = q[rw];
+      return;
+    }
+    const int p = pivot_of(1);
+    x = blk(u.r, u.c);
+    y = Opnd::mblk(u.r, p);
+    z = Opnd::mblk(p, p);
+    w = blk(p, u.c);
+  }
 
   int next_node() { return node_counter_++; }
   SlotPool& pool() { return pool_; }
@@ -172,12 +290,11 @@ class Builder {
  private:
   std::vector<int> leaf(const std::vector<Node>& L, const std::vector<int>& accs) {
     const size_t n = L.size();
-    const int p = pivot_of(1);
     const int memo = memo_of(1);
     std::vector<int> sp(n), sx(n), outs(n);
-    std::vector<Opnd> rhs(n), xd(n);
+    std::vector<Opnd> rhs(n), xd(n), bx(n), by(n), bz(n);
     for (size_t t = 0; t < n; ++t) {
-      rhs[t] = blk(p, L[t].c);
+      leaf_blocks(L[t], bx[t], by[t], bz[t], rhs[t]);
     }
     if (memo >= 0) {
       for (size_t t = 0; t < n; ++t) sx[t] = pool_.alloc();
@@ -191,7 +308,7 @@ class Builder {
       for (size_t t = 0; t < n; ++t) {
         StepItem it;
         it.dst = Opnd::slot(sp[t]);
-        it.x = Opnd::mblk(p, p);
+        it.x = bz[t];
         ld.items.push_back(it);
       }
       for (size_t t = 0; t < n; ++t) xd[t] = Opnd::slot(sx[t]);
@@ -203,9 +320,9 @@ class Builder {
     for (size_t t = 0; t < n; ++t) {
       StepItem it;
       it.dst = Opnd::slot(outs[t]);
-      it.x = Opnd::mblk(L[t].r, p);
+      it.x = by[t];
       it.y = Opnd::slot(sx[t]);
-      it.cin = blk(L[t].r, L[t].c);
+      it.cin = bx[t];
       it.sub = accs[t] >= 0 ? Opnd::slot(accs[t]) : Opnd::none();
       g.items.push_back(it);
     }
@@ -216,15 +333,16 @@ class Builder {
   std::vector<int> expand(const std::vector<Node>& L, const std::vector<int>& accs) {
     const size_t n = L.size();
     const int d = L[0].depth;
-    const int p = pivot_of(d);
     const int memo = memo_of(d);
     const int nk = memo >= 0 ? 3 : 4;
     std::vector<Node> kids;
     for (size_t t = 0; t < n; ++t) {
-      kids.push_back({L[t].r, L[t].c, d - 1});
-      kids.push_back({L[t].r, p, d - 1});
-      if (memo < 0) kids.push_back({p, p, d - 1});
-      kids.push_back({p, L[t].c, d - 1});
+      Node x, y, z, w;
+      kids_of(L[t], x, y, z, w);
+      kids.push_back(x);
+      kids.push_back(y);
+      if (memo < 0) kids.push_back(z);
+      kids.push_back(w);
     }
     const std::vector<int> res = eval_children(kids);
     std::vector<int> src(n), srp(n), spp(n), spc(n);
@@ -266,19 +384,20 @@ class Builder {
   std::vector<int> lockstep(const std::vector<Node>& L, const std::vector<int>& accs) {
     const size_t n = L.size();
     const int d = L[0].depth;
-    const int p = pivot_of(d);
     const int memo = memo_of(d);
     const std::vector<int> none(n, -1);
+    std::vector<Node> kx(n), ky(n), kz(n), kw(n);
+    for (size_t t = 0; t < n; ++t) kids_of(L[t], kx[t], ky[t], kz[t], kw[t]);
     std::vector<Node> kids(n);
     std::vector<int> sp(n, memo);
     if (memo < 0) {
       // Pivot children, factored at once so only their factors stay live.
-      for (size_t t = 0; t < n; ++t) kids[t] = {p, p, d - 1};
+      kids = kz;
       sp = eval_children(kids);
       factor_only(sp);
     }
     // Right-hand children; X = P^{-1} B replaces them.
-    for (size_t t = 0; t < n; ++t) kids[t] = {p, L[t].c, d - 1};
+    kids = kw;
     const std::vector<int> sb = eval_children(kids);
     if (memo < 0) {
       solve_only(sp, sb);
@@ -290,7 +409,7 @@ class Builder {
       plan_.schur_ops += static_cast<int64_t>(n);
     }
     // Left children: acc (+)= C X.
-    for (size_t t = 0; t < n; ++t) kids[t] = {L[t].r, p, d - 1};
+    kids = ky;
     const std::vector<int> sc = eval_children(kids);
     std::vector<int> acc(n);
     std::vector<bool> own(n, false);
@@ -316,7 +435,7 @@ class Builder {
       pool_.release(sb[t]);
     }
     // Diagonal children subtract the accumulated sum in their last product.
-    for (size_t t = 0; t < n; ++t) kids[t] = {L[t].r, L[t].c, d - 1};
+    kids = kx;
     const std::vector<int> outs = eval_children(kids, acc);
     for (size_t t = 0; t < n; ++t)
       if (own[t]) pool_.release(acc[t]);
@@ -423,6 +542,7 @@ class Builder {
 
   Plan& plan_;
   std::vector<int> elim_;
+  const LitTree* lit_ = nullptr;
   int width_;
   SlotPool pool_;
   int node_counter_ = 0;
@@ -602,6 +722,33 @@ Plan make_block_plan(int64_t n, int k, int i, int j, int width) {
   const double b3 = cube(plan.b);
   const double T = static_cast<double>((static_cast<int64_t>(std::pow(4.0, k - 1)) - 1) / 3);
   plan.algorithmic_flops = T * (14.0 / 3.0) * b3 + 2.0 * b3 + (i != j ? 2.0 * b3 : 0.0);
+  account(plan);
+  return plan;
+}
+
+Plan make_block_plan_literal(int64_t n, int k, int i, int j, int width) {
+  if (k < 2 || n < k || i < 0 || i >= k || j < 0 || j >= k) throw std::invalid_argument("bad target");
+  Plan plan;
+  plan.n = n;
+  plan.k = k;
+  plan.i = i;
+  plan.j = j;
+  plan.b = static_cast<int>((n + k - 1) / k);
+  const int64_t leaves = static_cast<int64_t>(std::pow(4.0, std::max(0, k - 2)));
+  plan.width = std::max<int64_t>(1, std::min<int64_t>(width, leaves));
+  const LitTree tree(k, i, j);
+  Builder B(plan, {}, plan.width);
+  B.set_literal(&tree);
+  // The root frame reduces to the (M/D) of the permuted matrix, whose inverse
+  // is the target block (eq. blockmatrix_NxN); every target, diagonal or
+  // not, ends with that one inversion.
+  const int sz = B.eval({Node{-1, -1, k - 1, tree.root()}}, {-1})[0];
+  B.final_inverse(sz, Opnd::outp(), true);
+  B.pool().release(sz);
+  plan.nslots = B.pool().peak;
+  const double b3 = cube(plan.b);
+  const double T = static_cast<double>((static_cast<int64_t>(std::pow(4.0, k - 1)) - 1) / 3);
+  plan.algorithmic_flops = T * (14.0 / 3.0) * b3 + 2.0 * b3;
   account(plan);
   return plan;
 }

@@ -125,13 +125,12 @@ def test_gaussian_b1024_pivoting(pivoting):
         assert err < 1e-10
 
 
-@pytest.mark.parametrize("factorization", ["tile", "recursive"])
-def test_permuted_pivot_block(factorization):
+@pytest.mark.parametrize("factorization,b", [("tile", 64), ("recursive", 64), ("tile", 256), ("recursive", 256)])
+def test_permuted_pivot_block(factorization, b):
     # The first pivot block of target (0, 0) is the anti-diagonal permutation
     # matrix: perfectly conditioned, but every 32 x 32 diagonal tile is zero.
     # Tile pivoting reports it; automatic pivoting recomputes with panel
     # pivoting and matches the oracle.
-    b = 64
     rng = np.random.default_rng(21)
     a = rng.standard_normal((b, b)) + b * np.eye(b)
     bb = rng.standard_normal((b, b))
@@ -145,7 +144,7 @@ def test_permuted_pivot_block(factorization):
                                factorization=factorization).cpu().numpy()
         torch.cuda.synchronize()
         st = int(info.item())
-        print(f"permuted pivot block {factorization} {pivoting}: info {st}", flush=True)
+        print(f"permuted pivot block b={b} {factorization} {pivoting}: info {st}", flush=True)
         if pivoting == "tile":
             assert st == 1
         else:
@@ -503,3 +502,4 @@ def test_autotune_writes_and_applies_a_cache(tmp_path):
     empty = tmp_path / "empty.txt"
     empty.write_text("")
     bri.tune_load(str(empty))
+

@@ -402,3 +402,65 @@ def test_tuning_cache_drives_the_lu_choice(tmp_path):
     assert bri.plan_describe(n, k, 0, 0, "f64")["kernel_launches"] == auto
     with pytest.raises(bri.BriError):
         bri.tune_load(str(tmp_path / "missing.txt"))
+
+
+# ---------------------------------------------------------------------------
+# The paper's literal frame order (typed frames, non-principal pivots)
+# ---------------------------------------------------------------------------
+LITERAL_CASES = [(16, 2, 0, 0, 1), (16, 2, 1, 0, 1), (18, 3, 0, 0, 1), (18, 3, 2, 1, 4), (24, 4, 0, 0, 1),
+                 (24, 4, 1, 2, 4), (23, 4, 3, 3, 16), (25, 5, 0, 0, 1), (25, 5, 4, 1, 16), (25, 5, 2, 2, 64),
+                 (18, 6, 5, 2, 64), (14, 7, 3, 3, 16)]
+
+
+@pytest.mark.parametrize("n,k,i,j,W", LITERAL_CASES)
+def test_literal_plan_follows_the_literal_oracle(n, k, i, j, W):
+    import oracle
+    m = workloads.gaussian_dd(n, 4000 + 7 * n + k)
+    steps = bri.plan_dump(n, k, i, j, "f64", W, order="paper")
+    out = run_plan(m, k, steps)
+    want = oracle.literal_invert_block(m, k, i, j)
+    assert np.abs(out[0] - want).max() < 1e-12
+    d = bri.plan_describe(n, k, i, j, "f64", W, order="paper")
+    assert d["schur_ops"] == (4 ** (k - 1) - 1) // 3 and d["final_inversions"] == 1
+
+
+def test_literal_plan_pivots_on_non_principal_blocks():
+    # Tridiagonal M (4 on the diagonal, -1 beside it), n = 20, k = 5: every
+    # off-diagonal block has rank <= 1 and every principal Schur complement
+    # is SPD.  The literal order's typed frames (M/C) and (M/B) pivot on
+    # non-principal Schur complements, and for k = 5 one of them is exactly
+    # singular here (as in the oracle); the principal order is not affected.
+    import oracle
+    m = workloads.tridiag_toeplitz(20)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.literal_invert_block(m, 5, 0, 0)
+    with pytest.raises(np.linalg.LinAlgError):
+        run_plan(m, 5, bri.plan_dump(20, 5, 0, 0, "f64", 4, order="paper"))
+    out = run_plan(m, 5, bri.plan_dump(20, 5, 0, 0, "f64", 4))
+    assert np.abs(out[0] - np.linalg.inv(m)[:4, :4]).max() < 1e-12
+
+
+def test_literal_order_meets_a_singular_padded_pivot():
+    # n = 26, k = 5 (b = 6): the last block row and column carry four rows of
+    # Gamma's identity padding, so a non-principal pivot block taken from
+    # them has zero rows.  The literal order meets such a pivot for block
+    # (4, 1) (the oracle's dense solves fail there too); the principal order
+    # pivots on principal blocks only and is unaffected.
+    import oracle
+    m = workloads.gaussian_dd(26, 4000 + 7 * 26 + 5)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.literal_invert_block(m, 5, 4, 1)
+    with pytest.raises(np.linalg.LinAlgError):
+        run_plan(m, 5, bri.plan_dump(26, 5, 4, 1, "f64", 16, order="paper"))
+    out = run_plan(m, 5, bri.plan_dump(26, 5, 4, 1, "f64", 16))
+    full = np.eye(30)
+    full[:26, :26] = m
+    assert np.abs(out[0] - np.linalg.inv(full)[24:30, 6:12]).max() < 1e-12
+
+
+def test_literal_order_is_rejected_where_it_does_not_apply():
+    assert bri.workspace_size(64, 4, 0, 0, "mixed_f16", order="paper") == 0
+    assert bri.workspace_size(64, 4, 0, 0, "f64", reuse=True, order="paper") == 0
+    assert bri.workspace_size(64, 4, 0, 0, "f64", order="paper") > 0
+    with pytest.raises(ValueError):
+        bri.make_opts("f64", order="literal")

@@ -59,18 +59,21 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_gemm_dl_explicit_hbm_traffic
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1612_00001_amd", "csrc", "bri_kernels.hip")
 
 
-def gemm_source_digest():
-    """sha256 over the source of the explicit-item product kernel: its
+def gemm_source_digest(text=None):
+    """sha256 over the source of the FP64 explicit-item product kernel: its
     operand loaders and kernel bodies, register-staged and direct-to-LDS (from
-    the "Operand tiles." section to the low-precision kernel) and its
-    tile-shape selection (launch_gemm_mode, launch_gemm)."""
-    text = open(KERNEL_SOURCE).read()
+    the "Operand tiles." section to the low-precision kernel) and its FP64
+    tile-shape selection (launch_gemm_mode and the FP64 branch of
+    launch_gemm)."""
+    if text is None:
+        text = open(KERNEL_SOURCE).read()
     a = text.index("// Operand tiles.")
     e = text.index("// Low-precision products")
     c = text.index("hipError_t launch_gemm_mode(")
     d = text.index("\n}\n", c)
     f = text.index("hipError_t launch_gemm(const GemmLaunch& L")
-    g = text.index("\n}\n", f)
+    f = text.index("if constexpr (sizeof(T) == 8) {", f)
+    g = min(x for x in (text.find("\n      } else {\n", f), text.find("\n      }\n      GemmLaunch F = L;", f)) if x >= 0)
     return hashlib.sha256((text[a:e] + text[c:d] + text[f:g]).encode()).hexdigest()
 
 

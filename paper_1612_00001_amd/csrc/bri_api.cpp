@@ -425,10 +425,13 @@ void describe_step(const Ctx& c, const Step& s, StepItems& out) {
           }
           g.alpha = (s.kind == ST_GEMM_ACC) ? 1.0 : -1.0;
         }
+        // direct: the FP64 direct-to-LDS instance, or for the split
+        // low-precision products of float storage the vectorised instance
+        const bool direct = c.elem == 8 ? gemm_item_is_direct(g, 8) : (c.lp != 0 && gemm_item_is_lp_vec(g));
         if (!gemm_item_is_fast(g))
           out.slow.push_back(g);
         else
-          (gemm_item_is_direct(g, c.elem) ? out.direct : out.fast).push_back(g);
+          (direct ? out.direct : out.fast).push_back(g);
         break;
       }
     }

@@ -160,6 +160,18 @@ inline bool gemm_item_is_direct(const GemmItem& g, int elem) {
          (g.B.rowperm == nullptr || g.K <= kMaxBlock) &&
          (!g.has_cin || view_plain(g.Cin, g.M, g.N)) && (!g.has_sub || view_plain(g.Sub, g.M, g.N));
 }
+// An item of the vectorised split low-precision instance (float storage,
+// k_gemm_lpv): A stored untransposed with 16-byte aligned rows, unpermuted,
+// possibly triangular; B stored untransposed, untriangular, possibly with a
+// row permutation; K a multiple of 8 (runs of eight k never cross it) and at
+// most kMaxBlock; plain Cin / Sub; no element conversion or evaluation.
+inline bool gemm_item_is_lp_vec(const GemmItem& g) {
+  return g.M > 0 && g.N > 0 && g.K > 0 && g.K % 8 == 0 && g.K <= kMaxBlock &&
+         view_direct(g.A, g.M, g.K, 4) && g.A.rowperm == nullptr && g.A.src64_max == nullptr && g.A.rbf == nullptr &&
+         g.B.p != nullptr && !g.B.trans && g.B.tri == 0 && g.K <= g.B.rows && g.N <= g.B.cols &&
+         g.B.src64_max == nullptr && g.B.rbf == nullptr &&
+         (!g.has_cin || view_plain(g.Cin, g.M, g.N)) && (!g.has_sub || view_plain(g.Sub, g.M, g.N));
+}
 inline bool gemm_item_is_fast(const GemmItem& g) {
   return view_fast(g.A, g.M, g.K) && view_fast(g.B, g.K, g.N) && (!g.has_cin || view_plain(g.Cin, g.M, g.N)) &&
          (!g.has_sub || view_plain(g.Sub, g.M, g.N));

@@ -1115,6 +1115,201 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lp(GemmLaun
 }
 
 // ---------------------------------------------------------------------------
+// Split low-precision products with vectorised operand staging, for the
+// items of gemm_item_is_lp_vec (A and B stored untransposed, 16-byte aligned
+// rows of A, a triangular form on A only, a row permutation on B only, K a
+// multiple of 8).  Every thread stages runs of eight consecutive k: a run of
+// a row of A (two 16-byte loads) or of a column of B (eight loads, each
+// coalesced across the wavefront), splits them into parts and writes each
+// part as one 16-byte LDS store in the layout the MFMA reads (k contiguous
+// per row of A and per column of B).  Wavefronts own 64 x 64 output tiles
+// (16 MFMA blocks), which halves the LDS bytes read per product compared
+// with 32 x 32.  Parts and products as in k_gemm_lp.
+// ---------------------------------------------------------------------------
+template <int LP, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLaunch L) {
+  typedef LPT<LP> P;
+  typedef typename P::E E;
+  typedef typename P::V V;
+  constexpr int NP = P::PARTS;
+  constexpr int NWN = BN / WN, FM = WM / 16, FN = WN / 16;
+  constexpr int NT = (BM / WM) * NWN * 64, BK = 32, KP = BK + 8;
+  constexpr int ACH = BM * (BK / 8) / NT, BCH = BN * (BK / 8) / NT;  // runs of 8 per thread
+  static_assert(ACH * NT == BM * (BK / 8) && BCH * NT == BN * (BK / 8) && ACH >= 1 && BCH >= 1, "runs");
+  __shared__ __attribute__((aligned(16))) E As[2][NP][BM][KP];
+  __shared__ __attribute__((aligned(16))) E Bs[2][NP][BN][KP];
+  __shared__ int16_t s_perm[kMaxBlock];
+
+  GemmItem it;
+  int item, tile;
+  product_workgroup(item, tile);
+  if (!gemm_item<float, GEMM_EXPLICIT>(L, item, it)) return;
+  const int tiles_n = (it.N + BN - 1) / BN;
+  const int tiles_m = (it.M + BM - 1) / BM;
+  if (tile >= tiles_m * tiles_n) return;
+  int tm, tn;
+  heavy_first(it, tile, tiles_m, tiles_n, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int M = it.M, N = it.N, K = it.K;
+  int kb = 0, ke = K;
+  if (it.A.tri == 1) ke = min(ke, m0 + BM);
+  if (it.A.tri == 2) kb = max(kb, m0);
+  kb = (kb / BK) * BK;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / NWN, wn = wave % NWN;
+  const bool perm = it.B.rowperm != nullptr;
+  if (perm) {
+    for (int e = tid; e < K; e += NT) s_perm[e] = static_cast<int16_t>(it.B.rowperm[e]);
+    __syncthreads();
+  }
+  const float* Ap = static_cast<const float*>(it.A.p);
+  const float* Bp = static_cast<const float*>(it.B.p);
+  const int64_t lda = it.A.ld, ldb = it.B.ld;
+  const int atri = it.A.tri;
+
+  f4_t acc[FM][FN], accx[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[i][j][v] = 0.f;
+        accx[i][j][v] = 0.f;
+      }
+
+  // This thread's runs: A run q covers row ar(q) at k offsets ak(q) .. +7,
+  // B run q column bn(q) at k offsets bk(q) .. +7.
+  float ra[ACH][8], rb[BCH][8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < ACH; ++q) {
+      const int c = tid + q * NT, ar = c >> 2, ak = (c & 3) * 8;
+      const int64_t row = min(m0 + ar, M - 1);
+      const int k = min(k0 + ak, K - 8);
+      const float4 lo = *reinterpret_cast<const float4*>(Ap + row * lda + k);
+      const float4 hi = *reinterpret_cast<const float4*>(Ap + row * lda + k + 4);
+      ra[q][0] = lo.x; ra[q][1] = lo.y; ra[q][2] = lo.z; ra[q][3] = lo.w;
+      ra[q][4] = hi.x; ra[q][5] = hi.y; ra[q][6] = hi.z; ra[q][7] = hi.w;
+    }
+#pragma unroll
+    for (int q = 0; q < BCH; ++q) {
+      const int c = tid + q * NT, bn = c % BN, bk = (c / BN) * 8;
+      const int col = min(n0 + bn, N - 1);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int kk = min(k0 + bk + u, K - 1);
+        const int r = perm ? s_perm[kk] : kk;
+        rb[q][u] = gload(Bp + static_cast<int64_t>(r) * ldb + col);
+      }
+    }
+  };
+  bool out_of_range = false;
+  auto store = [&](int buf, int k0) {
+#pragma unroll
+    for (int q = 0; q < ACH; ++q) {
+      const int c = tid + q * NT, ar = c >> 2, ak = (c & 3) * 8;
+      const int x = m0 + ar;
+      V part[NP];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int y = k0 + ak + u;
+        float v = y < K ? ra[q][u] : 0.f;
+        if (atri == 1) v = x > y ? v : (x == y ? 1.f : 0.f);
+        if (atri == 2) v = x <= y ? v : 0.f;
+        if (LP == 1) out_of_range = out_of_range || !(fabsf(v) < 65504.0f);
+        E pv[NP];
+        P::split(v, pv);
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) part[pp][u] = pv[pp];
+      }
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp) *reinterpret_cast<V*>(&As[buf][pp][ar][ak]) = part[pp];
+    }
+#pragma unroll
+    for (int q = 0; q < BCH; ++q) {
+      const int c = tid + q * NT, bn = c % BN, bk = (c / BN) * 8;
+      V part[NP];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float v = k0 + bk + u < K ? rb[q][u] : 0.f;
+        if (LP == 1) out_of_range = out_of_range || !(fabsf(v) < 65504.0f);
+        E pv[NP];
+        P::split(v, pv);
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) part[pp][u] = pv[pp];
+      }
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp) *reinterpret_cast<V*>(&Bs[buf][pp][bn][bk]) = part[pp];
+    }
+  };
+
+  if (kb < ke) {
+    load(kb);
+    store(0, kb);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+      const bool more = k0 + BK < ke;
+      if (more) load(k0 + BK);
+      V bv[FN][NP];
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp)
+          bv[j][pp] = *reinterpret_cast<const V*>(&Bs[buf][pp][wn * WN + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        V a[NP];
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp)
+          a[pp] = *reinterpret_cast<const V*>(&As[buf][pp][wm * WM + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          if (LP == 1) {
+            acc[i][j] = P::mma(a[0], bv[j][0], acc[i][j]);
+            accx[i][j] = P::mma(a[0], bv[j][1], accx[i][j]);
+            accx[i][j] = P::mma(a[1], bv[j][0], accx[i][j]);
+          } else {
+            accx[i][j] = P::mma(a[1], bv[j][1], accx[i][j]);
+            accx[i][j] = P::mma(a[0], bv[j][NP - 1], accx[i][j]);
+            accx[i][j] = P::mma(a[NP - 1], bv[j][0], accx[i][j]);
+            acc[i][j] = P::mma(a[0], bv[j][1], acc[i][j]);
+            acc[i][j] = P::mma(a[1], bv[j][0], acc[i][j]);
+            acc[i][j] = P::mma(a[0], bv[j][0], acc[i][j]);
+          }
+        }
+      }
+      if (more) store(buf ^ 1, k0 + BK);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  if (LP == 1 && L.range_flag && __any(out_of_range) && lane == 0) atomicOr(L.range_flag, 1);
+  float* out = static_cast<float*>(it.out);
+  const float alpha = static_cast<float>(it.alpha), beta = static_cast<float>(it.beta);
+  const float xs = (LP == 1) ? (1.0f / 2048.0f) : 1.0f;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    float cv[FN][4], sv[FN][4];
+    epilogue_operands<float, FN>(it, m0 + wm * WM + i * 16, n0 + wn * WN, lane, cv, sv);
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wm * WM + i * 16 + MF<float>::row(lane, v);
+        const int c = n0 + wn * WN + j * 16 + (lane & 15);
+        float val = alpha * (acc[i][j][v] + accx[i][j][v] * xs);
+        if (it.has_cin) val += beta * cv[j][v];
+        if (it.has_sub) val -= sv[j][v];
+        if (r < M && c < N) gstore(out + static_cast<int64_t>(r) * it.ldo + c, val);
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Wave-wide argmax with DPP: the largest value, lowest index on ties (the
 // rule of LAPACK's idamax).  Every lane returns the wave's winner.
 // ---------------------------------------------------------------------------
@@ -2418,6 +2613,25 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
           } else {
             dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
             hipLaunchKernelGGL((k_gemm_dl<GEMM_EXPLICIT, 128, 128, 32, 32>), grid, dim3(1024), 0, st, L);
+          }
+          hipError_t e = hipGetLastError();
+          if (e != hipSuccess) return e;
+        }
+      } else {
+        // Split FP16 / BF16 products of float storage: the vectorised
+        // instance when every fast item qualifies (GemmLaunch::ndl).
+        if (L.lp != 0 && nfast > 0 && L.ndl == nfast) {
+          ndl = nfast;
+          const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * ndl;
+          if (L.lp == 1 && tiles256 >= 256) {
+            dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), ndl);
+            hipLaunchKernelGGL((k_gemm_lpv<1, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
+          } else if (L.lp == 1) {
+            dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
+            hipLaunchKernelGGL((k_gemm_lpv<1, 128, 128, 64, 64>), grid, dim3(256), 0, st, L);
+          } else {
+            dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
+            hipLaunchKernelGGL((k_gemm_lpv<2, 128, 128, 64, 64>), grid, dim3(256), 0, st, L);
           }
           hipError_t e = hipGetLastError();
           if (e != hipSuccess) return e;

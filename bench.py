@@ -524,12 +524,17 @@ def main() -> int:
             dt_ = torch.float32 if prec == "f32" else torch.float64
             Ms = [torch.from_numpy(m).to(dev, dt_) for m in mats]
             binfo = torch.zeros(len(probs), dtype=torch.int32, device=dev)
-            outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo, pivoting=PIV)
+            wsz = bri.batched_workspace_size([p.n for p in probs], ks, ii, jj, precision=prec, pivoting=PIV)
+            wsb = torch.empty(wsz, dtype=torch.uint8, device=dev)
+            # The first call captures the batch (plain precisions); the timed
+            # calls, with the same blocks and workspace, replay it.
+            outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo, pivoting=PIV, workspace=wsb)
             torch.cuda.synchronize()
             reps = 3
             t0 = time.perf_counter()
             for _ in range(reps):
-                outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo, pivoting=PIV)
+                outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo, pivoting=PIV, out=outs,
+                                                workspace=wsb)
             torch.cuda.synchronize()
             bms = (time.perf_counter() - t0) * 1e3 / reps
             err = max(rel_err(outs[t].double().cpu().numpy(), dense[t]) for t in sample)
@@ -537,7 +542,7 @@ def main() -> int:
                             "problems_per_s": len(probs) / (bms * 1e-3), "max_rel_error_sampled": err,
                             "info_nonzero": int((binfo != 0).sum().item()),
                             "refine_sweeps": bri.refine_last()[0] if prec.startswith("mixed") else 0})
-            del Ms, outs
+            del Ms, outs, wsb
         line["batched"] = {"workload": "512 problems, n ~ U[64,1024], k ~ U{2,3,4}, random block, Gaussian + n I, "
                                        "seeds SeedSequence(5).spawn(512); error vs dense inverse on every 32nd problem",
                            "algorithmic_flops": bflops, "runs": batched}

@@ -398,11 +398,27 @@ def invert_block_backward(M: torch.Tensor, k: int, i: int, j: int, G: torch.Tens
     return grad
 
 
+def batched_workspace_size(ns: Sequence[int], ks: Sequence[int], iis: Sequence[int], jjs: Sequence[int],
+                           precision: str = "f64", reuse: bool = False, pivoting: str = "auto") -> int:
+    """Workspace bytes of invert_block_batched for these problems (0 when invalid)."""
+    count = len(ns)
+    o = make_opts(precision, 0, reuse=reuse, pivoting=pivoting)
+    return int(lib().bri_batched_workspace_size(count, (ctypes.c_int64 * count)(*ns), (ctypes.c_int * count)(*ks),
+                                                (ctypes.c_int * count)(*iis), (ctypes.c_int * count)(*jjs),
+                                                ctypes.byref(o)))
+
+
 def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Sequence[int],
                          jjs: Sequence[int], precision: str = "f64", concurrency: int = 0,
                          info: Optional[torch.Tensor] = None, reuse: bool = False,
-                         factorization: str = "auto", pivoting: str = "auto") -> List[torch.Tensor]:
-    """One block per problem; all problems share one workspace and one call."""
+                         factorization: str = "auto", pivoting: str = "auto",
+                         out: Optional[Sequence[torch.Tensor]] = None,
+                         workspace: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
+    """One block per problem; all problems share one workspace and one call.
+
+    Passing the same ``out`` blocks and ``workspace`` again (with the same
+    matrices and targets) lets the library replay the batch it captured as a
+    HIP graph on the first call."""
     count = len(Ms)
     dtype = _DTYPE_OF[precision]
     for t, m in enumerate(Ms):
@@ -413,8 +429,17 @@ def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Seq
     kk = (ctypes.c_int * count)(*ks)
     ii = (ctypes.c_int * count)(*iis)
     jj = (ctypes.c_int * count)(*jjs)
-    outs = [torch.empty(block_size(m.shape[0], k), block_size(m.shape[0], k), dtype=dtype, device=dev)
-            for m, k in zip(Ms, ks)]
+    if out is None:
+        outs = [torch.empty(block_size(m.shape[0], k), block_size(m.shape[0], k), dtype=dtype, device=dev)
+                for m, k in zip(Ms, ks)]
+    else:
+        outs = list(out)
+        if len(outs) != count:
+            raise ValueError("out must hold one block per problem")
+        for t, (o_, m, k) in enumerate(zip(outs, Ms, ks)):
+            _require_gpu(o_, f"out[{t}]", dtype)
+            if o_.shape[0] < block_size(m.shape[0], k) or o_.shape[1] < block_size(m.shape[0], k):
+                raise ValueError(f"out[{t}] is smaller than its block")
     ldo = (ctypes.c_int64 * count)(*[o_.stride(0) for o_ in outs])
     mp = (ctypes.c_void_p * count)(*[m.data_ptr() for m in Ms])
     op = (ctypes.c_void_p * count)(*[o_.data_ptr() for o_ in outs])
@@ -422,7 +447,8 @@ def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Seq
     need = lib().bri_batched_workspace_size(count, n, kk, ii, jj, ctypes.byref(o))
     if need == 0 and count > 0:
         raise BriError(BRI_ERR_UNSUPPORTED, "invalid arguments")
-    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    ws = workspace if workspace is not None and workspace.numel() >= need else \
+        torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     o.workspace = ws.data_ptr()
     o.workspace_bytes = need
     o.d_info = info.data_ptr() if info is not None else None

@@ -160,7 +160,7 @@ inline bool gemm_item_is_direct(const GemmItem& g, int elem) {
          (g.B.rowperm == nullptr || g.K <= kMaxBlock) &&
          (!g.has_cin || view_plain(g.Cin, g.M, g.N)) && (!g.has_sub || view_plain(g.Sub, g.M, g.N));
 }
-// An item of the vectorised split low-precision instance (float storage,
+// An item of the vectorised split FP16 instance (float storage,
 // k_gemm_lpv): A stored untransposed with 16-byte aligned rows, unpermuted,
 // possibly triangular; B stored untransposed, untriangular, possibly with a
 // row permutation; K a multiple of 8 (runs of eight k never cross it) and at

@@ -19,8 +19,11 @@ hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, bool wide,
 // triangular inversion follows); needs LuItem::tmp (a b x b shadow) and
 // b = 32 * 2^m.  getrf_rec_applies() tells whether a launch of count
 // matrices of order b takes it.
+// lp: products of float matrices in split FP16 (1) or BF16 (2) parts, with
+// range_flag as in GemmLaunch; 0 for FP32 / FP64 products.
 template <typename T>
-hipError_t launch_getrf_rec(const LuItem* d_items, int count, int b, bool wide, hipStream_t st);
+hipError_t launch_getrf_rec(const LuItem* d_items, int count, int b, bool wide, int lp, int32_t* range_flag,
+                            hipStream_t st);
 template <typename T>
 // diag_inverted: the LU (tile pivoting) already left its diagonal 32 x 32 tiles inverted.
 hipError_t launch_trtri(const LuItem* d_items, int count, int b, bool diag_inverted, hipStream_t st);

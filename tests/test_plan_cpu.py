@@ -102,7 +102,12 @@ def test_auto_width_is_a_power_of_four():
     d = bri.plan_describe(4096, 4, 0, 0, "f64", 0)
     assert d["batch_width"] == 16
     d = bri.plan_describe(16384, 8, 0, 0, "f64", 0)
-    assert d["batch_width"] in (4, 16, 64)
+    assert d["batch_width"] == 256
+    # the estimated live workspace stays within 48 GiB
+    assert d["workspace_bytes"] <= 48 * 2**30
+    d = bri.plan_describe(32768, 8, 0, 0, "f64", 0)
+    assert d["batch_width"] == 64
+    assert d["workspace_bytes"] <= 48 * 2**30 + 2**28
 
 
 def test_flop_accounting():
@@ -382,16 +387,17 @@ def test_mixed_workspace_below_the_matrix_at_width_one():
 
 
 def test_tuning_cache_drives_the_lu_choice(tmp_path):
-    # A tuning cache entry for factorisation launches of 64 matrices of order
-    # 2048 overrides the built-in rule (which takes the recursive LU there):
-    # the plan's launch count changes accordingly; an empty cache restores it.
+    # Tuning cache entries for factorisation launches of up to 256 matrices of
+    # order 2048 override the built-in rule (which takes the recursive LU
+    # there): the plan's launch count changes accordingly; an empty cache
+    # restores it.
     n, k = 16384, 8
     auto = bri.plan_describe(n, k, 0, 0, "f64")["kernel_launches"]
     cache = tmp_path / "tune.txt"
-    lines = [f"lu {c} 2048 0" for c in (1, 2, 4, 8, 16, 32, 64)] + ["product 8 0 64 2048 2048 3"]
+    lines = [f"lu {c} 2048 0" for c in (1, 2, 4, 8, 16, 32, 64, 128, 256)] + ["product 8 0 256 2048 2048 3"]
     cache.write_text("# test\n" + "\n".join(lines) + "\n")
     try:
-        assert bri.tune_load(str(cache)) == 8
+        assert bri.tune_load(str(cache)) == 10
         tiled = bri.plan_describe(n, k, 0, 0, "f64")["kernel_launches"]
         forced = bri.plan_describe(n, k, 0, 0, "f64", factorization="tile")["kernel_launches"]
         assert tiled == forced and tiled != auto

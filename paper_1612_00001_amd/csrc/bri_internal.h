@@ -312,8 +312,9 @@ int tuned_product_shape(int elem, int tri, int count, int m, int n);
 // Overrides for the autotuner's timing runs (-1: none), per host thread.
 extern thread_local int g_force_shape;
 extern thread_local int g_force_lu;
-// Tile shapes of the FP64 explicit products that the autotuner chooses from.
-constexpr int kShapeDl128 = 1, kShapeDl64 = 2, kShapeDl256 = 3;
+// Tile shapes of the FP64 explicit products that the autotuner chooses from:
+// 128 x 128, 64 x 64, 256 x 128 and 128 x 256 (rows x columns).
+constexpr int kShapeDl128 = 1, kShapeDl64 = 2, kShapeDl256 = 3, kShapeDl128w = 4;
 
 inline LuKind lu_kind(int count, int b, bool panel_pivoting, bool uniform, int choice) {
   if (panel_pivoting) return LU_PANEL;

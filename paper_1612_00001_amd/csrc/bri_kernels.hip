@@ -2634,21 +2634,26 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
         if (nfast > 0 && L.ndl == nfast && tier != kTierTiny) {
           // 128 x 128 tiles of 16 wavefronts of 32 x 32 for the two larger
           // shapes, 64 x 64 tiles of 4 wavefronts of 32 x 32 for the small
-          // one; launches of at least 512 tiles of 256 x 128 (full products,
-          // or triangular ones with K >= 2048) take 256 x 128 tiles of 8
-          // wavefronts of 64 x 64, which read a quarter fewer operand bytes per
-          // flop (the shape the autotuner picks on the MI355X in every such
-          // case it measures).
+          // one; launches of at least 512 tiles of 256 x 128 take tiles of 8
+          // wavefronts of 64 x 64, which read a quarter fewer operand bytes
+          // per flop: 256 x 128 for full products, 128 x 256 for triangular
+          // ones (the triangular operand is always A here, and a tile's K
+          // range ends with its last row: half the overhang past the
+          // diagonal).  These are the shapes the autotuner picks on the
+          // MI355X in every such case it measures.
           ndl = nfast;
           int shape = tier == kTierSmall ? kShapeDl64 : kShapeDl128;
           const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * ndl;
-          if (tier != kTierSmall && tiles256 >= 512 && (L.tri == 0 || min(max_m, max_n) >= 2048)) shape = kShapeDl256;
+          if (tier != kTierSmall && tiles256 >= 512) shape = L.tri == 0 ? kShapeDl256 : kShapeDl128w;
           const int tuned = tuned_product_shape(8, L.tri, ndl, max_m, max_n);
-          if (tuned == kShapeDl64 || tuned == kShapeDl128 || tuned == kShapeDl256) shape = tuned;
-          if (g_force_shape >= kShapeDl128 && g_force_shape <= kShapeDl256) shape = g_force_shape;
+          if (tuned >= kShapeDl128 && tuned <= kShapeDl128w) shape = tuned;
+          if (g_force_shape >= kShapeDl128 && g_force_shape <= kShapeDl128w) shape = g_force_shape;
           if (shape == kShapeDl64) {
             dim3 grid(cdiv(max_m, 64) * cdiv(max_n, 64), ndl);
             hipLaunchKernelGGL((k_gemm_dl<GEMM_EXPLICIT, 64, 64, 32, 32>), grid, dim3(256), 0, st, L);
+          } else if (shape == kShapeDl128w) {
+            dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 256), ndl);
+            hipLaunchKernelGGL((k_gemm_dl<GEMM_EXPLICIT, 128, 256, 64, 64>), grid, dim3(512), 0, st, L);
           } else if (shape == kShapeDl256) {
             dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), ndl);
             hipLaunchKernelGGL((k_gemm_dl<GEMM_EXPLICIT, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);

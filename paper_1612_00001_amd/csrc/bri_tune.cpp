@@ -210,7 +210,7 @@ int bri_autotune(const bri_opts* o, const char* path) {
         L.tri = tri;
         int best = -1;
         double best_ms = 0.0;
-        for (int shape : {kShapeDl128, kShapeDl64, kShapeDl256}) {
+        for (int shape : {kShapeDl128, kShapeDl64, kShapeDl256, kShapeDl128w}) {
           g_force_shape = shape;
           const double ms = time_ms(st, 3, [&] { return launch_gemm<double>(L, s, s, st); }, [] {});
           g_force_shape = -1;

@@ -125,6 +125,9 @@ struct GemmLaunch {
                         // the direct-to-LDS FP64 instance (gemm_item_is_direct)
   int32_t* range_flag;  // FP16 split products: set to 1 when an operand value lies
                         // outside the FP16 range (or is not finite); may be null
+  int32_t part;         // recursive LU modes: 0 = every part of each node (count =
+                        // matrices x parts), 1 / 2 = only the first / second part
+                        // (count = matrices)
 };
 
 constexpr int kMaxBlock = 4096;  // == BRI_MAX_BLOCK

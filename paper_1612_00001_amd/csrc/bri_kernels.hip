@@ -171,8 +171,9 @@ __device__ bool gemm_item(const GemmLaunch& L, int idx, GemmItem& it) {
     // the first half is done, likewise (2,2); the shadow sh (b x b, same
     // coordinates) holds the node's intermediate blocks at their positions.
     constexpr int P = MODE == GEMM_RLU_D ? 1 : 2;
-    const int part = idx % P;
-    const LuItem lu = static_cast<const LuItem*>(L.items)[idx / P];
+    const int np = L.part ? 1 : P;
+    const int part = L.part ? L.part - 1 : idx % P;
+    const LuItem lu = static_cast<const LuItem*>(L.items)[idx / np];
     const int b = lu.b, o = L.j, h = L.s;
     if (o + 2 * h > b) return false;
     char* a = static_cast<char*>(lu.a);
@@ -2595,11 +2596,32 @@ hipError_t launch_gemm_rlu(const GemmLaunch& L, int max_m, int max_n, hipStream_
     }
     if (tier != kTierTiny) {
       // Halves of order >= 1024 in launches of >= 512 tiles of 256 x 128:
-      // the 256 x 128 shape, as for the explicit products.
+      // tiles of 8 wavefronts of 64 x 64, as for the explicit products, one
+      // launch per part of the node: 128 x 256 for the part whose triangular
+      // operand is A (its K range ends with the tile's last row, so the
+      // shorter side sits on the diagonal), 256 x 128 for the other (a full
+      // product, or a triangular B whose K range follows the columns).
+      // (n = 16384, k = 8: -1.9 ms per factorisation launch group at h =
+      // 1024; at h = 512 the two launches took 8% longer than one of 128 x
+      // 128 tiles.)
       const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * L.count;
       if (max_m >= 1024 && max_n >= 1024 && tiles256 >= 512) {
-        dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), L.count);
-        hipLaunchKernelGGL((k_gemm_dl<MODE, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
+        if constexpr (MODE == GEMM_RLU_D) {
+          dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), L.count);
+          hipLaunchKernelGGL((k_gemm_dl<MODE, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
+        } else {
+          // Part with the triangular A: the first for A (L11^{-1} P1 A12)
+          // and C (L22^{-1} P2 L21), the second for B (U11^{-1} U12).
+          constexpr int tri_a = MODE == GEMM_RLU_B ? 2 : 1;
+          GemmLaunch F = L;
+          F.count = L.count / 2;
+          F.part = tri_a;
+          dim3 gw(cdiv(max_m, 128) * cdiv(max_n, 256), F.count);
+          hipLaunchKernelGGL((k_gemm_dl<MODE, 128, 256, 64, 64>), gw, dim3(512), 0, st, F);
+          F.part = 3 - tri_a;
+          dim3 gt(cdiv(max_m, 256) * cdiv(max_n, 128), F.count);
+          hipLaunchKernelGGL((k_gemm_dl<MODE, 256, 128, 64, 64>), gt, dim3(512), 0, st, F);
+        }
         return hipGetLastError();
       }
       dim3 grid(cdiv(max_m, 128) * cdiv(max_n, 128), L.count);

@@ -494,11 +494,13 @@ def invert_blocks(M: torch.Tensor, k: int, blocks: Optional[Sequence[tuple]] = N
 
 def gemm(A: Sequence[torch.Tensor], B: Sequence[torch.Tensor], C: Sequence[torch.Tensor],
          alpha: float = 1.0, beta: float = 0.0, workspace: Optional[torch.Tensor] = None,
-         products: Optional[str] = None) -> None:
+         products: Optional[str] = None, split_bytes: int = 0) -> None:
     """C[t] = beta C[t] + alpha A[t] B[t] on the library's MFMA product kernel (in place on C).
 
     ``products`` (float operands only): None or "f32" for FP32 MFMA, "f16" or
-    "bf16" for the split low-precision MFMA products of the mixed paths."""
+    "bf16" for the split low-precision MFMA products of the mixed paths.
+    ``split_bytes`` (FP16 products): scratch for operands split once before
+    the products (see bri_gemm in include/bri.h), appended to the workspace."""
     count = len(A)
     if count == 0:
         return
@@ -514,7 +516,7 @@ def gemm(A: Sequence[torch.Tensor], B: Sequence[torch.Tensor], C: Sequence[torch
     m, kk = A[0].shape
     n = B[0].shape[1]
     o = make_opts(prec)
-    need = lib().bri_gemm_workspace_size(count)
+    need = lib().bri_gemm_workspace_size(count) + int(split_bytes)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=A[0].device)
     o.workspace = workspace.data_ptr()

@@ -226,8 +226,10 @@ struct ExecCfg {
   int lp = 0;           // float products: 0 FP32 MFMA, 1 FP16 split, 2 BF16 split
   bool wide = false;    // tile factorisations of float matrices in double
   int32_t* range_flag = nullptr;  // FP16 split products: operand outside the FP16 range
+  char* split = nullptr;          // FP16 split products: scratch for operands split once
+  size_t split_bytes = 0;
 };
-ExecCfg cfg_of(const Ctx& c) { return ExecCfg{c.pivoting, c.lu, c.lp, c.wide, nullptr}; }
+ExecCfg cfg_of(const Ctx& c) { return ExecCfg{c.pivoting, c.lu, c.lp, c.wide, nullptr, nullptr, 0}; }
 
 DView zero_view() {
   DView v;
@@ -587,6 +589,8 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, const ExecCfg& cfg, h
         L.lp = lp;
         L.tri = (s.kind == ST_TRMM_L || s.kind == ST_TRMM_U) ? 1 : 0;
         L.range_flag = cfg.range_flag;
+        L.split = cfg.split;
+        L.split_bytes = static_cast<int64_t>(cfg.split_bytes);
         e = launch_gemm<T>(L, bmax, bmax, st);
         break;
       }
@@ -911,15 +915,20 @@ int run_merged(const MergedExec& ex, const ExecCfg& cfg, hipStream_t st) {
     return BRI_OK;
   }
   // The groups touch disjoint parts of the workspace (each problem its own
-  // region and status word, each group its own descriptors): they run side
-  // by side on the helper streams, forked from and joined into st.
+  // region and status word, each group its own descriptors, each stream its
+  // own share of the split scratch): they run side by side on the helper
+  // streams, forked from and joined into st.
   std::lock_guard<std::mutex> lk(gs->mu);
   if (hipEventRecord(gs->fork, st) != hipSuccess) return BRI_ERR_HIP;
   const size_t ns = std::min<size_t>(GroupStreams::kStreams, ex.groups.size());
   for (size_t q = 0; q < ns; ++q)
     if (hipStreamWaitEvent(gs->stream[q], gs->fork, 0) != hipSuccess) return BRI_ERR_HIP;
+  const size_t share = cfg.split ? cfg.split_bytes / ns / kAlign * kAlign : 0;
   for (size_t g = 0; g < ex.groups.size(); ++g) {
-    const int rc = run_exec<T>(ex.groups[g], ex.bmax[g], cfg, gs->stream[g % ns]);
+    ExecCfg gc = cfg;
+    gc.split = cfg.split ? cfg.split + share * (g % ns) : nullptr;
+    gc.split_bytes = share;
+    const int rc = run_exec<T>(ex.groups[g], ex.bmax[g], gc, gs->stream[g % ns]);
     if (rc != BRI_OK) return rc;
   }
   for (size_t q = 0; q < ns; ++q) {
@@ -1099,8 +1108,32 @@ struct MixedBatch {
   std::vector<size_t> region;
   MergedLayout col, sol;
   size_t info_off = 0, flag_off = 0, scal_off = 0, items_off = 0, gemm_off = 0, load_off = 0, col_off = 0, sol_off = 0;
+  size_t split_off = 0, split_bytes = 0;
   size_t desc_bytes = 0, total = 0;
 };
+
+// Scratch of the split FP16 products (mixed FP16 only): room for the split
+// operands of the largest explicit product step of the merged plans, at
+// most kSplitCap bytes (larger steps run in parts).
+constexpr size_t kSplitCap = size_t(2) << 30;
+size_t split_scratch_bytes(const std::vector<const Plan*>& plans, const MergedLayout& m, int precision) {
+  if (precision != BRI_MIXED_F16) return 0;
+  int bmax = 0;
+  for (const Plan* p : plans) bmax = std::max(bmax, p->b);
+  size_t items = 0;
+  for (const std::vector<int>& g : m.groups) {
+    const Plan& p0 = *plans[g[0]];
+    for (size_t si = 0; si < p0.steps.size(); ++si) {
+      const StepKind kd = p0.steps[si].kind;
+      if (kd == ST_LOAD || kd == ST_GETRF || kd == ST_TRTRI) continue;
+      size_t n = 0;
+      for (int t : g) n += plans[t]->steps[si].items.size();
+      items = std::max(items, n);
+    }
+  }
+  const size_t per = static_cast<size_t>(split_item_bytes(bmax, bmax, split_pitch(bmax)));
+  return align_up(std::min(kSplitCap, items * per));
+}
 
 MixedBatch make_mixed_batch(int count, const int64_t* n, const int* k, const int* j, const bri_opts* o,
                             bool merged_width_rule) {
@@ -1141,6 +1174,12 @@ MixedBatch make_mixed_batch(int count, const int64_t* n, const int* k, const int
   mb.sol_off = off;
   off += mb.sol.bytes;
   mb.desc_bytes = off - d0;
+  // Split scratch last, within a sixteenth of the rest (so that narrow
+  // widths under a memory budget stay lean; larger steps run in parts).
+  const size_t want = std::max(split_scratch_bytes(pc, mb.col, o->precision), split_scratch_bytes(ps, mb.sol, o->precision));
+  mb.split_off = off;
+  mb.split_bytes = std::min(want, off / 16 / kAlign * kAlign);
+  off += mb.split_bytes;
   mb.total = off;
   return mb;
 }
@@ -1277,7 +1316,8 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
   // call then starts again with the BF16 split products (same exponent range
   // as FP32), found at the first sweep's synchronisation.
   int32_t* range_flag = reinterpret_cast<int32_t*>(ws + mb.flag_off);
-  ExecCfg mcfg{o->pivoting, o->factorization, lp_of(o->precision), true, range_flag};
+  ExecCfg mcfg{o->pivoting, o->factorization, lp_of(o->precision), true, range_flag,
+               mb.split_bytes ? ws + mb.split_off : nullptr, mb.split_bytes};
   t_last_range_fallback = 0;
   std::vector<char> conv;
   std::vector<double> prev;
@@ -2099,6 +2139,18 @@ int bri_gemm(int count, int64_t m, int64_t n, int64_t kk, double alpha, const vo
   L.items = o->workspace;
   L.count = count;
   L.w = count;  // plain dense operands: all items take the fast instance
+  if (L.lp == 1) {
+    // Split FP16 products: the vectorised instance when every item
+    // qualifies, and workspace beyond the descriptors as split scratch.
+    bool vec = true;
+    for (const GemmItem& g : items) vec = vec && gemm_item_is_lp_vec(g);
+    L.ndl = vec ? count : 0;
+    L.max_k = static_cast<int32_t>(kk);
+    if (vec && o->workspace_bytes > need) {
+      L.split = static_cast<char*>(o->workspace) + need;
+      L.split_bytes = static_cast<int64_t>(o->workspace_bytes - need);
+    }
+  }
   const hipError_t e = L.elem == 8 ? launch_gemm<double>(L, static_cast<int>(m), static_cast<int>(n), o->stream)
                                    : launch_gemm<float>(L, static_cast<int>(m), static_cast<int>(n), o->stream);
   return e == hipSuccess ? BRI_OK : BRI_ERR_HIP;

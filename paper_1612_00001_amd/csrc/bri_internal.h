@@ -128,7 +128,21 @@ struct GemmLaunch {
   int32_t part;         // recursive LU modes: 0 = every part of each node (count =
                         // matrices x parts), 1 / 2 = only the first / second part
                         // (count = matrices)
+  // FP16 split products of float storage (GEMM_EXPLICIT): scratch for the
+  // operands split once before the product (split_item_bytes per item), or
+  // null; the launch then takes as many items at a time as it holds.
+  void* split;
+  int64_t split_bytes;
+  int32_t max_k;                       // largest inner order K of the items (0: at most
+                                       // max(max_m, max_n), as for block products)
+  int32_t split_kp, split_m, split_n;  // set by the launch: K pitch, A rows, B columns
 };
+
+// Bytes of one item's pre-split FP16 operands: high and low planes of A
+// (m rows) and of B transposed (n rows), kp elements per row.
+constexpr int64_t split_item_bytes(int m, int n, int kp) { return 4 * static_cast<int64_t>(m + n) * kp; }
+// The K pitch of the split operands of products of inner order up to k.
+constexpr int split_pitch(int k) { return (k + 63) / 64 * 64; }
 
 constexpr int kMaxBlock = 4096;  // == BRI_MAX_BLOCK
 

@@ -1323,6 +1323,247 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLau
 }
 
 // ---------------------------------------------------------------------------
+// Split FP16 products from operands split once (mixed FP16 path, large
+// launches of explicit items).  k_split16 converts every item's operands:
+// A (M x K) into FP16 high and low planes with K contiguous per row, B
+// (K x N) into the planes of its transpose (K contiguous per column), the
+// triangular form of A applied, K zero-padded to the pitch kp; x = hi +
+// lo 2^-11 as in LPT<1>, with the FP16 range check.  k_gemm_h16 then moves
+// those planes into LDS with direct loads and runs the three FP16 products
+// per K step with no conversion in its loop.  In k_gemm_lpv every output
+// tile converts its own operand panels, so an element of A is converted
+// once per tile column and one of B once per tile row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_split16(GemmLaunch L) {
+  __shared__ float tb[64][65];
+  const GemmItem it = static_cast<const GemmItem*>(L.items)[blockIdx.y];
+  const int kp = L.split_kp, kt = kp / 64;
+  _Float16* ah = reinterpret_cast<_Float16*>(static_cast<char*>(L.split) +
+                                             blockIdx.y * split_item_bytes(L.split_m, L.split_n, kp));
+  _Float16* al = ah + static_cast<int64_t>(L.split_m) * kp;
+  _Float16* bh = al + static_cast<int64_t>(L.split_m) * kp;
+  _Float16* bl = bh + static_cast<int64_t>(L.split_n) * kp;
+  const int tid = threadIdx.x;
+  const int ta = (L.split_m + 63) / 64 * kt;
+  bool bad = false;
+  int t = blockIdx.x;
+  if (t < ta) {
+    // A: rows r0 .. r0 + 63, k0 .. k0 + 63; a thread converts runs of 8 k.
+    const int r0 = (t / kt) * 64, k0 = (t % kt) * 64;
+    if (r0 >= it.M) return;
+    const float* Ap = static_cast<const float*>(it.A.p);
+    const int64_t lda = it.A.ld;
+    const int atri = it.A.tri;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int run = tid + q * 256, x = r0 + (run >> 3), y0 = k0 + 8 * (run & 7);
+      if (x >= it.M) continue;
+      float v[8];
+      if (y0 < it.K) {  // K is a multiple of 8: the run is stored entirely
+        const float4 p0 = *reinterpret_cast<const float4*>(Ap + x * lda + y0);
+        const float4 p1 = *reinterpret_cast<const float4*>(Ap + x * lda + y0 + 4);
+        v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
+        v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = 0.f;
+      }
+      h8_t hv, lv;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int y = y0 + u;
+        float a = y < it.K ? v[u] : 0.f;
+        if (atri == 1) a = x > y ? a : (x == y && y < it.K ? 1.f : 0.f);
+        if (atri == 2) a = x <= y ? a : 0.f;
+        bad = bad || !(fabsf(a) < 65504.0f);
+        _Float16 pv[2];
+        LPT<1>::split(a, pv);
+        hv[u] = pv[0];
+        lv[u] = pv[1];
+      }
+      *reinterpret_cast<h8_t*>(ah + static_cast<int64_t>(x) * kp + y0) = hv;
+      *reinterpret_cast<h8_t*>(al + static_cast<int64_t>(x) * kp + y0) = lv;
+    }
+  } else {
+    // B: columns n0 .. n0 + 63, k0 .. k0 + 63, transposed through LDS.
+    t -= ta;
+    const int n0 = (t / kt) * 64, k0 = (t % kt) * 64;
+    if (n0 >= it.N) return;
+    const float* Bp = static_cast<const float*>(it.B.p);
+    const int64_t ldb = it.B.ld;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int kr = (tid >> 6) + 4 * u, y = n0 + (tid & 63), k = k0 + kr;
+      float v = 0.f;
+      if (k < it.K && y < it.N) {
+        const int row = it.B.rowperm ? it.B.rowperm[k] : k;
+        v = Bp[static_cast<int64_t>(row) * ldb + y];
+      }
+      tb[kr][tid & 63] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int run = tid + q * 256, nr = run >> 3, c = run & 7, y = n0 + nr;
+      if (y >= it.N) continue;
+      h8_t hv, lv;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float b = tb[8 * c + u][nr];
+        bad = bad || !(fabsf(b) < 65504.0f);
+        _Float16 pv[2];
+        LPT<1>::split(b, pv);
+        hv[u] = pv[0];
+        lv[u] = pv[1];
+      }
+      *reinterpret_cast<h8_t*>(bh + static_cast<int64_t>(y) * kp + k0 + 8 * c) = hv;
+      *reinterpret_cast<h8_t*>(bl + static_cast<int64_t>(y) * kp + k0 + 8 * c) = lv;
+    }
+  }
+  if (L.range_flag && __any(bad) && (tid & 63) == 0) atomicOr(L.range_flag, 1);
+}
+
+// Products of the split planes: BM x BN tiles of 64 x 64 wavefronts, K in
+// steps of 32 (one MFMA K step) through three LDS buffers, loaded directly
+// (16-byte pieces, eight k of one row of one plane) with the pipeline of
+// k_gemm_dl.  LDS piece (plane, row r, slot s) holds k chunk s ^ ((r >> 2) & 3)
+// of that row, so that the 16 rows a quarter-wavefront reads at one chunk
+// fall in distinct banks.  Epilogue as in k_gemm_lpv.
+template <int BM, int BN>
+__global__ __launch_bounds__((BM / 64) * (BN / 64) * 64) void k_gemm_h16(GemmLaunch L) {
+  constexpr int WM = 64, WN = 64, NWN = BN / WN, FM = WM / 16, FN = WN / 16;
+  constexpr int NT = (BM / WM) * NWN * 64, BK = 32;
+  constexpr int AC = 2 * BM * 4, BC = 2 * BN * 4;  // 16-byte pieces per K step (2 planes, 4 per row)
+  constexpr int AI = AC / NT, BI = BC / NT;
+  static_assert(AI * NT == AC && BI * NT == BC && AI >= 1 && BI >= 1, "tile/thread mismatch");
+  static_assert(AI + BI < 16, "outstanding loads per K step must fit the vmcnt field");
+  __shared__ __attribute__((aligned(16))) _Float16 sA0[2 * BM * BK], sA1[2 * BM * BK], sA2[2 * BM * BK];
+  __shared__ __attribute__((aligned(16))) _Float16 sB0[2 * BN * BK], sB1[2 * BN * BK], sB2[2 * BN * BK];
+
+  GemmItem it;
+  int item, tile;
+  product_workgroup(item, tile);
+  it = static_cast<const GemmItem*>(L.items)[item];
+  const int tiles_n = (it.N + BN - 1) / BN;
+  const int tiles_m = (it.M + BM - 1) / BM;
+  if (tile >= tiles_m * tiles_n) return;
+  int tm, tn;
+  heavy_first(it, tile, tiles_m, tiles_n, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int kp = L.split_kp;
+  int kb = 0, ke = min(it.K, kp);
+  if (it.A.tri == 1) ke = min(ke, m0 + BM);
+  if (it.A.tri == 2) kb = max(kb, m0);
+  kb = (kb / BK) * BK;
+
+  const _Float16* ah = reinterpret_cast<const _Float16*>(static_cast<const char*>(L.split) +
+                                                         item * split_item_bytes(L.split_m, L.split_n, kp));
+  const _Float16* bh = ah + 2 * static_cast<int64_t>(L.split_m) * kp;
+  const int64_t aplane = static_cast<int64_t>(L.split_m) * kp, bplane = static_cast<int64_t>(L.split_n) * kp;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / NWN, wn = wave % NWN;
+
+  f4_t acc[FM][FN], accx[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[i][j][v] = 0.f;
+        accx[i][j][v] = 0.f;
+      }
+
+  const int nk = kb < ke ? (ke - kb + BK - 1) / BK : 0;
+  if (nk > 0) {
+    // Loads of K step t into (dA, dB); steps past the last repeat the last
+    // one (into a buffer no later step reads).  Piece P of a step: plane
+    // P / (4 rows), row (P % (4 rows)) / 4, slot P % 4 (rows clamped into
+    // the product).
+    auto issue = [&](int t, _Float16* dA, _Float16* dB) {
+      const int k0 = kb + min(t, nk - 1) * BK;
+#pragma unroll
+      for (int q = 0; q < AI; ++q) {
+        const int P = q * NT + tid, pl = P / (BM * 4), rem = P % (BM * 4), r = rem >> 2;
+        const int c = (rem & 3) ^ ((r >> 2) & 3);
+        const _Float16* src = ah + pl * aplane + static_cast<int64_t>(min(m0 + r, it.M - 1)) * kp + k0 + 8 * c;
+        __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t*)(dA + (q * NT + wave * 64) * 8), 16, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < BI; ++q) {
+        const int P = q * NT + tid, pl = P / (BN * 4), rem = P % (BN * 4), r = rem >> 2;
+        const int c = (rem & 3) ^ ((r >> 2) & 3);
+        const _Float16* src = bh + pl * bplane + static_cast<int64_t>(min(n0 + r, it.N - 1)) * kp + k0 + 8 * c;
+        __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t*)(dB + (q * NT + wave * 64) * 8), 16, 0, 0);
+      }
+    };
+    // Fragment reads: lane l takes row (l & 15) of a 16-row block and k
+    // chunk l >> 4 (8 halves), for A and for B transposed alike.
+    const int li = lane & 15, kc = lane >> 4;
+    auto compute = [&](const _Float16* a_s, const _Float16* b_s) {
+      h8_t bv[FN][2];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int r = wn * WN + j * 16 + li;
+        const int off = r * BK + 8 * (kc ^ ((r >> 2) & 3));
+        bv[j][0] = *reinterpret_cast<const h8_t*>(b_s + off);
+        bv[j][1] = *reinterpret_cast<const h8_t*>(b_s + BN * BK + off);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int r = wm * WM + i * 16 + li;
+        const int off = r * BK + 8 * (kc ^ ((r >> 2) & 3));
+        const h8_t a0 = *reinterpret_cast<const h8_t*>(a_s + off);
+        const h8_t a1 = *reinterpret_cast<const h8_t*>(a_s + BM * BK + off);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acc[i][j] = LPT<1>::mma(a0, bv[j][0], acc[i][j]);
+          accx[i][j] = LPT<1>::mma(a0, bv[j][1], accx[i][j]);
+          accx[i][j] = LPT<1>::mma(a1, bv[j][0], accx[i][j]);
+        }
+      }
+    };
+    // Step t (see k_gemm_dl): after the wait this thread's pieces of step t
+    // have landed, the barrier makes that true for all and ends every read
+    // of the buffer that then receives step t + 2.
+    auto step = [&](int t, _Float16* ra, _Float16* rb, _Float16* wa, _Float16* wb) {
+      lds_barrier<0x0070 | (AI + BI)>();
+      issue(t + 2, wa, wb);
+      if (t < nk) compute(ra, rb);
+    };
+    issue(0, sA0, sB0);
+    issue(1, sA1, sB1);
+    for (int t = 0; t < nk; t += 3) {
+      step(t, sA0, sB0, sA2, sB2);
+      step(t + 1, sA1, sB1, sA0, sB0);
+      step(t + 2, sA2, sB2, sA1, sB1);
+    }
+    wait_vmcnt<0>();  // no load into LDS may be in flight when the workgroup ends
+  }
+
+  float* out = static_cast<float*>(it.out);
+  const float alpha = static_cast<float>(it.alpha), beta = static_cast<float>(it.beta);
+  constexpr float xs = 1.0f / 2048.0f;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    float cv[FN][4], sv[FN][4];
+    epilogue_operands<float, FN>(it, m0 + wm * WM + i * 16, n0 + wn * WN, lane, cv, sv);
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wm * WM + i * 16 + MF<float>::row(lane, v);
+        const int c = n0 + wn * WN + j * 16 + (lane & 15);
+        float val = alpha * (acc[i][j][v] + accx[i][j][v] * xs);
+        if (it.has_cin) val += beta * cv[j][v];
+        if (it.has_sub) val -= sv[j][v];
+        if (r < it.M && c < it.N) gstore(out + static_cast<int64_t>(r) * it.ldo + c, val);
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Wave-wide argmax with DPP: the largest value, lowest index on ties (the
 // rule of LAPACK's idamax).  Every lane returns the wave's winner.
 // ---------------------------------------------------------------------------
@@ -2695,8 +2936,29 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
         const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * nfast;
         if (L.lp == 1 && nfast > 0 && L.ndl == nfast && tiles256 >= 256) {
           ndl = nfast;
-          dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), ndl);
-          hipLaunchKernelGGL((k_gemm_lpv<1, GEMM_EXPLICIT, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
+          // With split scratch: the operands split once (k_split16), then
+          // the products of the planes (k_gemm_h16), as many items at a time
+          // as the scratch holds.
+          const int kp = split_pitch(max(L.max_k, max(max_m, max_n)));
+          const int64_t per = split_item_bytes(max_m, max_n, kp);
+          const int chunk = L.split ? static_cast<int>(std::min<int64_t>(ndl, L.split_bytes / per)) : 0;
+          if (chunk > 0) {
+            for (int c0 = 0; c0 < ndl; c0 += chunk) {
+              GemmLaunch S = L;
+              S.items = static_cast<const GemmItem*>(L.items) + c0;
+              S.split_kp = kp;
+              S.split_m = max_m;
+              S.split_n = max_n;
+              const int cn = min(chunk, ndl - c0);
+              dim3 gs((cdiv(max_m, 64) + cdiv(max_n, 64)) * (kp / 64), cn);
+              hipLaunchKernelGGL(k_split16, gs, dim3(256), 0, st, S);
+              dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), cn);
+              hipLaunchKernelGGL((k_gemm_h16<256, 128>), grid, dim3(512), 0, st, S);
+            }
+          } else {
+            dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), ndl);
+            hipLaunchKernelGGL((k_gemm_lpv<1, GEMM_EXPLICIT, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
+          }
           hipError_t e = hipGetLastError();
           if (e != hipSuccess) return e;
         }

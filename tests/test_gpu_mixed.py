@@ -56,6 +56,40 @@ def test_split_product_gemm(products, m, n, kk):
     assert err <= 2.0 ** -20 * scale / np.sqrt(kk) * 8
 
 
+@pytest.mark.parametrize("count,m,n,kk,chunk", [(2, 2048, 2048, 2048, 2), (10, 1000, 776, 1000, 3),
+                                                 (300, 64, 136, 200, 64)])
+def test_split_once_products(count, m, n, kk, chunk):
+    # FP16 split products of launches with at least 256 output tiles of
+    # 256 x 128: operands split once into scratch (chunk items at a time),
+    # then the products of the split planes; against the FP64 product of the
+    # float operands, and against the same launch without scratch (operands
+    # split inside the product kernel).
+    rng = np.random.default_rng(7 * count + m + n + kk)
+    a = [rng.standard_normal((m, kk)).astype(np.float32) for _ in range(count)]
+    b = [rng.standard_normal((kk, n)).astype(np.float32) for _ in range(count)]
+    c0 = [rng.standard_normal((m, n)).astype(np.float32) for _ in range(count)]
+    kp = (kk + 63) // 64 * 64
+    per = 4 * (m + n) * kp
+    A = [gpu(x, torch.float32) for x in a]
+    B = [gpu(x, torch.float32) for x in b]
+    C1 = [gpu(x, torch.float32) for x in c0]
+    C2 = [gpu(x, torch.float32) for x in c0]
+    print(f"split once: {count} x {m}x{n}x{kk}, {chunk} items per part", flush=True)
+    bri.gemm(A, B, C1, alpha=-1.0, beta=1.0, products="f16", split_bytes=chunk * per)
+    bri.gemm(A, B, C2, alpha=-1.0, beta=1.0, products="f16")
+    torch.cuda.synchronize()
+    worst = 0.0
+    for t in range(count):
+        want = c0[t].astype(np.float64) - a[t].astype(np.float64) @ b[t].astype(np.float64)
+        got = C1[t].double().cpu().numpy()
+        scale = np.abs(a[t]).max() * np.abs(b[t]).max() * kk
+        err = np.abs(got - want).max()
+        worst = max(worst, err / scale)
+        assert err <= 2.0 ** -20 * scale / np.sqrt(kk) * 8
+        assert np.abs(got - C2[t].double().cpu().numpy()).max() <= 2.0 ** -20 * scale / np.sqrt(kk)
+    print(f"  worst err / (max|a| max|b| kk) = {worst:.2e}", flush=True)
+
+
 def run_mixed(m, k, i, j, precision, iters=10, tol=1e-12):
     info = torch.zeros(1, dtype=torch.int32, device=DEV)
     out = bri.invert_block(gpu(m), k, i, j, precision=precision, info=info, refine_max_iters=iters,

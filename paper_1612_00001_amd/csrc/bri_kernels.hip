@@ -1334,6 +1334,10 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLau
 // tile converts its own operand panels, so an element of A is converted
 // once per tile column and one of B once per tile row.
 // ---------------------------------------------------------------------------
+// Row tile of the k_gemm_h16 launches: for a triangular A, the split pass
+// skips the 64 x 64 tiles outside the K range of their row tile.
+constexpr int kH16TileM = 256;
+
 __global__ __launch_bounds__(256) void k_split16(GemmLaunch L) {
   __shared__ float tb[64][65];
   const GemmItem it = static_cast<const GemmItem*>(L.items)[blockIdx.y];
@@ -1351,6 +1355,8 @@ __global__ __launch_bounds__(256) void k_split16(GemmLaunch L) {
     // A: rows r0 .. r0 + 63, k0 .. k0 + 63; a thread converts runs of 8 k.
     const int r0 = (t / kt) * 64, k0 = (t % kt) * 64;
     if (r0 >= it.M) return;
+    const int tm0 = r0 / kH16TileM * kH16TileM;
+    if ((it.A.tri == 1 && k0 >= tm0 + kH16TileM) || (it.A.tri == 2 && k0 + 64 <= tm0)) return;
     const float* Ap = static_cast<const float*>(it.A.p);
     const int64_t lda = it.A.ld;
     const int atri = it.A.tri;
@@ -1510,19 +1516,29 @@ __global__ __launch_bounds__((BM / 64) * (BN / 64) * 64) void k_gemm_h16(GemmLau
         bv[j][0] = *reinterpret_cast<const h8_t*>(b_s + off);
         bv[j][1] = *reinterpret_cast<const h8_t*>(b_s + BN * BK + off);
       }
+      h8_t av[FM][2];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         const int r = wm * WM + i * 16 + li;
         const int off = r * BK + 8 * (kc ^ ((r >> 2) & 3));
-        const h8_t a0 = *reinterpret_cast<const h8_t*>(a_s + off);
-        const h8_t a1 = *reinterpret_cast<const h8_t*>(a_s + BM * BK + off);
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          acc[i][j] = LPT<1>::mma(a0, bv[j][0], acc[i][j]);
-          accx[i][j] = LPT<1>::mma(a0, bv[j][1], accx[i][j]);
-          accx[i][j] = LPT<1>::mma(a1, bv[j][0], accx[i][j]);
-        }
+        av[i][0] = *reinterpret_cast<const h8_t*>(a_s + off);
+        av[i][1] = *reinterpret_cast<const h8_t*>(a_s + BM * BK + off);
       }
+      // Three passes over the 16 fragment pairs: consecutive MFMAs never
+      // feed one accumulator (the two cross products would otherwise wait
+      // for each other).
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = LPT<1>::mma(av[i][0], bv[j][0], acc[i][j]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) accx[i][j] = LPT<1>::mma(av[i][0], bv[j][1], accx[i][j]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) accx[i][j] = LPT<1>::mma(av[i][1], bv[j][0], accx[i][j]);
     };
     // Step t (see k_gemm_dl): after the wait this thread's pieces of step t
     // have landed, the barrier makes that true for all and ends every read
@@ -2952,8 +2968,8 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
               const int cn = min(chunk, ndl - c0);
               dim3 gs((cdiv(max_m, 64) + cdiv(max_n, 64)) * (kp / 64), cn);
               hipLaunchKernelGGL(k_split16, gs, dim3(256), 0, st, S);
-              dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), cn);
-              hipLaunchKernelGGL((k_gemm_h16<256, 128>), grid, dim3(512), 0, st, S);
+              dim3 grid(cdiv(max_m, kH16TileM) * cdiv(max_n, 128), cn);
+              hipLaunchKernelGGL((k_gemm_h16<kH16TileM, 128>), grid, dim3(512), 0, st, S);
             }
           } else {
             dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), ndl);

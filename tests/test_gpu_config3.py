@@ -85,3 +85,22 @@ def test_k8_n2048_against_oracle(spd_n2048_k8, precision):
         print(f"n=2048 k=8 ({i},{j}) {precision}: rel err {err:.2e}", flush=True)
         assert int(info.item()) == 0
         assert err < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["mixed_f16", "mixed_f32"])
+def test_k8_n2048_unrefined_float_recursion(spd_n2048_k8, precision):
+    # The float recursion alone (no FP64 sweep): its explicit products at
+    # this size run as launches of hundreds of items, for FP16 on operands
+    # split once (triangular multiplies included).  Its error is the float
+    # recursion's, about cond(M) times the unit roundoff of the products
+    # (2^-22 for the split FP16 products, 2^-24 for FP32), here 1e4.
+    m, refs = spd_n2048_k8
+    g = torch.from_numpy(m).to(DEV)
+    want = refs[(0, 0)]
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    out = bri.invert_block(g, 8, 0, 0, precision=precision, info=info, refine_max_iters=0)
+    torch.cuda.synchronize()
+    err = rel(out.cpu().numpy(), want)
+    print(f"n=2048 k=8 (0,0) {precision} without refinement: rel err {err:.2e}", flush=True)
+    assert int(info.item()) == 0
+    assert err < 1e4 * 2.0 ** -22 * 16

@@ -1508,25 +1508,30 @@ __global__ __launch_bounds__((BM / 64) * (BN / 64) * 64) void k_gemm_h16(GemmLau
     // chunk l >> 4 (8 halves), for A and for B transposed alike.
     const int li = lane & 15, kc = lane >> 4;
     auto compute = [&](const _Float16* a_s, const _Float16* b_s) {
-      h8_t bv[FN][2];
+      h8_t bv[FN][2], av[FM][2];
+      int boff[FN], aoff[FM];
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int r = wn * WN + j * 16 + li;
-        const int off = r * BK + 8 * (kc ^ ((r >> 2) & 3));
-        bv[j][0] = *reinterpret_cast<const h8_t*>(b_s + off);
-        bv[j][1] = *reinterpret_cast<const h8_t*>(b_s + BN * BK + off);
+        boff[j] = r * BK + 8 * (kc ^ ((r >> 2) & 3));
       }
-      h8_t av[FM][2];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         const int r = wm * WM + i * 16 + li;
-        const int off = r * BK + 8 * (kc ^ ((r >> 2) & 3));
-        av[i][0] = *reinterpret_cast<const h8_t*>(a_s + off);
-        av[i][1] = *reinterpret_cast<const h8_t*>(a_s + BM * BK + off);
+        aoff[i] = r * BK + 8 * (kc ^ ((r >> 2) & 3));
       }
+      // High planes first (the first pass needs only them), then the low
+      // planes, whose reads overlap the first pass.
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bv[j][0] = *reinterpret_cast<const h8_t*>(b_s + boff[j]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i) av[i][0] = *reinterpret_cast<const h8_t*>(a_s + aoff[i]);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bv[j][1] = *reinterpret_cast<const h8_t*>(b_s + BN * BK + boff[j]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i) av[i][1] = *reinterpret_cast<const h8_t*>(a_s + BM * BK + aoff[i]);
       // Three passes over the 16 fragment pairs: consecutive MFMAs never
-      // feed one accumulator (the two cross products would otherwise wait
-      // for each other).
+      // feed one accumulator.
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -1539,6 +1544,16 @@ __global__ __launch_bounds__((BM / 64) * (BN / 64) * 64) void k_gemm_h16(GemmLau
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) accx[i][j] = LPT<1>::mma(av[i][1], bv[j][0], accx[i][j]);
+      // Instruction order (scheduling groups: 0x100 LDS reads, 0x008
+      // MFMA): the 8 high-plane reads, then each low-plane read after two
+      // MFMAs of the first pass, then the remaining MFMAs.
+      __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 32, 0);
     };
     // Step t (see k_gemm_dl): after the wait this thread's pieces of step t
     // have landed, the barrier makes that true for all and ends every read

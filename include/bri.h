@@ -256,12 +256,12 @@ int invert_block_backward(const void* M, int64_t n, int64_t ldm, int k, int i, i
  * least bri_gemm_workspace_size(count) bytes.  This is the MFMA kernel every
  * Schur complement D - C A^{-1} B of the recursion runs its products on
  * (eqs. SchurofA..SchurofD); it is exported to measure and test it alone.
- * BRI_MIXED_F16 (float operands, split FP16 products): workspace beyond
- * bri_gemm_workspace_size(count) is scratch for the operands split once
- * before the products, 4 (m + n) ceil(kk / 64) 64 bytes per item, as many
- * items at a time as it holds (used for launches of 256 or more output
- * tiles of 256 x 128 when kk is a multiple of 8 and the rows of A and C are
- * 16-byte aligned). */
+ * BRI_MIXED_F16 / BRI_MIXED_BF16 (float operands, split products): workspace
+ * beyond bri_gemm_workspace_size(count) is scratch for the operands split
+ * once before the products, 2 p (m + n) ceil(kk / 64) 64 bytes per item
+ * (p = 2 FP16 or 3 BF16 parts), as many items at a time as it holds (used
+ * for launches of 256 or more output tiles of 256 x 128 when kk is a
+ * multiple of 8 and the rows of A are 16-byte aligned). */
 size_t bri_gemm_workspace_size(int count);
 int bri_gemm(int count, int64_t m, int64_t n, int64_t kk, double alpha, const void* const* A, int64_t lda,
              const void* const* B, int64_t ldb, double beta, void* const* C, int64_t ldc, const bri_opts* o);

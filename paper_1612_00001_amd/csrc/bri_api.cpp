@@ -433,7 +433,7 @@ void describe_step(const Ctx& c, const Step& s, StepItems& out) {
         }
         // direct: the FP64 direct-to-LDS instance, or for the split FP16
         // products of float storage the vectorised instance
-        const bool direct = c.elem == 8 ? gemm_item_is_direct(g, 8) : (c.lp == 1 && gemm_item_is_lp_vec(g));
+        const bool direct = c.elem == 8 ? gemm_item_is_direct(g, 8) : (c.lp >= 1 && gemm_item_is_lp_vec(g));
         if (!gemm_item_is_fast(g))
           out.slow.push_back(g);
         else
@@ -1112,12 +1112,13 @@ struct MixedBatch {
   size_t desc_bytes = 0, total = 0;
 };
 
-// Scratch of the split FP16 products (mixed FP16 only): room for the split
-// operands of the largest explicit product step of the merged plans, at
+// Scratch of the split products (mixed FP16 and BF16): room for the split
+// operands (three BF16 planes, which an FP16 call needs when it falls back
+// to BF16) of the largest explicit product step of the merged plans, at
 // most kSplitCap bytes (larger steps run in parts).
 constexpr size_t kSplitCap = size_t(2) << 30;
 size_t split_scratch_bytes(const std::vector<const Plan*>& plans, const MergedLayout& m, int precision) {
-  if (precision != BRI_MIXED_F16) return 0;
+  if (precision != BRI_MIXED_F16 && precision != BRI_MIXED_BF16) return 0;
   int bmax = 0;
   for (const Plan* p : plans) bmax = std::max(bmax, p->b);
   size_t items = 0;
@@ -1131,7 +1132,7 @@ size_t split_scratch_bytes(const std::vector<const Plan*>& plans, const MergedLa
       items = std::max(items, n);
     }
   }
-  const size_t per = static_cast<size_t>(split_item_bytes(bmax, bmax, split_pitch(bmax)));
+  const size_t per = static_cast<size_t>(split_item_bytes(bmax, bmax, split_pitch(bmax), 3));
   return align_up(std::min(kSplitCap, items * per));
 }
 
@@ -2139,9 +2140,9 @@ int bri_gemm(int count, int64_t m, int64_t n, int64_t kk, double alpha, const vo
   L.items = o->workspace;
   L.count = count;
   L.w = count;  // plain dense operands: all items take the fast instance
-  if (L.lp == 1) {
-    // Split FP16 products: the vectorised instance when every item
-    // qualifies, and workspace beyond the descriptors as split scratch.
+  if (L.lp >= 1) {
+    // Split products: the vectorised or split-once instances when every
+    // item qualifies, and workspace beyond the descriptors as split scratch.
     bool vec = true;
     for (const GemmItem& g : items) vec = vec && gemm_item_is_lp_vec(g);
     L.ndl = vec ? count : 0;

@@ -138,9 +138,11 @@ struct GemmLaunch {
   int32_t split_kp, split_m, split_n;  // set by the launch: K pitch, A rows, B columns
 };
 
-// Bytes of one item's pre-split FP16 operands: high and low planes of A
-// (m rows) and of B transposed (n rows), kp elements per row.
-constexpr int64_t split_item_bytes(int m, int n, int kp) { return 4 * static_cast<int64_t>(m + n) * kp; }
+// Bytes of one item's pre-split operands: the parts (2 FP16 or 3 BF16
+// planes) of A (m rows) and of B transposed (n rows), kp elements per row.
+constexpr int64_t split_item_bytes(int m, int n, int kp, int parts) {
+  return 2 * static_cast<int64_t>(parts) * (m + n) * kp;
+}
 // The K pitch of the split operands of products of inner order up to k.
 constexpr int split_pitch(int k) { return (k + 63) / 64 * 64; }
 

@@ -1323,30 +1323,44 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_lpv(GemmLau
 }
 
 // ---------------------------------------------------------------------------
-// Split FP16 products from operands split once (mixed FP16 path, large
-// launches of explicit items).  k_split16 converts every item's operands:
-// A (M x K) into FP16 high and low planes with K contiguous per row, B
-// (K x N) into the planes of its transpose (K contiguous per column), the
-// triangular form of A applied, K zero-padded to the pitch kp; x = hi +
-// lo 2^-11 as in LPT<1>, with the FP16 range check.  k_gemm_h16 then moves
-// those planes into LDS with direct loads and runs the three FP16 products
-// per K step with no conversion in its loop.  In k_gemm_lpv every output
-// tile converts its own operand panels, so an element of A is converted
-// once per tile column and one of B once per tile row.
+// Split products from operands split once (mixed FP16 / BF16 paths, large
+// launches of explicit items).  k_split_ops converts every item's operands:
+// A (M x K) into low-precision planes (FP16 high and low, x = hi + lo 2^-11;
+// BF16 high, middle and low; as in LPT) with K contiguous per row, B (K x N)
+// into the planes of its transpose (K contiguous per column), the triangular
+// form of A applied and K zero-padded to the pitch kp; FP16 also checks the
+// range.  k_gemm_split then moves those planes into LDS with direct loads and
+// runs the products of the parts per K step (3 for FP16, 6 for BF16) with no
+// conversion in its loop.  In k_gemm_lpv and k_gemm_lp every output tile
+// converts its own operand panels, so an element of A is converted once per
+// tile column and one of B once per tile row.
 // ---------------------------------------------------------------------------
-// Row tile of the k_gemm_h16 launches: for a triangular A, the split pass
-// skips the 64 x 64 tiles outside the K range of their row tile.
-constexpr int kH16TileM = 256;
+// Row tile of the k_gemm_split launches per split kind: for a triangular A,
+// the split pass skips the 64 x 64 tiles outside the K range of their row tile.
+template <int LP>
+struct SplitShape;
+template <>
+struct SplitShape<1> {
+  static constexpr int BM = 256, BN = 128;
+};
+template <>
+struct SplitShape<2> {
+  static constexpr int BM = 128, BN = 128;
+};
 
-__global__ __launch_bounds__(256) void k_split16(GemmLaunch L) {
+template <int LP>
+__global__ __launch_bounds__(256) void k_split_ops(GemmLaunch L) {
+  typedef LPT<LP> P;
+  typedef typename P::E E;
+  typedef typename P::V V;
+  constexpr int NP = P::PARTS, TM = SplitShape<LP>::BM;
   __shared__ float tb[64][65];
   const GemmItem it = static_cast<const GemmItem*>(L.items)[blockIdx.y];
   const int kp = L.split_kp, kt = kp / 64;
-  _Float16* ah = reinterpret_cast<_Float16*>(static_cast<char*>(L.split) +
-                                             blockIdx.y * split_item_bytes(L.split_m, L.split_n, kp));
-  _Float16* al = ah + static_cast<int64_t>(L.split_m) * kp;
-  _Float16* bh = al + static_cast<int64_t>(L.split_m) * kp;
-  _Float16* bl = bh + static_cast<int64_t>(L.split_n) * kp;
+  E* ap = reinterpret_cast<E*>(static_cast<char*>(L.split) +
+                               blockIdx.y * split_item_bytes(L.split_m, L.split_n, kp, NP));
+  E* bp = ap + static_cast<int64_t>(NP) * L.split_m * kp;
+  const int64_t aplane = static_cast<int64_t>(L.split_m) * kp, bplane = static_cast<int64_t>(L.split_n) * kp;
   const int tid = threadIdx.x;
   const int ta = (L.split_m + 63) / 64 * kt;
   bool bad = false;
@@ -1355,8 +1369,8 @@ __global__ __launch_bounds__(256) void k_split16(GemmLaunch L) {
     // A: rows r0 .. r0 + 63, k0 .. k0 + 63; a thread converts runs of 8 k.
     const int r0 = (t / kt) * 64, k0 = (t % kt) * 64;
     if (r0 >= it.M) return;
-    const int tm0 = r0 / kH16TileM * kH16TileM;
-    if ((it.A.tri == 1 && k0 >= tm0 + kH16TileM) || (it.A.tri == 2 && k0 + 64 <= tm0)) return;
+    const int tm0 = r0 / TM * TM;
+    if ((it.A.tri == 1 && k0 >= tm0 + TM) || (it.A.tri == 2 && k0 + 64 <= tm0)) return;
     const float* Ap = static_cast<const float*>(it.A.p);
     const int64_t lda = it.A.ld;
     const int atri = it.A.tri;
@@ -1374,21 +1388,22 @@ __global__ __launch_bounds__(256) void k_split16(GemmLaunch L) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) v[u] = 0.f;
       }
-      h8_t hv, lv;
+      V part[NP];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int y = y0 + u;
         float a = y < it.K ? v[u] : 0.f;
         if (atri == 1) a = x > y ? a : (x == y && y < it.K ? 1.f : 0.f);
         if (atri == 2) a = x <= y ? a : 0.f;
-        bad = bad || !(fabsf(a) < 65504.0f);
-        _Float16 pv[2];
-        LPT<1>::split(a, pv);
-        hv[u] = pv[0];
-        lv[u] = pv[1];
+        if (LP == 1) bad = bad || !(fabsf(a) < 65504.0f);
+        E pv[NP];
+        P::split(a, pv);
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) part[pp][u] = pv[pp];
       }
-      *reinterpret_cast<h8_t*>(ah + static_cast<int64_t>(x) * kp + y0) = hv;
-      *reinterpret_cast<h8_t*>(al + static_cast<int64_t>(x) * kp + y0) = lv;
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp)
+        *reinterpret_cast<V*>(ap + pp * aplane + static_cast<int64_t>(x) * kp + y0) = part[pp];
     }
   } else {
     // B: columns n0 .. n0 + 63, k0 .. k0 + 63, transposed through LDS.
@@ -1412,21 +1427,22 @@ __global__ __launch_bounds__(256) void k_split16(GemmLaunch L) {
     for (int q = 0; q < 2; ++q) {
       const int run = tid + q * 256, nr = run >> 3, c = run & 7, y = n0 + nr;
       if (y >= it.N) continue;
-      h8_t hv, lv;
+      V part[NP];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const float b = tb[8 * c + u][nr];
-        bad = bad || !(fabsf(b) < 65504.0f);
-        _Float16 pv[2];
-        LPT<1>::split(b, pv);
-        hv[u] = pv[0];
-        lv[u] = pv[1];
+        if (LP == 1) bad = bad || !(fabsf(b) < 65504.0f);
+        E pv[NP];
+        P::split(b, pv);
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) part[pp][u] = pv[pp];
       }
-      *reinterpret_cast<h8_t*>(bh + static_cast<int64_t>(y) * kp + k0 + 8 * c) = hv;
-      *reinterpret_cast<h8_t*>(bl + static_cast<int64_t>(y) * kp + k0 + 8 * c) = lv;
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp)
+        *reinterpret_cast<V*>(bp + pp * bplane + static_cast<int64_t>(y) * kp + k0 + 8 * c) = part[pp];
     }
   }
-  if (L.range_flag && __any(bad) && (tid & 63) == 0) atomicOr(L.range_flag, 1);
+  if (LP == 1 && L.range_flag && __any(bad) && (tid & 63) == 0) atomicOr(L.range_flag, 1);
 }
 
 // Products of the split planes: BM x BN tiles of 64 x 64 wavefronts, K in
@@ -1434,17 +1450,21 @@ __global__ __launch_bounds__(256) void k_split16(GemmLaunch L) {
 // (16-byte pieces, eight k of one row of one plane) with the pipeline of
 // k_gemm_dl.  LDS piece (plane, row r, slot s) holds k chunk s ^ ((r >> 2) & 3)
 // of that row, so that the 16 rows a quarter-wavefront reads at one chunk
-// fall in distinct banks.  Epilogue as in k_gemm_lpv.
-template <int BM, int BN>
-__global__ __launch_bounds__((BM / 64) * (BN / 64) * 64) void k_gemm_h16(GemmLaunch L) {
+// fall in distinct banks.  Products and epilogue as in k_gemm_lpv.
+template <int LP, int BM, int BN>
+__global__ __launch_bounds__((BM / 64) * (BN / 64) * 64) void k_gemm_split(GemmLaunch L) {
+  typedef LPT<LP> P;
+  typedef typename P::E E;
+  typedef typename P::V V;
+  constexpr int NP = P::PARTS;
   constexpr int WM = 64, WN = 64, NWN = BN / WN, FM = WM / 16, FN = WN / 16;
   constexpr int NT = (BM / WM) * NWN * 64, BK = 32;
-  constexpr int AC = 2 * BM * 4, BC = 2 * BN * 4;  // 16-byte pieces per K step (2 planes, 4 per row)
+  constexpr int AC = NP * BM * 4, BC = NP * BN * 4;  // 16-byte pieces per K step (4 per row and plane)
   constexpr int AI = AC / NT, BI = BC / NT;
   static_assert(AI * NT == AC && BI * NT == BC && AI >= 1 && BI >= 1, "tile/thread mismatch");
   static_assert(AI + BI < 16, "outstanding loads per K step must fit the vmcnt field");
-  __shared__ __attribute__((aligned(16))) _Float16 sA0[2 * BM * BK], sA1[2 * BM * BK], sA2[2 * BM * BK];
-  __shared__ __attribute__((aligned(16))) _Float16 sB0[2 * BN * BK], sB1[2 * BN * BK], sB2[2 * BN * BK];
+  __shared__ __attribute__((aligned(16))) E sA0[NP * BM * BK], sA1[NP * BM * BK], sA2[NP * BM * BK];
+  __shared__ __attribute__((aligned(16))) E sB0[NP * BN * BK], sB1[NP * BN * BK], sB2[NP * BN * BK];
 
   GemmItem it;
   int item, tile;
@@ -1462,9 +1482,9 @@ __global__ __launch_bounds__((BM / 64) * (BN / 64) * 64) void k_gemm_h16(GemmLau
   if (it.A.tri == 2) kb = max(kb, m0);
   kb = (kb / BK) * BK;
 
-  const _Float16* ah = reinterpret_cast<const _Float16*>(static_cast<const char*>(L.split) +
-                                                         item * split_item_bytes(L.split_m, L.split_n, kp));
-  const _Float16* bh = ah + 2 * static_cast<int64_t>(L.split_m) * kp;
+  const E* ah = reinterpret_cast<const E*>(static_cast<const char*>(L.split) +
+                                           item * split_item_bytes(L.split_m, L.split_n, kp, NP));
+  const E* bh = ah + static_cast<int64_t>(NP) * L.split_m * kp;
   const int64_t aplane = static_cast<int64_t>(L.split_m) * kp, bplane = static_cast<int64_t>(L.split_n) * kp;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1487,28 +1507,28 @@ __global__ __launch_bounds__((BM / 64) * (BN / 64) * 64) void k_gemm_h16(GemmLau
     // one (into a buffer no later step reads).  Piece P of a step: plane
     // P / (4 rows), row (P % (4 rows)) / 4, slot P % 4 (rows clamped into
     // the product).
-    auto issue = [&](int t, _Float16* dA, _Float16* dB) {
+    auto issue = [&](int t, E* dA, E* dB) {
       const int k0 = kb + min(t, nk - 1) * BK;
 #pragma unroll
       for (int q = 0; q < AI; ++q) {
         const int P = q * NT + tid, pl = P / (BM * 4), rem = P % (BM * 4), r = rem >> 2;
         const int c = (rem & 3) ^ ((r >> 2) & 3);
-        const _Float16* src = ah + pl * aplane + static_cast<int64_t>(min(m0 + r, it.M - 1)) * kp + k0 + 8 * c;
+        const E* src = ah + pl * aplane + static_cast<int64_t>(min(m0 + r, it.M - 1)) * kp + k0 + 8 * c;
         __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t*)(dA + (q * NT + wave * 64) * 8), 16, 0, 0);
       }
 #pragma unroll
       for (int q = 0; q < BI; ++q) {
         const int P = q * NT + tid, pl = P / (BN * 4), rem = P % (BN * 4), r = rem >> 2;
         const int c = (rem & 3) ^ ((r >> 2) & 3);
-        const _Float16* src = bh + pl * bplane + static_cast<int64_t>(min(n0 + r, it.N - 1)) * kp + k0 + 8 * c;
+        const E* src = bh + pl * bplane + static_cast<int64_t>(min(n0 + r, it.N - 1)) * kp + k0 + 8 * c;
         __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t*)(dB + (q * NT + wave * 64) * 8), 16, 0, 0);
       }
     };
     // Fragment reads: lane l takes row (l & 15) of a 16-row block and k
-    // chunk l >> 4 (8 halves), for A and for B transposed alike.
+    // chunk l >> 4 (8 elements), for A and for B transposed alike.
     const int li = lane & 15, kc = lane >> 4;
-    auto compute = [&](const _Float16* a_s, const _Float16* b_s) {
-      h8_t bv[FN][2], av[FM][2];
+    auto compute = [&](const E* a_s, const E* b_s) {
+      V bv[FN][NP], av[FM][NP];
       int boff[FN], aoff[FM];
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
@@ -1520,45 +1540,52 @@ __global__ __launch_bounds__((BM / 64) * (BN / 64) * 64) void k_gemm_h16(GemmLau
         const int r = wm * WM + i * 16 + li;
         aoff[i] = r * BK + 8 * (kc ^ ((r >> 2) & 3));
       }
-      // High planes first (the first pass needs only them), then the low
-      // planes, whose reads overlap the first pass.
+      // High planes first (the first pass needs only them), then the
+      // others, whose reads overlap the first passes.
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bv[j][0] = *reinterpret_cast<const h8_t*>(b_s + boff[j]);
+      for (int pp = 0; pp < NP; ++pp) {
 #pragma unroll
-      for (int i = 0; i < FM; ++i) av[i][0] = *reinterpret_cast<const h8_t*>(a_s + aoff[i]);
+        for (int j = 0; j < FN; ++j) bv[j][pp] = *reinterpret_cast<const V*>(b_s + pp * BN * BK + boff[j]);
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bv[j][1] = *reinterpret_cast<const h8_t*>(b_s + BN * BK + boff[j]);
+        for (int i = 0; i < FM; ++i) av[i][pp] = *reinterpret_cast<const V*>(a_s + pp * BM * BK + aoff[i]);
+      }
+      // One pass per product over the 16 fragment pairs: consecutive MFMAs
+      // never feed one accumulator.  FP16: hi hi into acc, the cross
+      // products into accx (scaled by 2^-11 at the end); BF16: hi hi and the
+      // hi-mid products into acc, the smaller ones into accx.
+      auto pass = [&](f4_t (&c)[FM][FN], int pa, int pb) {
 #pragma unroll
-      for (int i = 0; i < FM; ++i) av[i][1] = *reinterpret_cast<const h8_t*>(a_s + BM * BK + aoff[i]);
-      // Three passes over the 16 fragment pairs: consecutive MFMAs never
-      // feed one accumulator.
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = LPT<1>::mma(av[i][0], bv[j][0], acc[i][j]);
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) accx[i][j] = LPT<1>::mma(av[i][0], bv[j][1], accx[i][j]);
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) accx[i][j] = LPT<1>::mma(av[i][1], bv[j][0], accx[i][j]);
+          for (int j = 0; j < FN; ++j) c[i][j] = P::mma(av[i][pa], bv[j][pb], c[i][j]);
+      };
+      pass(acc, 0, 0);
+      if (LP == 1) {
+        pass(accx, 0, 1);
+        pass(accx, 1, 0);
+      } else {
+        pass(acc, 0, 1);
+        pass(acc, 1, 0);
+        pass(accx, 1, 1);
+        pass(accx, 0, 2);
+        pass(accx, 2, 0);
+      }
       // Instruction order (scheduling groups: 0x100 LDS reads, 0x008
-      // MFMA): the 8 high-plane reads, then each low-plane read after two
-      // MFMAs of the first pass, then the remaining MFMAs.
-      __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+      // MFMA): the high-plane reads, then each further read after two
+      // MFMAs, then the remaining MFMAs.
+      constexpr int R0 = FM + FN, RX = (NP - 1) * (FM + FN), NMF = FM * FN * (LP == 1 ? 3 : 6);
+      __builtin_amdgcn_sched_group_barrier(0x100, R0, 0);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < RX; ++q) {
         __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
       }
-      __builtin_amdgcn_sched_group_barrier(0x008, 32, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, NMF - 2 * RX, 0);
     };
     // Step t (see k_gemm_dl): after the wait this thread's pieces of step t
     // have landed, the barrier makes that true for all and ends every read
     // of the buffer that then receives step t + 2.
-    auto step = [&](int t, _Float16* ra, _Float16* rb, _Float16* wa, _Float16* wb) {
+    auto step = [&](int t, E* ra, E* rb, E* wa, E* wb) {
       lds_barrier<0x0070 | (AI + BI)>();
       issue(t + 2, wa, wb);
       if (t < nk) compute(ra, rb);
@@ -1575,7 +1602,7 @@ __global__ __launch_bounds__((BM / 64) * (BN / 64) * 64) void k_gemm_h16(GemmLau
 
   float* out = static_cast<float*>(it.out);
   const float alpha = static_cast<float>(it.alpha), beta = static_cast<float>(it.beta);
-  constexpr float xs = 1.0f / 2048.0f;
+  const float xs = LP == 1 ? 1.0f / 2048.0f : 1.0f;
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
     float cv[FN][4], sv[FN][4];
@@ -2959,21 +2986,22 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
           if (e != hipSuccess) return e;
         }
       } else {
-        // Split FP16 products of float storage: the vectorised instance
-        // when every fast item qualifies (GemmLaunch::ndl; split BF16 keeps
-        // the register-staged instance, see launch_gemm_rlu).
-        // Launches of fewer than 256 tiles of 256 x 128 keep the
-        // register-staged instance's smaller tiles (more workgroups).
+        // Split products of float storage, when every fast item qualifies
+        // (GemmLaunch::ndl).  Launches of fewer than 256 tiles of 256 x 128
+        // keep the register-staged instance's smaller tiles (more
+        // workgroups).
         const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * nfast;
-        if (L.lp == 1 && nfast > 0 && L.ndl == nfast && tiles256 >= 256) {
-          ndl = nfast;
-          // With split scratch: the operands split once (k_split16), then
-          // the products of the planes (k_gemm_h16), as many items at a time
-          // as the scratch holds.
+        if (L.lp >= 1 && nfast > 0 && L.ndl == nfast && tiles256 >= 256) {
+          // With split scratch: the operands split once (k_split_ops), then
+          // the products of the planes (k_gemm_split), as many items at a
+          // time as the scratch holds.  Without it, FP16 takes the
+          // vectorised instance and BF16 the register-staged one (below).
+          const int parts = L.lp == 1 ? 2 : 3;
           const int kp = split_pitch(max(L.max_k, max(max_m, max_n)));
-          const int64_t per = split_item_bytes(max_m, max_n, kp);
-          const int chunk = L.split ? static_cast<int>(std::min<int64_t>(ndl, L.split_bytes / per)) : 0;
+          const int64_t per = split_item_bytes(max_m, max_n, kp, parts);
+          const int chunk = L.split ? static_cast<int>(std::min<int64_t>(nfast, L.split_bytes / per)) : 0;
           if (chunk > 0) {
+            ndl = nfast;
             for (int c0 = 0; c0 < ndl; c0 += chunk) {
               GemmLaunch S = L;
               S.items = static_cast<const GemmItem*>(L.items) + c0;
@@ -2982,11 +3010,20 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
               S.split_n = max_n;
               const int cn = min(chunk, ndl - c0);
               dim3 gs((cdiv(max_m, 64) + cdiv(max_n, 64)) * (kp / 64), cn);
-              hipLaunchKernelGGL(k_split16, gs, dim3(256), 0, st, S);
-              dim3 grid(cdiv(max_m, kH16TileM) * cdiv(max_n, 128), cn);
-              hipLaunchKernelGGL((k_gemm_h16<kH16TileM, 128>), grid, dim3(512), 0, st, S);
+              if (L.lp == 1) {
+                constexpr int BM = SplitShape<1>::BM, BN = SplitShape<1>::BN;
+                hipLaunchKernelGGL(k_split_ops<1>, gs, dim3(256), 0, st, S);
+                dim3 grid(cdiv(max_m, BM) * cdiv(max_n, BN), cn);
+                hipLaunchKernelGGL((k_gemm_split<1, BM, BN>), grid, dim3((BM / 64) * (BN / 64) * 64), 0, st, S);
+              } else {
+                constexpr int BM = SplitShape<2>::BM, BN = SplitShape<2>::BN;
+                hipLaunchKernelGGL(k_split_ops<2>, gs, dim3(256), 0, st, S);
+                dim3 grid(cdiv(max_m, BM) * cdiv(max_n, BN), cn);
+                hipLaunchKernelGGL((k_gemm_split<2, BM, BN>), grid, dim3((BM / 64) * (BN / 64) * 64), 0, st, S);
+              }
             }
-          } else {
+          } else if (L.lp == 1) {
+            ndl = nfast;
             dim3 grid(cdiv(max_m, 256) * cdiv(max_n, 128), ndl);
             hipLaunchKernelGGL((k_gemm_lpv<1, GEMM_EXPLICIT, 256, 128, 64, 64>), grid, dim3(512), 0, st, L);
           }

@@ -56,27 +56,28 @@ def test_split_product_gemm(products, m, n, kk):
     assert err <= 2.0 ** -20 * scale / np.sqrt(kk) * 8
 
 
+@pytest.mark.parametrize("products", ["f16", "bf16"])
 @pytest.mark.parametrize("count,m,n,kk,chunk", [(2, 2048, 2048, 2048, 2), (10, 1000, 776, 1000, 3),
                                                  (300, 64, 136, 200, 64)])
-def test_split_once_products(count, m, n, kk, chunk):
-    # FP16 split products of launches with at least 256 output tiles of
-    # 256 x 128: operands split once into scratch (chunk items at a time),
-    # then the products of the split planes; against the FP64 product of the
-    # float operands, and against the same launch without scratch (operands
-    # split inside the product kernel).
+def test_split_once_products(products, count, m, n, kk, chunk):
+    # Split products of launches with at least 256 output tiles of 256 x 128:
+    # operands split once into scratch (chunk items at a time; 2 FP16 or 3
+    # BF16 planes), then the products of the split planes; against the FP64
+    # product of the float operands, and against the same launch without
+    # scratch (operands split inside the product kernel).
     rng = np.random.default_rng(7 * count + m + n + kk)
     a = [rng.standard_normal((m, kk)).astype(np.float32) for _ in range(count)]
     b = [rng.standard_normal((kk, n)).astype(np.float32) for _ in range(count)]
     c0 = [rng.standard_normal((m, n)).astype(np.float32) for _ in range(count)]
     kp = (kk + 63) // 64 * 64
-    per = 4 * (m + n) * kp
+    per = 2 * (2 if products == "f16" else 3) * (m + n) * kp
     A = [gpu(x, torch.float32) for x in a]
     B = [gpu(x, torch.float32) for x in b]
     C1 = [gpu(x, torch.float32) for x in c0]
     C2 = [gpu(x, torch.float32) for x in c0]
-    print(f"split once: {count} x {m}x{n}x{kk}, {chunk} items per part", flush=True)
-    bri.gemm(A, B, C1, alpha=-1.0, beta=1.0, products="f16", split_bytes=chunk * per)
-    bri.gemm(A, B, C2, alpha=-1.0, beta=1.0, products="f16")
+    print(f"split once ({products}): {count} x {m}x{n}x{kk}, {chunk} items per part", flush=True)
+    bri.gemm(A, B, C1, alpha=-1.0, beta=1.0, products=products, split_bytes=chunk * per)
+    bri.gemm(A, B, C2, alpha=-1.0, beta=1.0, products=products)
     torch.cuda.synchronize()
     worst = 0.0
     for t in range(count):

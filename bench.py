@@ -275,9 +275,9 @@ def main() -> int:
     # multiplies and Schur products; one launch per plan step) or the
     # factorisation of the pivot blocks, whichever takes longer.
     prods = family_roofline(prof, PRODUCT_KINDS, 1,
-                            "k_gemm_dl<GEMM_EXPLICIT, 256, 128, 64, 64> (direct-to-LDS FP64 products: "
-                            "triangular multiplies and Schur products of a plan step; 128 x 128 tiles for "
-                            "the launches of fewer than 512 tiles)",
+                            "k_gemm_dl<GEMM_EXPLICIT, ...> (direct-to-LDS FP64 products of the plan "
+                            "steps: 128 x 256 tiles for the triangular multiplies, 256 x 128 for the Schur "
+                            "products; 128 x 128 or 64 x 64 tiles for launches of fewer than 512 tiles)",
                             "b^3 per triangular multiply, 2 b^3 per Schur product")
     prods["traffic"] = counted_traffic()
     facts = family_roofline(prof, FACTOR_KINDS, 1,

@@ -150,6 +150,9 @@ def main() -> int:
                          "library; only with --headline-only)")
     ap.add_argument("--factorization", choices=("auto", "tile", "recursive"), default="auto",
                     help="LU variant of the headline calls (default: the library's choice)")
+    ap.add_argument("--profile-precision", choices=("mixed_f16", "mixed_bf16"), default=None,
+                    help="only run one call of the headline workload in this mixed precision and exit "
+                         "(for kernel traces of the mixed paths)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -225,6 +228,13 @@ def main() -> int:
         ref = ((qb * torch.from_numpy(1.0 / lam).to(dev)[None, :]) @ qb.T.contiguous()).cpu().numpy()
         del qb
     torch.cuda.synchronize()
+    if args.profile_precision:
+        pc, po, pinfo, pws = setup(M3, n, k, i, j, args.profile_precision)
+        pms, _ = time_calls(pc, 1, 0, torch)
+        print(json.dumps({"workload": "spd_n16384_k8" if args.input == "spd" else "dd_n16384_k8",
+                          "precision": args.profile_precision, "ms": pms, "info": int(pinfo.item()),
+                          "refine_sweeps": bri.refine_last()[0]}), flush=True)
+        return 0
     stats = bri.plan_describe(n, k, i, j, "f64")
     flops = stats["algorithmic_flops"]
     call, out, info, ws = setup(M3, n, k, i, j, "f64", factorization=args.factorization)

@@ -260,7 +260,7 @@ int invert_block_backward(const void* M, int64_t n, int64_t ldm, int k, int i, i
  * beyond bri_gemm_workspace_size(count) is scratch for the operands split
  * once before the products, 2 p (m + n) ceil(kk / 64) 64 bytes per item
  * (p = 2 FP16 or 3 BF16 parts), as many items at a time as it holds (used
- * for launches of 256 or more output tiles of 256 x 128 when kk is a
+ * for launches of 2048 or more output tiles of 256 x 128 when kk is a
  * multiple of 8 and the rows of A are 16-byte aligned). */
 size_t bri_gemm_workspace_size(int count);
 int bri_gemm(int count, int64_t m, int64_t n, int64_t kk, double alpha, const void* const* A, int64_t lda,

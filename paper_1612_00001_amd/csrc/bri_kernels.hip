@@ -2992,14 +2992,19 @@ hipError_t launch_gemm(const GemmLaunch& L, int max_m, int max_n, hipStream_t st
         // workgroups).
         const int64_t tiles256 = static_cast<int64_t>(cdiv(max_m, 256)) * cdiv(max_n, 128) * nfast;
         if (L.lp >= 1 && nfast > 0 && L.ndl == nfast && tiles256 >= 256) {
-          // With split scratch: the operands split once (k_split_ops), then
-          // the products of the planes (k_gemm_split), as many items at a
-          // time as the scratch holds.  Without it, FP16 takes the
-          // vectorised instance and BF16 the register-staged one (below).
+          // Launches of at least 2048 such tiles, with split scratch: the
+          // operands split once (k_split_ops), then the products of the
+          // planes (k_gemm_split), as many items at a time as the scratch
+          // holds (n = 16384, k = 8: 32768 tiles per launch).  Otherwise FP16
+          // takes the vectorised instance and BF16 the register-staged one
+          // (below): at n = 4096, k = 4 (512 tiles) the split pass made the
+          // mixed FP16 / BF16 calls 16% / 28% slower.
           const int parts = L.lp == 1 ? 2 : 3;
           const int kp = split_pitch(max(L.max_k, max(max_m, max_n)));
           const int64_t per = split_item_bytes(max_m, max_n, kp, parts);
-          const int chunk = L.split ? static_cast<int>(std::min<int64_t>(nfast, L.split_bytes / per)) : 0;
+          const int chunk = L.split && tiles256 >= 2048
+                                ? static_cast<int>(std::min<int64_t>(nfast, L.split_bytes / per))
+                                : 0;
           if (chunk > 0) {
             ndl = nfast;
             for (int c0 = 0; c0 < ndl; c0 += chunk) {

@@ -87,20 +87,36 @@ def test_k8_n2048_against_oracle(spd_n2048_k8, precision):
         assert err < 1e-10
 
 
-@pytest.mark.parametrize("precision", ["mixed_f16", "mixed_f32"])
-def test_k8_n2048_unrefined_float_recursion(spd_n2048_k8, precision):
-    # The float recursion alone (no FP64 sweep): its explicit products at
-    # this size run as launches of hundreds of items, for FP16 on operands
-    # split once (triangular multiplies included).  Its error is the float
-    # recursion's, about cond(M) times the unit roundoff of the products
-    # (2^-22 for the split FP16 products, 2^-24 for FP32), here 1e4.
-    m, refs = spd_n2048_k8
+@pytest.fixture(scope="module")
+def spd_n4096_k8():
+    w = workloads.haar_spd(4096, 37, 0.0, 4.0, pin_endpoints=True)
+    b = 512
+    qb = w.q[:b]
+    # closed form of block (0, 0) of M^{-1} = Q Lam^{-1} Q^T
+    return w.m, (qb / w.lam[None, :]) @ qb.T
+
+
+@pytest.mark.parametrize("precision", ["mixed_f16", "mixed_bf16", "mixed_f32"])
+def test_k8_n4096_unrefined_float_recursion(spd_n4096_k8, precision):
+    # The float recursion alone (no FP64 sweep) at n = 4096, k = 8: its
+    # explicit product launches (256 items of order 512, 2048 tiles of
+    # 256 x 128) run on operands split once for FP16 and BF16, triangular
+    # multiplies included.  Its error is the float recursion's, about
+    # cond(M) = 1e4 times the unit roundoff of the products (2^-22 for the
+    # split FP16 products, 2^-24 for split BF16 and FP32).
+    m, want = spd_n4096_k8
     g = torch.from_numpy(m).to(DEV)
-    want = refs[(0, 0)]
     info = torch.zeros(1, dtype=torch.int32, device=DEV)
     out = bri.invert_block(g, 8, 0, 0, precision=precision, info=info, refine_max_iters=0)
     torch.cuda.synchronize()
     err = rel(out.cpu().numpy(), want)
-    print(f"n=2048 k=8 (0,0) {precision} without refinement: rel err {err:.2e}", flush=True)
+    print(f"n=4096 k=8 (0,0) {precision} without refinement: rel err {err:.2e}", flush=True)
     assert int(info.item()) == 0
     assert err < 1e4 * 2.0 ** -22 * 16
+    # and with the FP64 sweeps
+    out = bri.invert_block(g, 8, 0, 0, precision=precision, info=info)
+    torch.cuda.synchronize()
+    err = rel(out.cpu().numpy(), want)
+    print(f"  refined: rel err {err:.2e}", flush=True)
+    assert int(info.item()) == 0
+    assert err < 1e-10

@@ -57,10 +57,10 @@ def test_split_product_gemm(products, m, n, kk):
 
 
 @pytest.mark.parametrize("products", ["f16", "bf16"])
-@pytest.mark.parametrize("count,m,n,kk,chunk", [(2, 2048, 2048, 2048, 2), (10, 1000, 776, 1000, 3),
-                                                 (300, 64, 136, 200, 64)])
+@pytest.mark.parametrize("count,m,n,kk,chunk", [(64, 1024, 1024, 1024, 20), (80, 1000, 776, 1000, 23),
+                                                 (1100, 64, 136, 200, 300)])
 def test_split_once_products(products, count, m, n, kk, chunk):
-    # Split products of launches with at least 256 output tiles of 256 x 128:
+    # Split products of launches with at least 2048 output tiles of 256 x 128:
     # operands split once into scratch (chunk items at a time; 2 FP16 or 3
     # BF16 planes), then the products of the split planes; against the FP64
     # product of the float operands, and against the same launch without

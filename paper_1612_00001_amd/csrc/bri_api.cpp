@@ -226,7 +226,7 @@ struct ExecCfg {
   int lp = 0;           // float products: 0 FP32 MFMA, 1 FP16 split, 2 BF16 split
   bool wide = false;    // tile factorisations of float matrices in double
   int32_t* range_flag = nullptr;  // FP16 split products: operand outside the FP16 range
-  char* split = nullptr;          // FP16 split products: scratch for operands split once
+  char* split = nullptr;          // split FP16 / BF16 products: scratch for operands split once
   size_t split_bytes = 0;
 };
 ExecCfg cfg_of(const Ctx& c) { return ExecCfg{c.pivoting, c.lu, c.lp, c.wide, nullptr, nullptr, 0}; }
@@ -431,8 +431,8 @@ void describe_step(const Ctx& c, const Step& s, StepItems& out) {
           }
           g.alpha = (s.kind == ST_GEMM_ACC) ? 1.0 : -1.0;
         }
-        // direct: the FP64 direct-to-LDS instance, or for the split FP16
-        // products of float storage the vectorised instance
+        // direct: the FP64 direct-to-LDS instance, or for the split FP16 /
+        // BF16 products of float storage the vectorised and split-once ones
         const bool direct = c.elem == 8 ? gemm_item_is_direct(g, 8) : (c.lp >= 1 && gemm_item_is_lp_vec(g));
         if (!gemm_item_is_fast(g))
           out.slow.push_back(g);

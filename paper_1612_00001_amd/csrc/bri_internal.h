@@ -180,10 +180,11 @@ inline bool gemm_item_is_direct(const GemmItem& g, int elem) {
          (!g.has_cin || view_plain(g.Cin, g.M, g.N)) && (!g.has_sub || view_plain(g.Sub, g.M, g.N));
 }
 // An item of the vectorised split FP16 instance (float storage,
-// k_gemm_lpv): A stored untransposed with 16-byte aligned rows, unpermuted,
-// possibly triangular; B stored untransposed, untriangular, possibly with a
-// row permutation; K a multiple of 8 (runs of eight k never cross it) and at
-// most kMaxBlock; plain Cin / Sub; no element conversion or evaluation.
+// k_gemm_lpv) and of the split pass (k_split_ops): A stored untransposed
+// with 16-byte aligned rows, unpermuted, possibly triangular; B stored
+// untransposed, untriangular, possibly with a row permutation; K a multiple
+// of 8 (runs of eight k never cross it) and at most kMaxBlock; plain Cin /
+// Sub; no element conversion or evaluation.
 inline bool gemm_item_is_lp_vec(const GemmItem& g) {
   return g.M > 0 && g.N > 0 && g.K > 0 && g.K % 8 == 0 && g.K <= kMaxBlock &&
          view_direct(g.A, g.M, g.K, 4) && g.A.rowperm == nullptr && g.A.src64_max == nullptr && g.A.rbf == nullptr &&

@@ -138,6 +138,21 @@ typedef struct {
                               BRI_ERR_WORKSPACE when even width 1 does not fit.
                               Batched calls ignore it.                            */
   int order;               /* a bri_order value (default BRI_ORDER_PRINCIPAL)         */
+  int64_t* d_stats;        /* device accounting of the work a call executes, or NULL:
+                              4 device int64 words, zeroed at the start of the call's
+                              last pass (automatic pivoting: the panel pass when it
+                              ran; mixed: the BF16 pass after an FP16 range restart)
+                              and filled by small kernels after every plan step from
+                              the descriptors that step ran on: [0] pivot
+                              factorisations (Theorem "C_BRI": T(k) Schur operations
+                              + the final inversion), [1] Schur products D - C X,
+                              [2] other products (triangular multiplies, final
+                              products), [3] workspace high-water mark: the end of
+                              the highest workspace byte a step wrote, relative to
+                              workspace (Theorem "MC_BRI").  invert_block (plain and
+                              mixed precisions, noalloc included); calls with it do
+                              not replay captured graphs.  Costs one small launch
+                              per plan step.                                          */
 } bri_opts;
 
 /* Fills *o with defaults: BRI_F64, automatic concurrency, automatic pivoting
@@ -350,6 +365,10 @@ const char* bri_status_string(int status);
 
 /* Library version string. */
 const char* bri_version(void);
+
+/* sizeof(bri_opts) as the library was built with (for bindings that lay the
+ * struct out themselves). */
+size_t bri_opts_size(void);
 
 #ifdef __cplusplus
 }

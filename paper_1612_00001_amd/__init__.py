@@ -47,6 +47,7 @@ class BriOpts(ctypes.Structure):
         ("factorization", ctypes.c_int),
         ("workspace_budget", ctypes.c_size_t),
         ("order", ctypes.c_int),
+        ("d_stats", ctypes.c_void_p),
     ]
 
 
@@ -137,6 +138,7 @@ _SIGNATURES = [
     ("bri_tune_load", ctypes.c_int, [ctypes.c_char_p]),
     ("bri_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("bri_version", ctypes.c_char_p, []),
+    ("bri_opts_size", ctypes.c_size_t, []),
 ]
 
 
@@ -268,7 +270,7 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
                  workspace: Optional[torch.Tensor] = None, refine_max_iters: int = 10,
                  refine_tol: float = 1e-12, pivoting: str = "auto", reuse: bool = False,
                  factorization: str = "auto", workspace_budget: int = 0,
-                 order: str = "principal") -> torch.Tensor:
+                 order: str = "principal", stats: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Block N_ij (b x b, b = ceil(n/k)) of M^{-1} (of Gamma^{-1} when k does not divide n).
 
     ``order="paper"`` runs the paper's literal frame procedure instead of the
@@ -276,6 +278,10 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
 
     ``info`` (optional int32 GPU tensor of one element) receives the device
     status of include/bri.h; it is not checked here (no synchronisation).
+
+    ``stats`` (optional int64 GPU tensor of four elements) receives the
+    device accounting of the executed work (bri_opts::d_stats in
+    include/bri.h; ``stats_dict`` names its fields).
     """
     dtype = _DTYPE_OF[precision]
     _require_gpu(M, "M", dtype)
@@ -299,10 +305,23 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
     o.workspace = workspace.data_ptr()
     o.workspace_bytes = workspace.numel()
     o.d_info = info.data_ptr() if info is not None else None
+    if stats is not None:
+        if not isinstance(stats, torch.Tensor) or stats.device.type != "cuda" or stats.dtype != torch.int64 \
+                or stats.numel() < 4 or not stats.is_contiguous():
+            raise ValueError("stats must be a contiguous int64 GPU tensor of at least 4 elements")
+        o.d_stats = stats.data_ptr()
     o.stream = _stream_ptr(M.device)
     _check(lib().invert_block(M.data_ptr(), n, M.stride(0), k, i, j, out.data_ptr(), out.stride(0),
                               ctypes.byref(o)))
     return out
+
+
+def stats_dict(stats: torch.Tensor) -> dict:
+    """The device accounting words of ``invert_block(..., stats=...)`` by name
+    (synchronises with the device to read them)."""
+    v = [int(x) for x in stats[:4].cpu().tolist()]
+    return {"factorizations": v[0], "schur_products": v[1], "other_products": v[2],
+            "workspace_high_water": v[3]}
 
 
 def rbf_workspace_size(npts: int, d: int, k: int, i: int, j: int, precision: str = "f64",

@@ -217,6 +217,9 @@ struct Ctx {
   int m_elem = 0;       // element size of M when it differs from elem (mixed: double M, float plan)
   const double* m_max = nullptr;  // mixed: max |M| on the device (blocks of M read scaled)
   const RbfSource* rbf = nullptr;  // matrix-free M: its description on the device
+  unsigned long long* stats = nullptr;  // device accounting (bri_opts::d_stats), or null
+  const char* stats_base = nullptr;     // the caller's workspace and its size
+  uint64_t stats_limit = 0;
 };
 
 // How the kernels of a plan are launched.
@@ -228,8 +231,13 @@ struct ExecCfg {
   int32_t* range_flag = nullptr;  // FP16 split products: operand outside the FP16 range
   char* split = nullptr;          // split FP16 / BF16 products: scratch for operands split once
   size_t split_bytes = 0;
+  unsigned long long* stats = nullptr;  // device accounting of the executed steps, or null
+  const char* stats_base = nullptr;
+  uint64_t stats_limit = 0;
 };
-ExecCfg cfg_of(const Ctx& c) { return ExecCfg{c.pivoting, c.lu, c.lp, c.wide, nullptr, nullptr, 0}; }
+ExecCfg cfg_of(const Ctx& c) {
+  return ExecCfg{c.pivoting, c.lu, c.lp, c.wide, nullptr, nullptr, 0, c.stats, c.stats_base, c.stats_limit};
+}
 
 DView zero_view() {
   DView v;
@@ -596,6 +604,9 @@ int run_exec(const std::vector<ExecStep>& steps, int bmax, const ExecCfg& cfg, h
       }
     }
     if (e != hipSuccess) return BRI_ERR_HIP;
+    if (cfg.stats && launch_stats(s.kind, s.desc, s.count, sizeof(T), cfg.stats, cfg.stats_base, cfg.stats_limit,
+                                  st) != hipSuccess)
+      return BRI_ERR_HIP;
     if (prof) {
       std::lock_guard<std::mutex> g(g_prof_mu);
       if (hipEventRecord(rec.e1, st) != hipSuccess) return BRI_ERR_HIP;
@@ -631,6 +642,7 @@ std::mutex g_noalloc_mu;
 // kernels of plan cp on st.
 int enqueue_call(CachedPlan& cp, Ctx& c, bool clear_info, hipStream_t st) {
   if (clear_info && launch_fill_int(c.info, 1, 0, st) != hipSuccess) return BRI_ERR_HIP;
+  if (c.stats && launch_fill_int(reinterpret_cast<int32_t*>(c.stats), 8, 0, st) != hipSuccess) return BRI_ERR_HIP;
   if (cp.layout.desc_bytes > 0) {
     if (hipMemcpyAsync(c.ws + cp.layout.desc_off, cp.host, cp.layout.desc_bytes, hipMemcpyHostToDevice, st) !=
         hipSuccess)
@@ -720,6 +732,7 @@ int execute(CachedPlan& cp, Ctx& c, hipStream_t st, bool clear_info, bool noallo
       return BRI_ERR_UNSUPPORTED;
     }
     if (clear_info && launch_fill_int(c.info, 1, 0, st) != hipSuccess) return BRI_ERR_HIP;
+    if (c.stats && launch_fill_int(reinterpret_cast<int32_t*>(c.stats), 8, 0, st) != hipSuccess) return BRI_ERR_HIP;
     if (cp.layout.desc_bytes > 0 && hipMemcpyAsync(c.ws + cp.layout.desc_off, g_noalloc_desc, cp.layout.desc_bytes,
                                                    hipMemcpyHostToDevice, st) != hipSuccess)
       return BRI_ERR_HIP;
@@ -737,8 +750,9 @@ int execute(CachedPlan& cp, Ctx& c, hipStream_t st, bool clear_info, bool noallo
   } catch (const std::exception&) {
     return BRI_ERR_UNSUPPORTED;
   }
-  // The whole call as one graph launch when it repeats the captured one.
-  if (graph_eligible(cp)) {
+  // The whole call as one graph launch when it repeats the captured one
+  // (calls with device accounting launch directly).
+  if (graph_eligible(cp) && !c.stats) {
     const std::vector<char> key = graph_key(cp, c, clear_info);
     if (cp.graph && key == cp.graph_desc) {
       if (hipGraphLaunch(cp.graph, st) != hipSuccess) return BRI_ERR_HIP;
@@ -1318,13 +1332,16 @@ int run_mixed_batch(const MixedBatch& mb, int count, const void* const* M, const
   // as FP32), found at the first sweep's synchronisation.
   int32_t* range_flag = reinterpret_cast<int32_t*>(ws + mb.flag_off);
   ExecCfg mcfg{o->pivoting, o->factorization, lp_of(o->precision), true, range_flag,
-               mb.split_bytes ? ws + mb.split_off : nullptr, mb.split_bytes};
+               mb.split_bytes ? ws + mb.split_off : nullptr, mb.split_bytes,
+               count == 1 ? reinterpret_cast<unsigned long long*>(o->d_stats) : nullptr, ws, o->workspace_bytes};
   t_last_range_fallback = 0;
   std::vector<char> conv;
   std::vector<double> prev;
   std::vector<double> hs(static_cast<size_t>(count) * kRefineScalars);
   for (int pass = 0;; ++pass) {
   if (mcfg.lp == 1 && launch_fill_int(range_flag, 1, 0, st) != hipSuccess) return BRI_ERR_HIP;
+  if (mcfg.stats && launch_fill_int(reinterpret_cast<int32_t*>(mcfg.stats), 8, 0, st) != hipSuccess)
+    return BRI_ERR_HIP;
   // sigma from max |M|, then X0 = sigma (sigma Gamma)^{-1} E_j by the float
   // block-column plans (which keep their pivots for the correction solves).
   if (launch_scal_clear(d_items, count, 0, kRefineScalars, st) != hipSuccess) return BRI_ERR_HIP;
@@ -1453,6 +1470,8 @@ void bri_default_opts(bri_opts* o) {
 }
 
 const char* bri_version(void) { return "bri-mi355x 0.1"; }
+
+size_t bri_opts_size(void) { return sizeof(bri_opts); }
 
 const char* bri_status_string(int status) {
   if (status == BRI_OK) return "success";
@@ -1705,6 +1724,9 @@ static int invert_block_impl(const void* M, int64_t n, int64_t ldm, int k, int i
   c.out = static_cast<char*>(out);
   c.ldo = ldo;
   c.info = o->d_info ? o->d_info : reinterpret_cast<int32_t*>(c.ws + cp->layout.info_off);
+  c.stats = reinterpret_cast<unsigned long long*>(o->d_stats);
+  c.stats_base = static_cast<const char*>(o->workspace);
+  c.stats_limit = o->workspace_bytes;
   return execute(*cp, c, o->stream, true, noalloc);
 }
 

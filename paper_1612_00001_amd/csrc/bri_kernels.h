@@ -30,6 +30,10 @@ hipError_t launch_trtri(const LuItem* d_items, int count, int b, bool diag_inver
 template <typename T>
 hipError_t launch_load(const LoadItem* d_items, int count, int rows, int cols, hipStream_t st);
 hipError_t launch_fill_int(int32_t* p, int n, int v, hipStream_t st);
+// Device accounting of a plan step that has run (kind: a StepKind; elem:
+// element size of its matrices): see bri_opts::d_stats.
+hipError_t launch_stats(int kind, const void* items, int count, int elem, unsigned long long* stats,
+                        const void* base, uint64_t limit, hipStream_t st);
 // Diagonally dominant FP64 test matrices in the LU items (autotuner inputs).
 hipError_t launch_fill_diag_dominant(const LuItem* d_items, int count, int b, hipStream_t st);
 // Writes *src (passed by value as a kernel argument) to dst on the device.

@@ -3246,6 +3246,75 @@ hipError_t launch_store_rbf(RbfSource* dst, const RbfSource& src, hipStream_t st
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Device accounting of executed plan steps (optional, bri_opts::d_stats):
+// one thread per item of a step that has just run reads the item's
+// descriptor (the one its kernels ran on) and counts it, and records the end
+// of the workspace bytes it wrote (highest offset below the workspace size).
+// stats[0] pivot factorisations, stats[1] Schur products D - C X (plain and
+// accumulated), stats[2] other products (triangular multiplies, final
+// products), stats[3] workspace high-water mark in bytes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void stats_note_end(unsigned long long* stats, const char* base, uint64_t limit,
+                                               const void* p, uint64_t bytes) {
+  const char* q = static_cast<const char*>(p);
+  if (q < base) return;
+  const uint64_t end = static_cast<uint64_t>(q - base) + bytes;
+  if (end <= limit) atomicMax(stats + 3, static_cast<unsigned long long>(end));
+}
+
+__global__ void k_stats_lu(const LuItem* items, int count, int elem, int factorisation, unsigned long long* stats,
+                           const char* base, uint64_t limit) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const LuItem it = items[t];
+  const uint64_t bytes = static_cast<uint64_t>(it.b) * it.b * elem;
+  if (factorisation) atomicAdd(stats + 0, 1ull);
+  stats_note_end(stats, base, limit, it.a, bytes);
+  if (it.tmp) stats_note_end(stats, base, limit, it.tmp, bytes);
+}
+
+__global__ void k_stats_gemm(const GemmItem* items, int count, int which, int elem, unsigned long long* stats,
+                             const char* base, uint64_t limit) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const GemmItem it = items[t];
+  atomicAdd(stats + which, 1ull);
+  if (it.M > 0 && it.N > 0)
+    stats_note_end(stats, base, limit, it.out,
+                   (static_cast<uint64_t>(it.M - 1) * it.ldo + it.N) * static_cast<uint64_t>(elem));
+}
+
+__global__ void k_stats_load(const LoadItem* items, int count, int elem, unsigned long long* stats, const char* base,
+                             uint64_t limit) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const LoadItem it = items[t];
+  if (it.rows > 0 && it.cols > 0)
+    stats_note_end(stats, base, limit, it.dst,
+                   (static_cast<uint64_t>(it.rows - 1) * it.ldd + it.cols) * static_cast<uint64_t>(elem));
+}
+
+hipError_t launch_stats(int kind, const void* items, int count, int elem, unsigned long long* stats,
+                        const void* base, uint64_t limit, hipStream_t st) {
+  if (count <= 0 || !stats) return hipSuccess;
+  const dim3 grid(cdiv(count, 256)), block(256);
+  const char* b = static_cast<const char*>(base);
+  if (kind == ST_LOAD) {
+    hipLaunchKernelGGL(k_stats_load, grid, block, 0, st, static_cast<const LoadItem*>(items), count, elem, stats, b,
+                       limit);
+  } else if (kind == ST_GETRF || kind == ST_TRTRI) {
+    // the triangular inversion writes the LU block and its scratch block
+    hipLaunchKernelGGL(k_stats_lu, grid, block, 0, st, static_cast<const LuItem*>(items), count, elem,
+                       kind == ST_GETRF ? 1 : 0, stats, b, limit);
+  } else {
+    const int which = (kind == ST_GEMM || kind == ST_GEMM_ACC) ? 1 : 2;
+    hipLaunchKernelGGL(k_stats_gemm, grid, block, 0, st, static_cast<const GemmItem*>(items), count, which, elem,
+                       stats, b, limit);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_int(int32_t* p, int n, int v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();

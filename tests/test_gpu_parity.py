@@ -534,3 +534,70 @@ def test_batched_calls_repeated_with_the_same_blocks():
     torch.cuda.synchronize()
     for t in range(5):
         assert rel(other[t].cpu().numpy(), oracle.invert_block(mats[t], ks[t], iis[t], jjs[t])) < 1e-12
+
+
+def _planned_counts(steps):
+    # (factorisations, Schur products, other products) of a host step list
+    # (kinds: 2 getrf, 6 Schur product, 7 accumulated Schur product, 4 / 5
+    # triangular multiplies, 8 final product).
+    fact = sum(len(it) for kd, it in steps if kd == 2)
+    schur = sum(len(it) for kd, it in steps if kd in (6, 7))
+    other = sum(len(it) for kd, it in steps if kd in (4, 5, 8))
+    return fact, schur, other
+
+
+@pytest.mark.parametrize("precision,reuse", [("f64", False), ("f32", False), ("f64", True)])
+def test_device_stats_count_the_executed_work(precision, reuse):
+    # Device accounting (bri_opts.d_stats): the kernels' descriptors of the
+    # executed steps counted on the device equal the host plan (which the
+    # CPU tests pin to Theorem "C_BRI": T(k) Schur operations plus the final
+    # inversion without reuse), and the highest workspace byte written lies
+    # in the plan's last slot (the workspace bound of Theorem "MC_BRI" is
+    # reached and not exceeded).
+    n, k = 1280, 5
+    b = bri.block_size(n, k)
+    m = workloads.gaussian_dd(n, 4242)
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    elem = 8 if precision == "f64" else 4
+    slot = (b * b * elem + 255) // 256 * 256
+    for i, j in [(0, 0), (1, 3)]:
+        stats = torch.full((4,), -7, dtype=torch.int64, device=DEV)
+        info = torch.zeros(1, dtype=torch.int32, device=DEV)
+        out = bri.invert_block(gpu(m, dtype), k, i, j, precision=precision, info=info, pivoting="tile",
+                               reuse=reuse, stats=stats)
+        d = bri.stats_dict(stats)
+        desc = bri.plan_describe(n, k, i, j, precision, reuse=reuse)
+        fact, schur, other = _planned_counts(bri.plan_dump(n, k, i, j, precision, reuse=reuse))
+        print(f"stats {precision} reuse={reuse} ({i},{j}): {d}, planned {fact}/{schur}/{other}, "
+              f"slots {desc['slots']} x {slot} B", flush=True)
+        assert int(info.item()) == 0
+        assert (d["factorizations"], d["schur_products"], d["other_products"]) == (fact, schur, other)
+        if not reuse:
+            t = (4 ** (k - 1) - 1) // 3
+            assert d["factorizations"] == t + desc["final_inversions"] and d["schur_products"] == t
+        assert (desc["slots"] - 1) * slot < d["workspace_high_water"] <= desc["slots"] * slot
+        assert d["workspace_high_water"] <= bri.workspace_size(n, k, i, j, precision, reuse=reuse)
+        want = oracle.invert_block(m, k, i, j)
+        tol = 1e-12 if precision == "f64" else 64 * EPS32 * 4.0
+        assert rel(out.double().cpu().numpy(), want) < tol
+
+
+def test_device_stats_mixed_f16():
+    # The mixed path counts its float block-column plan and one correction
+    # solve per sweep (the FP64 residual products are not plan steps).
+    n, k = 1280, 5
+    m = workloads.gaussian_dd(n, 4243)
+    stats = torch.zeros(4, dtype=torch.int64, device=DEV)
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    out = bri.invert_block(gpu(m), k, 2, 1, precision="mixed_f16", info=info, stats=stats)
+    d = bri.stats_dict(stats)
+    sweeps = bri.refine_last()[0]
+    col = _planned_counts(bri.refine_plan_dump(n, k, 1, "column"))
+    sol = _planned_counts(bri.refine_plan_dump(n, k, 1, "solve"))
+    print(f"stats mixed_f16: {d}, column {col}, solve {sol}, sweeps {sweeps}", flush=True)
+    assert int(info.item()) == 0 and sweeps >= 1
+    assert d["factorizations"] == col[0] + sweeps * sol[0]
+    assert d["schur_products"] == col[1] + sweeps * sol[1]
+    assert d["other_products"] == col[2] + sweeps * sol[2]
+    assert 0 < d["workspace_high_water"] <= bri.workspace_size(n, k, 2, 1, "mixed_f16")
+    assert rel(out.cpu().numpy(), oracle.invert_block(m, k, 2, 1)) < 1e-10

@@ -98,6 +98,12 @@ def test_theorem_schur_counts_and_workspace_bound():
                 assert d["slots"] <= batch * (k + 1) + (4 * batch) // 3 * k + 2
 
 
+def test_binding_lays_out_bri_opts_like_the_library():
+    # The ctypes structure of the binding and the C struct agree in size (a
+    # field missing on either side changes it).
+    assert ctypes.sizeof(bri.BriOpts) == bri.lib().bri_opts_size()
+
+
 def test_auto_width_is_a_power_of_four():
     d = bri.plan_describe(4096, 4, 0, 0, "f64", 0)
     assert d["batch_width"] == 16

@@ -195,9 +195,10 @@ def main() -> int:
         out = torch.empty(b, b, dtype=M.dtype, device=dev)
         info = torch.zeros(1, dtype=torch.int32, device=dev)
 
-        def call():
+        def call(stats=None):
             bri.invert_block(M, k, i, j, precision=precision, out=out, info=info, workspace=ws, reuse=reuse,
-                             pivoting=PIV, workspace_budget=workspace_budget, factorization=factorization)
+                             pivoting=PIV, workspace_budget=workspace_budget, factorization=factorization,
+                             stats=stats)
         return call, out, info, ws
 
     # ---- headline: spd_n16384_k8, FP64, block (0, 0) -------------------------
@@ -265,12 +266,19 @@ def main() -> int:
 
     # One more call with HIP events around every plan step (per-kernel-family
     # times on the library's stream), then the result against the reference.
+    # The same call also fills the device accounting words (factorisations,
+    # Schur products and workspace high-water counted on the device).
     lib.bri_profile_enable(1)
     profile_read(lib)  # clear
-    prof_ms, _ = time_calls(call, 1, 0, torch)
+    dstats = torch.zeros(4, dtype=torch.int64, device=dev)
+    prof_ms, _ = time_calls(lambda: call(dstats), 1, 0, torch)
     prof = profile_read(lib)
     lib.bri_profile_enable(0)
     assert int(info.item()) == 0, "device status"
+    ds = bri.stats_dict(dstats)
+    ds["planned_schur_ops"] = stats["schur_ops"]
+    ds["planned_workspace_bytes"] = stats["workspace_bytes"]
+    line["device_stats"] = ds
     got = out.cpu().numpy()
     line["rel_error"] = rel_err(got, ref)
     line["rel_error_reference"] = "closed form Q[0:b] Lam^-1 Q[0:b]^T of the generated matrix (torch FP64)"

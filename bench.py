@@ -142,6 +142,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-budget", action="store_true")
+    ap.add_argument("--no-reuse", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the FP64 headline calls (no profiled pass, no reference, no other workloads)")
     ap.add_argument("--input", choices=("spd", "dd"), default="spd",
@@ -356,6 +357,24 @@ def main() -> int:
             "tflops": flops / (bms * 1e-3) / 1e12, "speed_vs_default": ms / bms,
             "rel_error": rel_err(ob.cpu().numpy(), ref), "info": int(ib.item())}
         del wsb, ob
+
+    # ---- reused pivots (the paper's reuse across branches) on the same matrix --
+    # Three children per Schur node instead of four: less work than F, so the
+    # rate is the executed one (the paper-equivalent rate F / time is given
+    # only for comparison with the recomputing call).
+    if not args.no_reuse:
+        print(f"reused pivots: FP64 n={n} k={k}", file=sys.stderr, flush=True)
+        cr, orr, ir, wsr = setup(M3, n, k, i, j, "f64", reuse=True)
+        rms, _ = time_calls(cr, 1, 1, torch)
+        str_ = bri.plan_describe(n, k, i, j, "f64", reuse=True)
+        line["reuse_pivots"] = {
+            "workload": "spd_n16384_k8, FP64, reused elimination pivots (3-way recursion)",
+            "ms_per_step": rms, "executed_flops": str_["executed_flops"],
+            "executed_tflops": str_["executed_flops"] / (rms * 1e-3) / 1e12,
+            "paper_equivalent_tflops": flops / (rms * 1e-3) / 1e12, "speed_vs_default": ms / rms,
+            "schur_ops": str_["schur_ops"], "workspace_over_M": str_["workspace_bytes"] / (8.0 * n * n),
+            "rel_error": rel_err(orr.cpu().numpy(), ref), "info": int(ir.item())}
+        del wsr, orr
 
     # ---- CPU baseline: the FP64 oracle on a sample of the same workload -------
     if not args.no_cpu_baseline:

@@ -306,9 +306,9 @@ def invert_block(M: torch.Tensor, k: int, i: int, j: int, precision: str = "f64"
     o.workspace_bytes = workspace.numel()
     o.d_info = info.data_ptr() if info is not None else None
     if stats is not None:
-        if not isinstance(stats, torch.Tensor) or stats.device.type != "cuda" or stats.dtype != torch.int64 \
+        if not isinstance(stats, torch.Tensor) or stats.device != M.device or stats.dtype != torch.int64 \
                 or stats.numel() < 4 or not stats.is_contiguous():
-            raise ValueError("stats must be a contiguous int64 GPU tensor of at least 4 elements")
+            raise ValueError("stats must be a contiguous int64 tensor of at least 4 elements on M's device")
         o.d_stats = stats.data_ptr()
     o.stream = _stream_ptr(M.device)
     _check(lib().invert_block(M.data_ptr(), n, M.stride(0), k, i, j, out.data_ptr(), out.stride(0),

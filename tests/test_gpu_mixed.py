@@ -229,6 +229,31 @@ def test_mixed_f16_out_of_range_falls_back_to_bf16():
         assert err < 1e-10
 
 
+def test_mixed_f16_range_fallback_on_split_once_products():
+    # The same fallback where the explicit products run on operands split
+    # once (n = 4096, k = 8: launches of 256 items of order 512): the FP16
+    # split pass flags the range, the BF16 pass reuses the split scratch with
+    # three planes.  D A D with A = Q Lam Q^T (cond 1e2) and the last 64 rows
+    # and columns scaled by 1e-4; reference D^-1 (Q Lam^-1 Q^T) D^-1.
+    n, k = 4096, 8
+    b = n // k
+    w = workloads.haar_spd(n, 71, 0.0, 2.0)
+    d = np.ones(n)
+    d[-64:] = 1e-4
+    m = d[:, None] * w.m * d[None, :]
+    for (i, j) in [(7, 7), (0, 7)]:
+        qi, qj = w.q[i * b:(i + 1) * b], w.q[j * b:(j + 1) * b]
+        want = ((qi / w.lam[None, :]) @ qj.T) / d[i * b:(i + 1) * b, None] / d[None, j * b:(j + 1) * b]
+        got, info = run_mixed(m, k, i, j, "mixed_f16", iters=30)
+        err = rel(got, want)
+        fell_back = bri.refine_last_bf16_fallback()
+        print(f"mixed_f16 n=4096 k=8 scaled ({i},{j}): rel err {err:.2e}, info {info}, bf16 fallback {fell_back}",
+              flush=True)
+        assert fell_back
+        assert info == 0
+        assert err < 1e-10
+
+
 @pytest.mark.parametrize("precision", ["mixed_f16", "mixed_bf16"])
 def test_mixed_recursive_lu_with_split_products(precision):
     # The recursive LU of the float recursion forced on b = 512 pivot blocks:
